@@ -1,0 +1,245 @@
+"""Seeded synthetic workloads for the differentiable 3D PIC space-charge step.
+
+This module only *describes* inputs: beam, lattice, grid box, parameter
+vector and the standard-normal draws that seed the initial particle cloud.
+It holds none of the method's arithmetic (no maps, deposition, field solve
+or moments), so both the CPU oracle and the HIP library can be fed from it
+without sharing any computation.
+
+Input recipe (the paper's FODO example, extended to 3D, see the method
+description in Sec. 4 and the lattice description in Sec. 3):
+
+* protons at 1 GeV kinetic energy;
+* an uncorrelated 6D Gaussian in (x, px/p0, y, py/p0, z, delta) with
+  sigma = (1 mm, 1e-3, 1 mm, 1e-3, 2 mm, 1e-3); every draw is a standard
+  normal truncated at |xi| <= 4 by resampling (numpy PCG64, seeded);
+* one FODO cell drift-QF-drift-QD-drift with hard-edge quadrupoles of
+  normalised strength +-22 m^-2 (the value the paper prints); the element
+  lengths (0.1, 0.1, 0.2, 0.1, 0.1 m) are not printed in the paper and are
+  this build's choice;
+* 7 parameters in the paper's order: D1 L, Q1 L, Q1 k, D2 L, Q2 L, Q2 k,
+  D3 L;
+* the bunch charge follows from a peak current of a Gaussian bunch,
+  Q = I * sqrt(2 pi) * sigma_z / (beta0 c).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+__all__ = [
+    "truncated_normals",
+    "Lattice",
+    "Workload",
+    "fodo_lattice",
+    "bunch_charge_from_peak_current",
+    "peak_current_for_tune_depression",
+    "NOMINAL_PARAMS",
+    "PARAM_NAMES",
+    "c1",
+    "c2",
+    "tiny",
+]
+
+# Recipe constants (CODATA 2018); used only to turn a peak current into a
+# bunch charge for the workload description.
+_E = 1.602176634e-19
+_C = 299792458.0
+_EPS0 = 8.8541878128e-12
+PROTON_REST_EV = 938.27208816e6
+
+PARAM_NAMES = ("D1 L", "Q1 L", "Q1 k", "D2 L", "Q2 L", "Q2 k", "D3 L")
+NOMINAL_PARAMS = (0.1, 0.1, 22.0, 0.2, 0.1, -22.0, 0.1)
+SIGMA_NOMINAL = (1e-3, 1e-3, 1e-3, 1e-3, 2e-3, 1e-3)
+
+DRIFT = 0
+QUAD = 1
+
+
+def truncated_normals(n: int, seed: int, cut: float = 4.0, ncoord: int = 6) -> np.ndarray:
+    """Standard normals of shape (n, ncoord), every entry with |xi| <= cut.
+
+    Entries outside the cut are redrawn from the same PCG64 stream until none
+    remain, so the array is a deterministic function of (n, seed, cut).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xi = rng.standard_normal((n, ncoord))
+    bad = np.abs(xi) > cut
+    while bad.any():
+        xi[bad] = rng.standard_normal(int(bad.sum()))
+        bad = np.abs(xi) > cut
+    return np.ascontiguousarray(xi, dtype=np.float64)
+
+
+@dataclasses.dataclass
+class Lattice:
+    """Element list of one period; the period is repeated n_periods times.
+
+    kind: 0 drift, 1 quadrupole. L and k are the fixed values used when the
+    element's length / strength is not bound to a parameter (L_param or
+    k_param = -1). Bound parameters are shared by every period.
+    """
+
+    kind: List[int]
+    n_steps: List[int]
+    L: List[float]
+    k: List[float]
+    L_param: List[int]
+    k_param: List[int]
+    n_periods: int = 1
+
+    @property
+    def n_elem(self) -> int:
+        return len(self.kind)
+
+    def total_steps(self) -> int:
+        return int(sum(self.n_steps)) * int(self.n_periods)
+
+
+def fodo_lattice(steps_per_element: int, n_periods: int,
+                 params: Sequence[float] = NOMINAL_PARAMS) -> Lattice:
+    """drift-QF-drift-QD-drift, every length and strength bound to a parameter."""
+    p = list(params)
+    return Lattice(
+        kind=[DRIFT, QUAD, DRIFT, QUAD, DRIFT],
+        n_steps=[steps_per_element] * 5,
+        L=[p[0], p[1], p[3], p[4], p[6]],
+        k=[0.0, p[2], 0.0, p[5], 0.0],
+        L_param=[0, 1, 3, 4, 6],
+        k_param=[-1, 2, -1, 5, -1],
+        n_periods=n_periods,
+    )
+
+
+def _beta_gamma(kinetic_eV: float, rest_eV: float) -> Tuple[float, float]:
+    g = 1.0 + kinetic_eV / rest_eV
+    return math.sqrt(1.0 - 1.0 / (g * g)), g
+
+
+def bunch_charge_from_peak_current(I_peak: float, sigma_z: float,
+                                   kinetic_eV: float = 1e9,
+                                   rest_eV: float = PROTON_REST_EV) -> float:
+    """Charge of a Gaussian bunch with peak current I_peak and rms length sigma_z."""
+    b, _ = _beta_gamma(kinetic_eV, rest_eV)
+    return I_peak * math.sqrt(2.0 * math.pi) * sigma_z / (b * _C)
+
+
+def peak_current_for_tune_depression(eta: float, sigma: float, emit: float,
+                                     kinetic_eV: float = 1e9,
+                                     rest_eV: float = PROTON_REST_EV) -> float:
+    """Peak current giving tune ratio eta = nu/nu0 in the smooth-focusing rms
+    envelope relation eta^2 = 1 / (1 + K sigma^2 / (4 emit^2)), with the
+    generalised perveance K = 2 I / (I0 (beta gamma)^3), I0 = 4 pi eps0 m c^3 / e.
+    """
+    b, g = _beta_gamma(kinetic_eV, rest_eV)
+    K = (1.0 / (eta * eta) - 1.0) * 4.0 * emit * emit / (sigma * sigma)
+    I0 = 4.0 * math.pi * _EPS0 * (rest_eV * _E) * _C / _E  # m c^3 / e with m c^2 in J
+    return 0.5 * K * I0 * (b * g) ** 3
+
+
+@dataclasses.dataclass
+class Workload:
+    """Everything needed to run one differentiable PIC simulation."""
+
+    name: str
+    n_particles: int
+    seed: int
+    grid: Tuple[int, int, int]
+    lo: Tuple[float, float, float]
+    hi: Tuple[float, float, float]
+    lattice: Lattice
+    params: Tuple[float, ...] = NOMINAL_PARAMS
+    sigma: Tuple[float, ...] = SIGMA_NOMINAL
+    ntan: int = 7
+    sigma_tangents: bool = False  # tangents 7..12 are d/d sigma_j (13-tangent mode)
+    kinetic_eV: float = 1e9
+    rest_eV: float = PROTON_REST_EV
+    charge_e: float = 1.0
+    bunch_charge_C: float = 0.0
+
+    # -- derived inputs (no method arithmetic) ---------------------------
+    def xi(self) -> np.ndarray:
+        return truncated_normals(self.n_particles, self.seed)
+
+    def param_seed(self) -> np.ndarray:
+        """[n_params][ntan]: parameter j carries tangent j (identity seeding)."""
+        s = np.zeros((len(self.params), self.ntan))
+        for j in range(min(len(self.params), self.ntan)):
+            s[j, j] = 1.0
+        return s
+
+    def sigma_seed(self) -> Optional[np.ndarray]:
+        """[6][ntan]: sigma_j carries tangent 7+j in 13-tangent mode, else None."""
+        if not self.sigma_tangents:
+            return None
+        s = np.zeros((6, self.ntan))
+        for j in range(6):
+            s[j, len(self.params) + j] = 1.0
+        return s
+
+    def total_steps(self) -> int:
+        return self.lattice.total_steps()
+
+    def with_(self, **kw) -> "Workload":
+        return dataclasses.replace(self, **kw)
+
+
+# Boxes are fixed per run and symmetric about the origin. They were chosen
+# to contain every particle at every step of the nominal run (checked by the
+# out-of-box counters, which the tests require to stay at zero) with margin
+# for the +-5% parameter perturbations used elsewhere.
+C1_HALF = (4.6e-3, 8.0e-3, 9.2e-3)
+C2_HALF = (14.0e-3, 14.0e-3, 12.0e-3)
+
+
+def c1(ntan: int = 7, **kw) -> Workload:
+    """1e4 protons, 32^3 grid (64^3 doubled), one FODO cell, 100 steps, 100 A peak."""
+    w = Workload(
+        name="c1: 1e4 protons, 32^3 grid, 1 FODO cell, 100 steps, 100 A",
+        n_particles=10_000,
+        seed=20251121,
+        grid=(32, 32, 32),
+        lo=tuple(-h for h in C1_HALF),
+        hi=C1_HALF,
+        lattice=fodo_lattice(20, 1),
+        ntan=ntan,
+        bunch_charge_C=bunch_charge_from_peak_current(100.0, SIGMA_NOMINAL[4]),
+    )
+    return w.with_(**kw) if kw else w
+
+
+def c2(**kw) -> Workload:
+    """1e6 protons, 64^3 grid (128^3 doubled), 10 FODO cells, 2000 steps, tune ratio 0.3."""
+    I = peak_current_for_tune_depression(0.3, 1e-3, 1e-6)
+    w = Workload(
+        name="c2: 1e6 protons, 64^3 grid, 10 FODO cells, 2000 steps, eta=0.3",
+        n_particles=1_000_000,
+        seed=20251122,
+        grid=(64, 64, 64),
+        lo=tuple(-h for h in C2_HALF),
+        hi=C2_HALF,
+        lattice=fodo_lattice(40, 10),
+        ntan=7,
+        bunch_charge_C=bunch_charge_from_peak_current(I, SIGMA_NOMINAL[4]),
+    )
+    return w.with_(**kw) if kw else w
+
+
+def tiny(n_particles: int = 3001, grid: int = 16, steps_per_element: int = 4,
+         ntan: int = 7, seed: int = 7, **kw) -> Workload:
+    """Small case for fast parity: ragged particle count, coarse grid."""
+    w = Workload(
+        name=f"tiny: {n_particles} protons, {grid}^3 grid, {5 * steps_per_element} steps",
+        n_particles=n_particles,
+        seed=seed,
+        grid=(grid, grid, grid),
+        lo=tuple(-h for h in C1_HALF),
+        hi=C1_HALF,
+        lattice=fodo_lattice(steps_per_element, 1),
+        ntan=ntan,
+        bunch_charge_C=bunch_charge_from_peak_current(100.0, SIGMA_NOMINAL[4]),
+    )
+    return w.with_(**kw) if kw else w
