@@ -1,0 +1,158 @@
+#!/usr/bin/env python3
+"""Throughput of the forward-mode differentiable 3D PIC space-charge step.
+
+Workload (one GPU): 1e6 protons at 1 GeV, 6D Gaussian beam, 64^3 CIC grid
+with the open-boundary Hockney solve on the 128^3 doubled grid, 10 FODO
+cells of 5 elements x 40 steps (2000 steps), 7 tangents (3 drift lengths,
+2 quadrupole lengths, 2 quadrupole strengths), FP64, beam current set for a
+tune ratio of 0.3. A bench "step" is one full PIC step (push, deposit, solve,
+field, gather, kick) over all particles; the timed region is K steps from the
+start of the lattice schedule with the beam already resident on the GPU.
+
+Prints one JSON line: value = particles * steps / seconds, the roofline of
+the dominant kernel (the fused particle kernel, 768 algorithmic bytes per
+particle per step: read and write 6 coordinates x 8 channels x 8 B), timed
+with HIP events on the library's stream, and the CPU oracle timed on a short
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_PARTICLE_STEP = 6 * 8 * 8 * 2  # 6 coords x 8 channels x 8 B, read + write
+
+
+def _cpu_baseline(w, xi, steps: int):
+    """The oracle on a bounded sample: the first `steps` steps of the same workload."""
+    from oracle import pic
+
+    t0 = time.perf_counter()
+    pic.simulate_workload(w, nsteps=steps, xi=xi)
+    dt = time.perf_counter() - t0
+    return {
+        "value": w.n_particles * steps / dt,
+        "unit": "dual particle-steps/s",
+        "cores": int(pic.FFT_WORKERS),
+        "kind": "oracle",
+        "sample": (f"first {steps} of {w.total_steps()} steps of the same workload "
+                   f"({w.n_particles} particles, 7 tangents), {dt:.1f} s; numpy FP64, "
+                   f"elementwise work on 1 thread, FFT convolution on {pic.FFT_WORKERS} threads"),
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--sort-every", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the design notes describe how the step would shard)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2511_21839_amd import dpic
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    w = synth.c2()
+    K, W = int(args.steps), int(args.warmup)
+    if K < 1 or K > w.total_steps() or W < 0 or W > w.total_steps():
+        print(f"--steps must be 1..{w.total_steps()} and --warmup 0..{w.total_steps()}", file=sys.stderr)
+        return 2
+    xi = w.xi()
+    sim = dpic.Simulation(w.n_particles, w.ntan, w.grid)
+    sim.set_beam(w.kinetic_eV, w.rest_eV, w.charge_e, w.bunch_charge_C)
+    sim.set_grid(w.lo, w.hi)
+    L = w.lattice
+    sim.set_lattice(L.kind, L.n_steps, L.L, L.k, L.L_param, L.k_param, L.n_periods)
+    sim.set_params(w.params, w.param_seed())
+    sim.set_option(dpic.OPT_SORT_EVERY, args.sort_every)
+
+    # warm-up on a first copy of the beam
+    sim.init_beam(xi, w.sigma, w.sigma_seed())
+    if W:
+        sim.step(W)
+    torch.cuda.synchronize()
+
+    # timed: K steps from the start of the schedule, beam resident in HBM
+    sim.init_beam(xi, w.sigma, w.sigma_seed())
+    sim.set_option(dpic.OPT_STAGE_TIMING, 1)
+    sim.stage_times()  # reset the stage timers
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(K)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms, launches = sim.stage_times()
+    sim.set_option(dpic.OPT_STAGE_TIMING, 0)
+    dt = t1 - t0
+    oob, steps_done, extent = sim.counters()
+    emit = sim.emittance()
+
+    part_avg_s = ms[0] / 1e3 / max(int(launches[0]), 1)
+    achieved = w.n_particles * BYTES_PER_PARTICLE_STEP / part_avg_s / 1e9
+    line = {
+        "metric": "dual particle-steps/s (7 tangents)",
+        "value": w.n_particles * K / dt,
+        "unit": "dual particle-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": dt / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name,
+            "n_particles": w.n_particles,
+            "grid": list(w.grid),
+            "fft_grid": [2 * g for g in w.grid],
+            "ntan": w.ntan,
+            "schedule_steps": w.total_steps(),
+            "bunch_charge_C": w.bunch_charge_C,
+            "sort_every": args.sort_every,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "k_particles (gather, kick, two half-maps, deposit)",
+            "avg_launch_us": part_avg_s * 1e6,
+        },
+        "stages_ms": {n: float(ms[i]) for i, n in enumerate(dpic.STAGE_TIMER_NAMES)},
+        "stage_launches": {n: int(launches[i]) for i, n in enumerate(dpic.STAGE_TIMER_NAMES)},
+        "checks": {"out_of_box": int(oob), "steps_done": int(steps_done),
+                   "emittance_x": float(emit[0, 0]), "emittance_y": float(emit[1, 0]),
+                   "finite": bool(np.isfinite(emit).all())},
+    }
+    if not args.no_cpu_baseline and args.cpu_steps > 0:
+        line["cpu_baseline"] = _cpu_baseline(w, xi, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

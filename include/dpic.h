@@ -1,0 +1,212 @@
+/*
+ * dpic.h -- C ABI of the forward-mode differentiable 3D particle-in-cell
+ * space-charge step on one AMD MI355X (gfx950).
+ *
+ * The method (arXiv 2511.21839, Sec. 4): macroparticles are advanced by the
+ * second-order split-operator map M1(tau/2) M2(tau) M1(tau/2), where M1 is the
+ * exact external map of a drift or hard-edge quadrupole and M2 the
+ * space-charge kick computed from a grid potential. Every particle coordinate,
+ * grid charge, potential and field value is a first-order dual number
+ * F = (f, f_x1, ..., f_xn) (Sec. 2), so one run yields the result and its
+ * derivatives with respect to n parameters (lattice lengths and strengths,
+ * initial beam sizes).
+ *
+ * Conventions
+ *  - Every function returns an int: DPIC_OK (0) or a negative DPIC_E* code.
+ *    No function throws or aborts across the ABI. dpic_last_error() gives a
+ *    message for the last failing call on a context.
+ *  - Pointers named *_dev are device pointers; all others are host pointers,
+ *    read or written only during the call.
+ *  - The caller owns all device memory: one workspace buffer, sized by
+ *    dpic_query_workspace(), bound at dpic_create() and never freed by the
+ *    library. The library allocates no device memory.
+ *  - All GPU work is enqueued on the stream bound at dpic_create() (a
+ *    hipStream_t passed as void*; NULL means the default stream). Calls that
+ *    return data to the host synchronise that stream; the others are
+ *    asynchronous.
+ *  - A context is not thread-safe; use one context per stream.
+ *  - Dual numbers are stored with a channel stride NC = 1 (ntan = 0),
+ *    8 (ntan <= 7) or 16 (ntan <= 15); channel 0 is the value, channel
+ *    1 + t the derivative with respect to tangent t, the rest zero.
+ *  - Units: SI (m, V, C); momenta are normalised, px/p0, py/p0 and
+ *    delta = (p - p0)/p0; z is the lab-frame distance from the bunch centre.
+ */
+#ifndef DPIC_H
+#define DPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DPIC_OK 0
+#define DPIC_EINVAL (-1)       /* bad argument or size */
+#define DPIC_ESTATE (-2)       /* call out of order (e.g. step before init) */
+#define DPIC_EHIP (-3)         /* a HIP runtime call failed */
+#define DPIC_ENONFINITE (-4)   /* a non-finite value was found */
+#define DPIC_EUNSUPPORTED (-5) /* ntan > 15 or a grid size other than 8/16/32/64 */
+
+#define DPIC_MAX_ELEMENTS 64
+#define DPIC_MAX_PARAMS 64
+
+typedef struct dpic_ctx dpic_ctx;
+
+/* Problem dimensions, fixed for the lifetime of a context. */
+typedef struct dpic_dims {
+    int64_t n_particles; /* capacity: maximum number of macroparticles      */
+    int32_t ntan;        /* number of tangents (derivative channels), 0..15  */
+    int32_t nx, ny, nz;  /* grid nodes per dimension, each in {8,16,32,64}   */
+    int32_t flags;       /* reserved, must be 0                              */
+} dpic_dims;
+
+/* Library version as major*10000 + minor*100 + patch. */
+int dpic_version(void);
+
+/* Bytes of device workspace a context with these dimensions needs. */
+int dpic_query_workspace(const dpic_dims* dims, size_t* bytes);
+
+/*
+ * Bind caller-owned device memory (at least the queried size, 256-byte
+ * aligned) and a HIP stream to a new context. The context owns host metadata
+ * only; dpic_destroy() frees that and never the workspace.
+ */
+int dpic_create(const dpic_dims* dims, void* workspace_dev, size_t workspace_bytes,
+                void* hip_stream, dpic_ctx** out);
+int dpic_destroy(dpic_ctx* ctx);
+
+/* Copy the message of the last failing call (NUL-terminated, truncated). */
+int dpic_last_error(const dpic_ctx* ctx, char* buf, size_t len);
+
+/*
+ * Reference particle and bunch: kinetic and rest energy in eV, particle
+ * charge in units of e, total bunch charge in C (0 switches space charge
+ * off). gamma0 = 1 + T / mc^2. The space-charge kick (Sec. 4, map M2) is read
+ * in 3D as Delta(px/p0) = tau q E_x / (m c^2 beta0^2 gamma0^2) (same for y)
+ * and Delta(delta) = tau q E_z / (m c^2 beta0^2 gamma0), E the rest-frame
+ * field; for a long beam this is the paper's perveance kick.
+ */
+int dpic_set_beam(dpic_ctx* ctx, double kinetic_eV, double rest_eV, double charge_e,
+                  double bunch_charge_C);
+
+/*
+ * Fixed grid box [lo, hi] per dimension (never differentiated). Nodes sit at
+ * lo + i h, h = (hi - lo) / (n - 1). A particle is inside iff
+ * 0 <= (u - lo)/h < n - 1 in every dimension; outside particles deposit
+ * nothing, feel no kick and are counted. Builds the transform of the
+ * open-boundary Green's function on the doubled grid; needs dpic_set_beam()
+ * first (the rest-frame kernel depends on gamma0).
+ */
+int dpic_set_grid(dpic_ctx* ctx, const double lo[3], const double hi[3]);
+
+/*
+ * One lattice period of n_elem elements, repeated n_periods times.
+ * kind[e]: 0 drift, 1 hard-edge quadrupole (Sec. 4 maps; k > 0 focuses x).
+ * n_steps[e]: integration steps per element (tau = L / n_steps, Sec. 4).
+ * L[e], k[e]: values used when L_param[e] / k_param[e] is -1; otherwise the
+ * element takes parameter L_param[e] / k_param[e] of dpic_set_params(),
+ * shared by every period.
+ */
+int dpic_set_lattice(dpic_ctx* ctx, int n_elem, const int* kind, const int* n_steps,
+                     const double* L, const double* k, const int* L_param,
+                     const int* k_param, int n_periods);
+
+/*
+ * Parameter values p[np] and their derivative seeds seed[np][ntan] (row j is
+ * the derivative of p[j] with respect to each tangent, Sec. 2 seeding
+ * X_i = (x_i, 0, .., 1, .., 0)); seed == NULL means identity (p[j] carries
+ * tangent j for j < ntan). Recomputes the per-element dual step sizes and
+ * half-step maps on the device.
+ */
+int dpic_set_params(dpic_ctx* ctx, int np, const double* p, const double* seed);
+
+/*
+ * Initial beam zeta_j = sigma_j xi_j for n <= capacity particles.
+ * xi_dev: device array [n][6] of standard normals (caller draws them).
+ * sigma[6]: rms sizes of x, px/p0, y, py/p0, z, delta.
+ * sigma_seed[6][ntan] or NULL: derivative of sigma_j per tangent, so the
+ * initial tangents are sigma_seed[j][t] * xi_j.
+ * Resets the step counter and the diagnostic counters.
+ */
+int dpic_init_beam(dpic_ctx* ctx, int64_t n, const double* xi_dev, const double sigma[6],
+                   const double* sigma_seed);
+
+/*
+ * Advance n steps along the lattice schedule (asynchronous). Each step is
+ * M1(tau/2), deposit, solve, field, gather + kick, M1(tau/2). Fails with
+ * DPIC_EINVAL past the end of the schedule.
+ */
+int dpic_step(dpic_ctx* ctx, int n);
+
+/*
+ * Raw dual moments over all particles, host out[3][5][1+ntan]: planes
+ * (x,px), (y,py), (z,delta); moments <u^2>, <u p>, <p^2>, <u>, <p> with 1/N
+ * sums (Sec. 4). Synchronises the stream.
+ */
+int dpic_read_moments(dpic_ctx* ctx, double* out);
+
+/*
+ * Emittances as duals, host out[3][1+ntan]: eps = sqrt(<u^2><p^2> - <u p>^2)
+ * with raw moments (Sec. 4) when centred == 0, central moments otherwise.
+ * Synchronises the stream.
+ */
+int dpic_read_emittance(dpic_ctx* ctx, int centred, double* out);
+
+/*
+ * Particle state in the original particle order, host out[n][6][1+ntan].
+ * Synchronises the stream.
+ */
+int dpic_read_particles(dpic_ctx* ctx, double* out);
+
+/*
+ * Diagnostics, host: particle-steps found outside the box, steps done, and
+ * max |x|, |y|, |z| seen at deposit time (extent may be NULL).
+ * Synchronises the stream.
+ */
+int dpic_counters(dpic_ctx* ctx, int64_t* out_of_box, int64_t* steps_done, double* extent);
+
+/* Stage-level access for parity checks and diagnostics ------------------ */
+#define DPIC_GRID_RHO 0 /* node charges  [nz][ny][nx][1+ntan]            */
+#define DPIC_GRID_PHI 1 /* potential     [nz+2][ny+2][nx+2][1+ntan], node i at i+1 */
+#define DPIC_GRID_E 2   /* rest-frame E  [nz][ny][nx][3][1+ntan]         */
+
+#define DPIC_STAGE_DEPOSIT 0 /* clear rho, deposit the current particles    */
+#define DPIC_STAGE_SOLVE 1   /* rho -> phi (consumes rho: it is left zeroed) */
+#define DPIC_STAGE_FIELD 2   /* phi -> E                                    */
+
+/* Run one stage on the current state (asynchronous). */
+int dpic_stage(dpic_ctx* ctx, int stage);
+/* Copy a grid array to / from host memory in the layouts above (synchronous). */
+int dpic_read_grid(dpic_ctx* ctx, int which, double* out);
+int dpic_write_grid(dpic_ctx* ctx, int which, const double* in);
+
+/*
+ * Checkpoint: bytes needed, then copy the particle state, particle order and
+ * step counter to / from caller device memory (asynchronous).
+ */
+int dpic_state_bytes(const dpic_ctx* ctx, size_t* bytes);
+int dpic_save_state(dpic_ctx* ctx, void* dev_buf);
+int dpic_load_state(dpic_ctx* ctx, const void* dev_buf);
+
+/*
+ * Options: DPIC_OPT_SORT_EVERY = re-sort particles by grid tile every k steps
+ * (0 = never); DPIC_OPT_STAGE_TIMING = 1 records HIP events around every
+ * stage launch of dpic_step (read with dpic_stage_times).
+ */
+#define DPIC_OPT_SORT_EVERY 1
+#define DPIC_OPT_STAGE_TIMING 2
+int dpic_set_option(dpic_ctx* ctx, int option, int64_t value);
+
+/*
+ * Accumulated stage times since the last call, host ms[DPIC_N_STAGE_TIMERS]
+ * and launch counts; synchronises. Order: particle push/deposit, solve,
+ * field, sort.
+ */
+#define DPIC_N_STAGE_TIMERS 4
+int dpic_stage_times(dpic_ctx* ctx, double* ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DPIC_H */

@@ -1,0 +1,88 @@
+// Shared device/host definitions of the dpic HIP library (gfx950).
+//
+// Dual numbers on the GPU (Sec. 2 algebra) use a lane-per-channel layout:
+// a particle (or grid node) owns a group of NC consecutive lanes, lane c
+// holding channel c of every dual quantity. Every lane also carries the value
+// so that all arithmetic is lane-local: a product F G is (f g, g f_c + f g_c)
+// in lane c without any cross-lane traffic. Lane 0's derivative slot is kept
+// at zero, so the rules never need a per-lane branch; the value is written
+// from lane 0 on store.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dpic {
+
+// ---------------------------------------------------------------- dual lane
+struct LD {
+    double v;  // value (uniform across the lane group)
+    double t;  // this lane's derivative channel (0 in lane 0)
+};
+
+__device__ __forceinline__ LD ldc(double v) { return LD{v, 0.0}; }
+__device__ __forceinline__ LD operator+(LD a, LD b) { return LD{a.v + b.v, a.t + b.t}; }
+__device__ __forceinline__ LD operator-(LD a, LD b) { return LD{a.v - b.v, a.t - b.t}; }
+__device__ __forceinline__ LD operator-(LD a) { return LD{-a.v, -a.t}; }
+__device__ __forceinline__ LD operator+(LD a, double s) { return LD{a.v + s, a.t}; }
+__device__ __forceinline__ LD operator+(double s, LD a) { return LD{a.v + s, a.t}; }
+__device__ __forceinline__ LD operator-(double s, LD a) { return LD{s - a.v, -a.t}; }
+__device__ __forceinline__ LD operator-(LD a, double s) { return LD{a.v - s, a.t}; }
+// product rule
+__device__ __forceinline__ LD operator*(LD a, LD b) { return LD{a.v * b.v, fma(a.v, b.t, a.t * b.v)}; }
+__device__ __forceinline__ LD operator*(LD a, double s) { return LD{a.v * s, a.t * s}; }
+__device__ __forceinline__ LD operator*(double s, LD a) { return LD{a.v * s, a.t * s}; }
+// quotient rule: (f/g, (f_c - (f/g) g_c) / g)
+__device__ __forceinline__ LD operator/(LD a, LD b) {
+    double q = a.v / b.v;
+    return LD{q, (a.t - q * b.t) / b.v};
+}
+// acc + a b
+__device__ __forceinline__ LD fmad(LD a, LD b, LD acc) {
+    return LD{fma(a.v, b.v, acc.v), fma(a.v, b.t, fma(a.t, b.v, acc.t))};
+}
+// function rule h(F) = (h(f), h'(f) f_c)
+__device__ __forceinline__ LD dsqrt(LD a) {
+    double s = sqrt(a.v);
+    return LD{s, a.t * (0.5 / s)};
+}
+__device__ __forceinline__ LD dsin(LD a) { return LD{sin(a.v), cos(a.v) * a.t}; }
+__device__ __forceinline__ LD dcos(LD a) { return LD{cos(a.v), -sin(a.v) * a.t}; }
+__device__ __forceinline__ LD dsinh(LD a) { return LD{sinh(a.v), cosh(a.v) * a.t}; }
+__device__ __forceinline__ LD dcosh(LD a) { return LD{cosh(a.v), sinh(a.v) * a.t}; }
+
+// Load channel c of a dual stored with channel stride NC at p (p[0] is the value).
+__device__ __forceinline__ LD ldload(const double* p, int c) {
+    double v = p[0];
+    double t = p[c];
+    return LD{v, c ? t : 0.0};
+}
+// The channel this lane stores.
+__device__ __forceinline__ double ldchan(LD a, int c) { return c ? a.t : a.v; }
+
+// ---------------------------------------------------------------- layout
+// Element constants: per element EC_N duals, each NC doubles.
+enum ElemSlot {
+    EC_TAU = 0,  // full step tau = L / n_steps
+    EC_AX = 1,   // 4 entries of the (x, px) half-step map, row-major
+    EC_AY = 5,   // 4 entries of the (y, py) half-step map
+    EC_SLIP = 9, // z += slip * delta per half step
+    EC_N = 10
+};
+
+// Particle-kernel stage flags.
+enum PartFlags {
+    PF_KICK = 1,       // gather E with CIC weights and apply the kick of e_cur
+    PF_HALF_CUR = 2,   // M1(tau/2) of element e_cur
+    PF_HALF_NEXT = 4,  // M1(tau/2) of element e_next
+    PF_DEPOSIT = 8,    // CIC deposit at the resulting position (implies counting)
+    PF_COUNT = 16      // count out-of-box particles and track the extent
+};
+
+enum CounterSlot { CNT_OUTSIDE = 0, CNT_EXT_X = 1, CNT_EXT_Y = 2, CNT_EXT_Z = 3, CNT_N = 8 };
+
+constexpr int MOM_N = 15;  // 3 planes x 5 moments
+
+__host__ __device__ constexpr int channels_for(int ntan) { return ntan == 0 ? 1 : (ntan <= 7 ? 8 : 16); }
+
+}  // namespace dpic

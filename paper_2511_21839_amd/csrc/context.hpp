@@ -1,0 +1,104 @@
+// Host-side context of the dpic library and the launchers each kernel file
+// exports to the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/dpic.h"
+#include "common.hpp"
+
+namespace dpic {
+
+struct Workspace {
+    double* st = nullptr;      // particle state [6][cap][NC]
+    double* st2 = nullptr;     // second state buffer (sort target, read-back staging)
+    int32_t* pid = nullptr;    // original index of each stored particle
+    int32_t* pid2 = nullptr;
+    uint32_t* key = nullptr;   // sort keys
+    uint32_t* hist = nullptr;  // sort histogram / offsets
+    double* rho = nullptr;     // node charges [nz][ny][nx][NC]
+    double* phi = nullptr;     // potential [nz+2][ny+2][nx+2][NC]
+    double* E = nullptr;       // field [nz][ny][nx][3][NC]
+    double2* buf0 = nullptr;   // FFT work arrays
+    double2* buf1 = nullptr;
+    double* ghat = nullptr;    // transform of G on the (nx+1)(ny+1)(nz+1) octant
+    double2* tw = nullptr;     // twiddles exp(-2 pi i m / M) for M = 2nx, 2ny, 2nz
+    double* ec = nullptr;      // element constants [MAX_ELEM][EC_N][NC]
+    double* elem_in = nullptr; // uploaded element L and k duals [MAX_ELEM][2][NC]
+    unsigned long long* counters = nullptr;
+    double* mom_part = nullptr;  // moment partial sums [MOM_BLOCKS][MOM_N][NC]
+    double* mom = nullptr;       // moments [MOM_N][NC]
+    double* emit = nullptr;      // emittance [2][3][NC] (raw, centred)
+    size_t bytes = 0;
+};
+
+constexpr int MOM_BLOCKS = 512;
+constexpr int NUM_TILE_BINS_MAX = 4096;
+
+size_t workspace_layout(const dpic_dims& d, char* base, Workspace* ws);
+
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
+}  // namespace dpic
+
+struct dpic_ctx {
+    dpic_dims dims{};
+    int NC = 1;
+    int ntan = 0;
+    hipStream_t stream = nullptr;
+    dpic::Workspace ws;
+    std::string err;
+
+    // beam
+    bool beam_set = false;
+    double gamma0 = 1, beta0 = 0, kperp = 0, kpar = 0, bunch_charge = 0;
+    // grid
+    bool grid_set = false;
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, h[3] = {0, 0, 0};
+    // lattice
+    bool lattice_set = false;
+    int n_elem = 0, n_periods = 1;
+    std::vector<int> kind, n_steps, L_param, k_param;
+    std::vector<double> L, k;
+    std::vector<int> schedule;  // element index of every step
+    // parameters
+    bool params_set = false;
+    std::vector<double> p, seed;  // seed [np][ntan]
+    // beam state
+    bool beam_init = false;
+    int64_t n = 0;
+    int64_t steps_done = 0;
+    // options
+    int64_t sort_every = 0;
+    bool stage_timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[DPIC_N_STAGE_TIMERS];
+    size_t ev_used[DPIC_N_STAGE_TIMERS] = {0, 0, 0, 0};
+    int64_t stage_launches[DPIC_N_STAGE_TIMERS] = {0, 0, 0, 0};
+};
+
+namespace dpic {
+
+// ---- launchers (particles.hip)
+hipError_t launch_element_consts(dpic_ctx* c);
+hipError_t launch_init_beam(dpic_ctx* c, const double* xi, const double* sig_dual /*[6][NC] host-marshalled*/);
+hipError_t launch_particles(dpic_ctx* c, int flags, int e_cur, int e_next);
+hipError_t launch_canonical_state(dpic_ctx* c);  // st -> st2 in original order
+hipError_t launch_sort(dpic_ctx* c);
+hipError_t launch_zero(dpic_ctx* c, double* p, size_t n);
+
+// ---- launchers (solver.hip)
+hipError_t launch_green(dpic_ctx* c);
+hipError_t launch_solve(dpic_ctx* c);
+hipError_t launch_field(dpic_ctx* c);
+
+// ---- launchers (moments.hip)
+hipError_t launch_moments(dpic_ctx* c);
+
+}  // namespace dpic

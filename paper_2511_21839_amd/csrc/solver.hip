@@ -1,0 +1,595 @@
+// Open-boundary Poisson solve by Hockney's method on the doubled grid, and
+// the central-difference field (Sec. 4: potential from the charge, field by
+// central finite differences; here with open boundaries instead of the
+// paper's conducting pipe).
+//
+// phi(i) = sum_j rho(j) G(i - j) for node indices i in -1..n (one exact ghost
+// ring), j in 0..n-1. With rho zero-padded to M = 2n per dimension and G
+// tabulated at offsets o = i (i <= n) or i - M (i > n), the circular
+// convolution on the M^3 grid equals the aperiodic sum for those targets.
+// G is even, so its transform Ghat is real; it is stored on the
+// (n+1)^3 octant with the 1/(Mx My Mz) normalisation folded in.
+//
+// Channels: the NC real channels of a dual grid array are packed pairwise
+// into NCC = NC/2 complex channels (c, c + NCC); since Ghat is real each
+// complex channel carries two independent real convolutions.
+//
+// Passes (complex arrays, x fastest, NCC channels innermost):
+//   1  rows:  rho[nz][ny][nx][NC]  -> A[nz][ny][Mx][NCC]  (x forward, clears rho)
+//   2  cols:  A -> B[nz][My][Mx][NCC]                       (y forward)
+//   3  cols:  B -> C[nz+2][My][Mx][NCC]                     (z forward, x Ghat, z inverse)
+//   4  cols:  C -> D[nz+2][ny+2][Mx][NCC]                   (y inverse)
+//   5  rows:  D -> phi[nz+2][ny+2][nx+2][NC]                 (x inverse)
+// Forward transforms read only the n nonzero inputs; inverse transforms write
+// only the n+2 outputs needed (positions M-1, 0, .., n).
+//
+// Each pass holds a tile of TILE complex values (one M-point transform per
+// column, B = TILE/M columns) in LDS and runs a Stockham autosort FFT
+// (radix 4, then one radix-2 stage when log2 M is odd) between two LDS
+// buffers; global loads and stores touch B contiguous complex values per row.
+#include "context.hpp"
+
+namespace dpic {
+
+constexpr int FFT_THREADS = 256;
+constexpr int TILE = 1024;
+
+// ---------------------------------------------------------------- FFT core
+template <int M, bool INV>
+__device__ __forceinline__ void stage4(const double* __restrict__ sr, const double* __restrict__ si,
+                                       double* __restrict__ dr, double* __restrict__ di, int Ns, int lb,
+                                       const double* __restrict__ twr, const double* __restrict__ twi) {
+    constexpr int Q = M / 4;
+    const int B = 1 << lb;
+    const int total = Q << lb;
+    const int tstride = M / (Ns * 4);
+    for (int t = threadIdx.x; t < total; t += FFT_THREADS) {
+        const int b = t & (B - 1);
+        const int j = t >> lb;
+        const int k = j & (Ns - 1);
+        double ar[4], ai[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            ar[r] = sr[((j + r * Q) << lb) + b];
+            ai[r] = si[((j + r * Q) << lb) + b];
+        }
+        if (k != 0) {
+#pragma unroll
+            for (int r = 1; r < 4; ++r) {
+                const int m = r * k * tstride;
+                const double wr = twr[m];
+                const double wi = INV ? -twi[m] : twi[m];
+                const double xr = ar[r] * wr - ai[r] * wi;
+                const double xi = ar[r] * wi + ai[r] * wr;
+                ar[r] = xr;
+                ai[r] = xi;
+            }
+        }
+        const double t0r = ar[0] + ar[2], t0i = ai[0] + ai[2];
+        const double t1r = ar[0] - ar[2], t1i = ai[0] - ai[2];
+        const double t2r = ar[1] + ar[3], t2i = ai[1] + ai[3];
+        const double t3r = ar[1] - ar[3], t3i = ai[1] - ai[3];
+        const int base = (j - k) * 4 + k;
+        dr[(base << lb) + b] = t0r + t2r;
+        di[(base << lb) + b] = t0i + t2i;
+        dr[((base + 2 * Ns) << lb) + b] = t0r - t2r;
+        di[((base + 2 * Ns) << lb) + b] = t0i - t2i;
+        if (!INV) {  // X1 = t1 - i t3, X3 = t1 + i t3
+            dr[((base + Ns) << lb) + b] = t1r + t3i;
+            di[((base + Ns) << lb) + b] = t1i - t3r;
+            dr[((base + 3 * Ns) << lb) + b] = t1r - t3i;
+            di[((base + 3 * Ns) << lb) + b] = t1i + t3r;
+        } else {  // X1 = t1 + i t3, X3 = t1 - i t3
+            dr[((base + Ns) << lb) + b] = t1r - t3i;
+            di[((base + Ns) << lb) + b] = t1i + t3r;
+            dr[((base + 3 * Ns) << lb) + b] = t1r + t3i;
+            di[((base + 3 * Ns) << lb) + b] = t1i - t3r;
+        }
+    }
+}
+
+template <int M, bool INV>
+__device__ __forceinline__ void stage2(const double* __restrict__ sr, const double* __restrict__ si,
+                                       double* __restrict__ dr, double* __restrict__ di, int Ns, int lb,
+                                       const double* __restrict__ twr, const double* __restrict__ twi) {
+    constexpr int Q = M / 2;
+    const int B = 1 << lb;
+    const int total = Q << lb;
+    const int tstride = M / (Ns * 2);
+    for (int t = threadIdx.x; t < total; t += FFT_THREADS) {
+        const int b = t & (B - 1);
+        const int j = t >> lb;
+        const int k = j & (Ns - 1);
+        const double a0r = sr[(j << lb) + b], a0i = si[(j << lb) + b];
+        double a1r = sr[((j + Q) << lb) + b], a1i = si[((j + Q) << lb) + b];
+        if (k != 0) {
+            const int m = k * tstride;
+            const double wr = twr[m];
+            const double wi = INV ? -twi[m] : twi[m];
+            const double xr = a1r * wr - a1i * wi;
+            const double xi = a1r * wi + a1i * wr;
+            a1r = xr;
+            a1i = xi;
+        }
+        const int base = (j - k) * 2 + k;
+        dr[(base << lb) + b] = a0r + a1r;
+        di[(base << lb) + b] = a0i + a1i;
+        dr[((base + Ns) << lb) + b] = a0r - a1r;
+        di[((base + Ns) << lb) + b] = a0i - a1i;
+    }
+}
+
+// M-point transform of each column of the [M][B] tile in (sr, si); (dr, di)
+// is scratch. On return (sr, si) point at the result.
+template <int M, bool INV>
+__device__ __forceinline__ void fft_tile(double*& sr, double*& si, double*& dr, double*& di, int lb,
+                                         const double* twr, const double* twi) {
+    int Ns = 1;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        if (Ns * 4 > M) break;
+        stage4<M, INV>(sr, si, dr, di, Ns, lb, twr, twi);
+        __syncthreads();
+        double* t = sr; sr = dr; dr = t;
+        t = si; si = di; di = t;
+        Ns *= 4;
+    }
+    if (Ns < M) {
+        stage2<M, INV>(sr, si, dr, di, Ns, lb, twr, twi);
+        __syncthreads();
+        double* t = sr; sr = dr; dr = t;
+        t = si; si = di; di = t;
+    }
+}
+
+template <int M>
+__device__ __forceinline__ void load_twiddles(double* twr, double* twi, const double2* __restrict__ tw) {
+    for (int m = threadIdx.x; m < M; m += FFT_THREADS) {
+        const double2 w = tw[m];
+        twr[m] = w.x;
+        twi[m] = w.y;
+    }
+}
+
+__device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
+
+// ---------------------------------------------------------------- pass 1
+template <int M, int NC>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_fwd(double* __restrict__ rho, double2* __restrict__ out,
+                                                              int nx, int rows, const double2* __restrict__ tw) {
+    constexpr int NCC = NC == 1 ? 1 : NC / 2;
+    constexpr int B = TILE / M;
+    constexpr int RB = B / NCC;
+    constexpr int LB = (B == 1) ? 0 : (B == 2) ? 1 : (B == 4) ? 2 : (B == 8) ? 3 : (B == 16) ? 4 : (B == 32) ? 5 : (B == 64) ? 6 : 7;
+    __shared__ double s0r[TILE], s0i[TILE], s1r[TILE], s1i[TILE], twr[M], twi[M];
+    load_twiddles<M>(twr, twi, tw);
+    for (int t = threadIdx.x; t < TILE; t += FFT_THREADS) {
+        s0r[t] = 0.0;
+        s0i[t] = 0.0;
+    }
+    __syncthreads();
+    const int row0 = blockIdx.x * RB;
+    const int per_row = nx * NC;
+    for (int t = threadIdx.x; t < RB * per_row; t += FFT_THREADS) {
+        const int r = t / per_row;
+        const int rem = t - r * per_row;
+        const int x = rem / NC;
+        const int ch = rem - x * NC;
+        const int row = row0 + r;
+        if (row < rows) {
+            const size_t gi = (size_t)row * per_row + rem;
+            const double v = rho[gi];
+            rho[gi] = 0.0;
+            const int col = r * NCC + (ch % NCC);
+            if (NC == 1 || ch < NCC)
+                s0r[x * B + col] = v;
+            else
+                s0i[x * B + col] = v;
+        }
+    }
+    __syncthreads();
+    double *sr = s0r, *si = s0i, *dr = s1r, *di = s1i;
+    fft_tile<M, false>(sr, si, dr, di, LB, twr, twi);
+    for (int t = threadIdx.x; t < RB * M * NCC; t += FFT_THREADS) {
+        const int r = t / (M * NCC);
+        const int rem = t - r * M * NCC;
+        const int kx = rem / NCC;
+        const int j = rem - kx * NCC;
+        const int row = row0 + r;
+        if (row < rows) out[(size_t)row * M * NCC + rem] = make_double2(sr[kx * B + r * NCC + j], si[kx * B + r * NCC + j]);
+    }
+}
+
+// ---------------------------------------------------------------- pass 5
+template <int M, int NC>
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_inv(const double2* __restrict__ in, double* __restrict__ phi,
+                                                              int nx, int rows, const double2* __restrict__ tw) {
+    constexpr int NCC = NC == 1 ? 1 : NC / 2;
+    constexpr int B = TILE / M;
+    constexpr int RB = B / NCC;
+    constexpr int LB = (B == 1) ? 0 : (B == 2) ? 1 : (B == 4) ? 2 : (B == 8) ? 3 : (B == 16) ? 4 : (B == 32) ? 5 : (B == 64) ? 6 : 7;
+    __shared__ double s0r[TILE], s0i[TILE], s1r[TILE], s1i[TILE], twr[M], twi[M];
+    load_twiddles<M>(twr, twi, tw);
+    const int row0 = blockIdx.x * RB;
+    for (int t = threadIdx.x; t < RB * M * NCC; t += FFT_THREADS) {
+        const int r = t / (M * NCC);
+        const int rem = t - r * M * NCC;
+        const int kx = rem / NCC;
+        const int j = rem - kx * NCC;
+        const int row = row0 + r;
+        double2 v = make_double2(0.0, 0.0);
+        if (row < rows) v = in[(size_t)row * M * NCC + rem];
+        s0r[kx * B + r * NCC + j] = v.x;
+        s0i[kx * B + r * NCC + j] = v.y;
+    }
+    __syncthreads();
+    double *sr = s0r, *si = s0i, *dr = s1r, *di = s1i;
+    fft_tile<M, true>(sr, si, dr, di, LB, twr, twi);
+    const int nxo = nx + 2;
+    const int per_row = nxo * NC;
+    for (int t = threadIdx.x; t < RB * per_row; t += FFT_THREADS) {
+        const int r = t / per_row;
+        const int rem = t - r * per_row;
+        const int xo = rem / NC;
+        const int ch = rem - xo * NC;
+        const int row = row0 + r;
+        if (row < rows) {
+            const int xs = (xo + M - 1) & (M - 1);  // output slot xo holds node xo - 1
+            const int col = r * NCC + (ch % NCC);
+            phi[(size_t)row * per_row + rem] = (NC == 1 || ch < NCC) ? sr[xs * B + col] : si[xs * B + col];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- passes 2-4
+struct ColArgs {
+    int W;            // columns per outer index
+    int lb;           // log2 of columns per tile
+    int64_t bstride;  // element stride between neighbouring columns
+    int64_t in_outer, in_stride;
+    int n_in;         // nonzero input rows
+    int64_t out_outer, out_stride;
+    int n_out;        // output rows; row t holds transform row (t - out_shift) mod M
+    int out_shift;
+    // Ghat multiply (mode 1): column w is (kx = w / ncc), outer index is ky
+    const double* ghat;
+    int ncc, gnx1, gny1, Mx, My;
+};
+
+template <int M, int MODE>  // 0: forward, 1: forward * Ghat * inverse, 2: inverse
+__global__ __launch_bounds__(FFT_THREADS) void k_fft_cols(const double2* __restrict__ in, double2* __restrict__ out,
+                                                          ColArgs a, const double2* __restrict__ tw) {
+    __shared__ double s0r[TILE], s0i[TILE], s1r[TILE], s1i[TILE], twr[M], twi[M];
+    load_twiddles<M>(twr, twi, tw);
+    const int B = 1 << a.lb;
+    const int tiles = a.W >> a.lb;
+    const int outer = blockIdx.x / tiles;
+    const int w0 = (blockIdx.x - outer * tiles) << a.lb;
+    const double2* src = in + (int64_t)outer * a.in_outer + (int64_t)w0 * a.bstride;
+    for (int t = threadIdx.x; t < (M << a.lb); t += FFT_THREADS) {
+        const int r = t >> a.lb;
+        const int b = t & (B - 1);
+        double2 v = make_double2(0.0, 0.0);
+        if (r < a.n_in) v = src[(int64_t)r * a.in_stride + (int64_t)b * a.bstride];
+        s0r[t] = v.x;
+        s0i[t] = v.y;
+    }
+    __syncthreads();
+    double *sr = s0r, *si = s0i, *dr = s1r, *di = s1i;
+    fft_tile<M, MODE == 2>(sr, si, dr, di, a.lb, twr, twi);
+    if (MODE == 1) {
+        const int ky = outer;
+        const int gy = ky <= a.My - ky ? ky : a.My - ky;
+        for (int t = threadIdx.x; t < (M << a.lb); t += FFT_THREADS) {
+            const int kz = t >> a.lb;
+            const int b = t & (B - 1);
+            const int kx = (w0 + b) / a.ncc;
+            const int gz = kz <= M - kz ? kz : M - kz;
+            const int gx = kx <= a.Mx - kx ? kx : a.Mx - kx;
+            const double g = a.ghat[((int64_t)gz * a.gny1 + gy) * a.gnx1 + gx];
+            sr[t] *= g;
+            si[t] *= g;
+        }
+        __syncthreads();
+        fft_tile<M, true>(sr, si, dr, di, a.lb, twr, twi);
+    }
+    double2* dst = out + (int64_t)outer * a.out_outer + (int64_t)w0 * a.bstride;
+    for (int t = threadIdx.x; t < (a.n_out << a.lb); t += FFT_THREADS) {
+        const int r = t >> a.lb;
+        const int b = t & (B - 1);
+        const int rs = (r - a.out_shift + M) & (M - 1);
+        dst[(int64_t)r * a.out_stride + (int64_t)b * a.bstride] = make_double2(sr[(rs << a.lb) + b], si[(rs << a.lb) + b]);
+    }
+}
+
+template <int MODE>
+static hipError_t launch_cols(int M, int n_outer, const ColArgs& a0, const double2* in, double2* out,
+                              const double2* tw, hipStream_t s) {
+    ColArgs a = a0;
+    int B = TILE / M;
+    if (B > a.W) B = a.W;
+    a.lb = 31 - __builtin_clz((unsigned)B);
+    const unsigned blocks = (unsigned)n_outer * (unsigned)(a.W / B);
+    switch (M) {
+        case 16: hipLaunchKernelGGL((k_fft_cols<16, MODE>), dim3(blocks), dim3(FFT_THREADS), 0, s, in, out, a, tw); break;
+        case 32: hipLaunchKernelGGL((k_fft_cols<32, MODE>), dim3(blocks), dim3(FFT_THREADS), 0, s, in, out, a, tw); break;
+        case 64: hipLaunchKernelGGL((k_fft_cols<64, MODE>), dim3(blocks), dim3(FFT_THREADS), 0, s, in, out, a, tw); break;
+        case 128: hipLaunchKernelGGL((k_fft_cols<128, MODE>), dim3(blocks), dim3(FFT_THREADS), 0, s, in, out, a, tw); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int NC>
+static hipError_t launch_rows_fwd_nc(int M, double* rho, double2* out, int nx, int rows, const double2* tw, hipStream_t s) {
+    constexpr int NCC = NC == 1 ? 1 : NC / 2;
+    switch (M) {
+#define DPIC_ROWS_FWD(MM)                                                                                       \
+    case MM: {                                                                                                  \
+        constexpr int RB = (TILE / MM) / NCC;                                                                   \
+        hipLaunchKernelGGL((k_fft_rows_fwd<MM, NC>), dim3((rows + RB - 1) / RB), dim3(FFT_THREADS), 0, s, rho, \
+                           out, nx, rows, tw);                                                                  \
+        break;                                                                                                  \
+    }
+        DPIC_ROWS_FWD(16) DPIC_ROWS_FWD(32) DPIC_ROWS_FWD(64) DPIC_ROWS_FWD(128)
+#undef DPIC_ROWS_FWD
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int NC>
+static hipError_t launch_rows_inv_nc(int M, const double2* in, double* phi, int nx, int rows, const double2* tw, hipStream_t s) {
+    constexpr int NCC = NC == 1 ? 1 : NC / 2;
+    switch (M) {
+#define DPIC_ROWS_INV(MM)                                                                                      \
+    case MM: {                                                                                                 \
+        constexpr int RB = (TILE / MM) / NCC;                                                                  \
+        hipLaunchKernelGGL((k_fft_rows_inv<MM, NC>), dim3((rows + RB - 1) / RB), dim3(FFT_THREADS), 0, s, in, \
+                           phi, nx, rows, tw);                                                                 \
+        break;                                                                                                 \
+    }
+        DPIC_ROWS_INV(16) DPIC_ROWS_INV(32) DPIC_ROWS_INV(64) DPIC_ROWS_INV(128)
+#undef DPIC_ROWS_INV
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_solve(dpic_ctx* cx) {
+    const int nx = cx->dims.nx, ny = cx->dims.ny, nz = cx->dims.nz;
+    const int Mx = 2 * nx, My = 2 * ny, Mz = 2 * nz;
+    const int NC = cx->NC;
+    const int NCC = NC == 1 ? 1 : NC / 2;
+    const double2* twx = cx->ws.tw;
+    const double2* twy = cx->ws.tw + Mx;
+    const double2* twz = cx->ws.tw + Mx + My;
+    hipStream_t s = cx->stream;
+    hipError_t e;
+    // 1: x forward, rho -> A
+    switch (NC) {
+        case 1: e = launch_rows_fwd_nc<1>(Mx, cx->ws.rho, cx->ws.buf0, nx, ny * nz, twx, s); break;
+        case 8: e = launch_rows_fwd_nc<8>(Mx, cx->ws.rho, cx->ws.buf0, nx, ny * nz, twx, s); break;
+        default: e = launch_rows_fwd_nc<16>(Mx, cx->ws.rho, cx->ws.buf0, nx, ny * nz, twx, s); break;
+    }
+    if (e != hipSuccess) return e;
+    const int64_t W = (int64_t)Mx * NCC;
+    ColArgs a{};
+    a.W = (int)W;
+    a.bstride = 1;
+    a.ghat = cx->ws.ghat;
+    a.ncc = NCC;
+    a.gnx1 = nx + 1;
+    a.gny1 = ny + 1;
+    a.Mx = Mx;
+    a.My = My;
+    // 2: y forward, A -> B
+    a.in_outer = (int64_t)ny * W;
+    a.in_stride = W;
+    a.n_in = ny;
+    a.out_outer = (int64_t)My * W;
+    a.out_stride = W;
+    a.n_out = My;
+    a.out_shift = 0;
+    if ((e = launch_cols<0>(My, nz, a, cx->ws.buf0, cx->ws.buf1, twy, s)) != hipSuccess) return e;
+    // 3: z forward, Ghat, z inverse, B -> C
+    a.in_outer = W;
+    a.in_stride = (int64_t)My * W;
+    a.n_in = nz;
+    a.out_outer = W;
+    a.out_stride = (int64_t)My * W;
+    a.n_out = nz + 2;
+    a.out_shift = 1;
+    if ((e = launch_cols<1>(Mz, My, a, cx->ws.buf1, cx->ws.buf0, twz, s)) != hipSuccess) return e;
+    // 4: y inverse, C -> D
+    a.in_outer = (int64_t)My * W;
+    a.in_stride = W;
+    a.n_in = My;
+    a.out_outer = (int64_t)(ny + 2) * W;
+    a.out_stride = W;
+    a.n_out = ny + 2;
+    a.out_shift = 1;
+    if ((e = launch_cols<2>(My, nz + 2, a, cx->ws.buf0, cx->ws.buf1, twy, s)) != hipSuccess) return e;
+    // 5: x inverse, D -> phi
+    switch (NC) {
+        case 1: return launch_rows_inv_nc<1>(Mx, cx->ws.buf1, cx->ws.phi, nx, (ny + 2) * (nz + 2), twx, s);
+        case 8: return launch_rows_inv_nc<8>(Mx, cx->ws.buf1, cx->ws.phi, nx, (ny + 2) * (nz + 2), twx, s);
+        default: return launch_rows_inv_nc<16>(Mx, cx->ws.buf1, cx->ws.phi, nx, (ny + 2) * (nz + 2), twx, s);
+    }
+}
+
+// ---------------------------------------------------------------- Green's function
+// Mean of 1/r over the box [-a,a] x [-b,b] x [-c,c] from the closed-form
+// antiderivative F of 1/r (d^3 F / dx dy dz = 1/r):
+// F = yz ln(x+r) + xz ln(y+r) + xy ln(z+r)
+//     - x^2/2 atan(yz/(xr)) - y^2/2 atan(xz/(yr)) - z^2/2 atan(xy/(zr)),
+// evaluated over the octant [0,a]x[0,b]x[0,c] by inclusion-exclusion; the
+// corners with a zero coordinate only keep the yz ln r style terms.
+__device__ double inv_r_antideriv(double x, double y, double z) {
+    const double r = sqrt(x * x + y * y + z * z);
+    double t = 0.0;
+    if (y > 0.0 && z > 0.0) t += y * z * log(x + r);
+    if (x > 0.0 && z > 0.0) t += x * z * log(y + r);
+    if (x > 0.0 && y > 0.0) t += x * y * log(z + r);
+    if (x > 0.0) t -= 0.5 * x * x * atan(y * z / (x * r));
+    if (y > 0.0) t -= 0.5 * y * y * atan(x * z / (y * r));
+    if (z > 0.0) t -= 0.5 * z * z * atan(x * y / (z * r));
+    return t;
+}
+
+__device__ double mean_inv_r(double hx, double hy, double hz) {
+    const double a = 0.5 * hx, b = 0.5 * hy, c = 0.5 * hz;
+    double s = 0.0;
+    for (int i = 0; i < 8; ++i) {
+        const double x = (i & 1) ? 0.0 : a;
+        const double y = (i & 2) ? 0.0 : b;
+        const double z = (i & 4) ? 0.0 : c;
+        const double sg = (__popc(i) & 1) ? -1.0 : 1.0;
+        s += sg * inv_r_antideriv(x, y, z);
+    }
+    return 8.0 * s / (hx * hy * hz);
+}
+
+// G on the doubled grid [Mz][My][Mx]; hz_rest = gamma0 hz (rest-frame cell).
+__global__ void k_green_fill(double2* __restrict__ g, int nx, int ny, int nz, double hx, double hy, double hz_rest,
+                             double coef) {
+    const int Mx = 2 * nx, My = 2 * ny, Mz = 2 * nz;
+    const int64_t total = (int64_t)Mx * My * Mz;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int ix = (int)(i % Mx);
+    const int iy = (int)((i / Mx) % My);
+    const int iz = (int)(i / ((int64_t)Mx * My));
+    const int ox = ix <= nx ? ix : ix - Mx;
+    const int oy = iy <= ny ? iy : iy - My;
+    const int oz = iz <= nz ? iz : iz - Mz;
+    double v;
+    if (ox == 0 && oy == 0 && oz == 0) {
+        v = coef * mean_inv_r(hx, hy, hz_rest);
+    } else {
+        const double rx = ox * hx, ry = oy * hy, rz = oz * hz_rest;
+        v = coef / sqrt(rx * rx + ry * ry + rz * rz);
+    }
+    g[i] = make_double2(v, 0.0);
+}
+
+__global__ void k_green_extract(const double2* __restrict__ G, double* __restrict__ ghat, int nx, int ny, int nz,
+                                double scale) {
+    const int Mx = 2 * nx, My = 2 * ny;
+    const int64_t total = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int ix = (int)(i % (nx + 1));
+    const int iy = (int)((i / (nx + 1)) % (ny + 1));
+    const int iz = (int)(i / ((int64_t)(nx + 1) * (ny + 1)));
+    ghat[i] = G[((int64_t)iz * My + iy) * Mx + ix].x * scale;
+}
+
+// tw[m] = exp(-2 pi i m / M) for each axis, tables back to back.
+__global__ void k_twiddles(double2* __restrict__ tw, int Mx, int My, int Mz) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int M, m;
+    if (i < Mx) {
+        M = Mx;
+        m = i;
+    } else if (i < Mx + My) {
+        M = My;
+        m = i - Mx;
+    } else if (i < Mx + My + Mz) {
+        M = Mz;
+        m = i - Mx - My;
+    } else {
+        return;
+    }
+    double sn, cs;
+    sincospi(2.0 * (double)m / (double)M, &sn, &cs);
+    tw[i] = make_double2(cs, -sn);
+}
+
+hipError_t launch_green(dpic_ctx* cx) {
+    const int nx = cx->dims.nx, ny = cx->dims.ny, nz = cx->dims.nz;
+    const int Mx = 2 * nx, My = 2 * ny, Mz = 2 * nz;
+    hipStream_t s = cx->stream;
+    hipLaunchKernelGGL(k_twiddles, dim3((Mx + My + Mz + 255) / 256), dim3(256), 0, s, cx->ws.tw, Mx, My, Mz);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const double eps0 = 8.8541878128e-12;
+    const double pi = 3.14159265358979323846;
+    const double coef = 1.0 / (4.0 * pi * eps0);
+    const int64_t total = (int64_t)Mx * My * Mz;
+    hipLaunchKernelGGL(k_green_fill, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, cx->ws.buf0, nx, ny, nz,
+                       cx->h[0], cx->h[1], cx->gamma0 * cx->h[2], coef);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const double2* twx = cx->ws.tw;
+    const double2* twy = cx->ws.tw + Mx;
+    const double2* twz = cx->ws.tw + Mx + My;
+    ColArgs a{};
+    // x: outer z, columns y (stride Mx), rows x (stride 1)
+    a.W = My;
+    a.bstride = Mx;
+    a.in_outer = (int64_t)Mx * My;
+    a.in_stride = 1;
+    a.n_in = Mx;
+    a.out_outer = (int64_t)Mx * My;
+    a.out_stride = 1;
+    a.n_out = Mx;
+    a.out_shift = 0;
+    if ((e = launch_cols<0>(Mx, Mz, a, cx->ws.buf0, cx->ws.buf1, twx, s)) != hipSuccess) return e;
+    // y: outer z, columns x (stride 1), rows y (stride Mx)
+    a.W = Mx;
+    a.bstride = 1;
+    a.in_stride = Mx;
+    a.n_in = My;
+    a.out_stride = Mx;
+    a.n_out = My;
+    if ((e = launch_cols<0>(My, Mz, a, cx->ws.buf1, cx->ws.buf0, twy, s)) != hipSuccess) return e;
+    // z: outer y, columns x, rows z (stride Mx My)
+    a.in_outer = Mx;
+    a.in_stride = (int64_t)Mx * My;
+    a.n_in = Mz;
+    a.out_outer = Mx;
+    a.out_stride = (int64_t)Mx * My;
+    a.n_out = Mz;
+    if ((e = launch_cols<0>(Mz, My, a, cx->ws.buf0, cx->ws.buf1, twz, s)) != hipSuccess) return e;
+    const int64_t oct = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+    hipLaunchKernelGGL(k_green_extract, dim3((unsigned)((oct + 255) / 256)), dim3(256), 0, s, cx->ws.buf1, cx->ws.ghat,
+                       nx, ny, nz, 1.0 / (double)total);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- field
+// E = -grad phi by central differences on every node; phi carries one ghost
+// ring. cz includes 1/gamma0 (rest-frame longitudinal field).
+template <int NC>
+__global__ void k_field(const double* __restrict__ phi, double* __restrict__ E, int nx, int ny, int nz, double cx,
+                        double cy, double cz) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)nx * ny * nz * NC;
+    if (gid >= total) return;
+    const int c = (int)(gid % NC);
+    const int64_t node = gid / NC;
+    const int ix = (int)(node % nx);
+    const int iy = (int)((node / nx) % ny);
+    const int iz = (int)(node / ((int64_t)nx * ny));
+    const int64_t sx = NC, sy = (int64_t)(nx + 2) * NC, sz = (int64_t)(nx + 2) * (ny + 2) * NC;
+    const double* p = phi + (iz + 1) * sz + (iy + 1) * sy + (ix + 1) * sx + c;
+    double* o = E + node * 3 * NC + c;
+    o[0] = cx * (p[sx] - p[-sx]);
+    o[NC] = cy * (p[sy] - p[-sy]);
+    o[2 * NC] = cz * (p[sz] - p[-sz]);
+}
+
+hipError_t launch_field(dpic_ctx* cx) {
+    const int nx = cx->dims.nx, ny = cx->dims.ny, nz = cx->dims.nz;
+    const double fx = -0.5 / cx->h[0], fy = -0.5 / cx->h[1], fz = -0.5 / (cx->h[2] * cx->gamma0);
+    const int64_t total = (int64_t)nx * ny * nz * cx->NC;
+    dim3 grid((unsigned)((total + 255) / 256)), block(256);
+    switch (cx->NC) {
+        case 1: hipLaunchKernelGGL(k_field<1>, grid, block, 0, cx->stream, cx->ws.phi, cx->ws.E, nx, ny, nz, fx, fy, fz); break;
+        case 8: hipLaunchKernelGGL(k_field<8>, grid, block, 0, cx->stream, cx->ws.phi, cx->ws.E, nx, ny, nz, fx, fy, fz); break;
+        default: hipLaunchKernelGGL(k_field<16>, grid, block, 0, cx->stream, cx->ws.phi, cx->ws.E, nx, ny, nz, fx, fy, fz); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace dpic
