@@ -48,6 +48,43 @@ def assert_particles_close(got, want, vtol=VALUE_RTOL, dtol=DERIV_RTOL):
             assert ed <= dtol, f"coordinate {j} derivative error {ed:.3e}"
 
 
+def moment_term_scales(particles):
+    """Mean magnitude of the summed terms of every moment, (3, 5, 2): value, derivatives.
+
+    A moment is a sum over particles; when the terms cancel (the mean
+    momentum's derivatives vanish by momentum conservation) the rounding error
+    of either side is relative to the sum of |terms|, not to the sum itself.
+    """
+    P = np.asarray(particles)
+    out = np.zeros((3, 5, 2))
+    for pl in range(3):
+        u, p = P[:, 2 * pl], P[:, 2 * pl + 1]
+        terms = []
+        for a, b in ((u, u), (u, p), (p, p)):
+            v = a[:, 0] * b[:, 0]
+            d = a[:, :1] * b[:, 1:] + a[:, 1:] * b[:, :1]
+            terms.append((v, d))
+        terms.append((u[:, 0], u[:, 1:]))
+        terms.append((p[:, 0], p[:, 1:]))
+        for m, (v, d) in enumerate(terms):
+            out[pl, m, 0] = np.abs(v).mean()
+            out[pl, m, 1] = np.abs(d).max(axis=1).mean() if d.shape[1] else 0.0
+    return out
+
+
+def assert_moments_close(got, want, ref_particles, vtol=VALUE_RTOL, dtol=DERIV_RTOL):
+    got, want = np.asarray(got), np.asarray(want)
+    sc = moment_term_scales(ref_particles)
+    for pl in range(3):
+        for m in range(5):
+            g, w = got[pl, m], want[pl, m]
+            sv = max(abs(w[0]), sc[pl, m, 0])
+            assert abs(g[0] - w[0]) <= vtol * sv, (pl, m, g[0], w[0])
+            if g.shape[0] > 1:
+                sd = max(np.abs(w[1:]).max(), sc[pl, m, 1])
+                assert np.abs(g[1:] - w[1:]).max() <= dtol * sd, (pl, m, g[1:], w[1:])
+
+
 def assert_outputs_close(got, want, vtol=VALUE_RTOL, dtol=DERIV_RTOL, what="output"):
     """got/want: (..., 1+ntan); value per scalar, derivatives normwise per output."""
     got, want = np.asarray(got), np.asarray(want)
