@@ -49,6 +49,21 @@ def _cpu_baseline(w, xi, steps: int):
     }
 
 
+def _copy_calibration(mib: int) -> int:
+    """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give the
+    factor that turns counter KiB into HBM bytes for the same profiler setup."""
+    import torch
+
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": n * 8, "copies": 3}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,7 +72,11 @@ def main(argv=None):
     ap.add_argument("--sort-every", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (to scale HBM byte counters)")
     args = ap.parse_args(argv)
+    if args.copy_calibration:
+        return _copy_calibration(args.copy_calibration)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the design notes describe how the step would shard)", file=sys.stderr)

@@ -74,12 +74,21 @@ void timer_end(dpic_ctx* c, int stage, hipEvent_t end) {
 
 enum { T_PART = 0, T_SOLVE = 1, T_FIELD = 2, T_SORT = 3 };
 
-int run_particles(dpic_ctx* c, int flags, int ecur, int enext) {
+int run_particles(dpic_ctx* c, int flags, int e_tau, const double* map) {
     hipEvent_t end;
     timer_begin(c, T_PART, &end);
-    HIPCHK(c, launch_particles(c, flags, ecur, enext));
+    HIPCHK(c, launch_particles(c, flags, e_tau, map, c->sort_every > 0 && c->chunks_valid));
     timer_end(c, T_PART, end);
     return DPIC_OK;
+}
+
+// Map block that ends step s: the second half step of element e(s) fused with
+// the first half step of e(s+1), or the lone half step on the last step of a call.
+const double* closing_map(const dpic_ctx* c, int64_t s, bool last) {
+    const int e = c->schedule[s];
+    if (last) return element_map_block(c, e, EC_HALF);
+    const int en = c->schedule[s + 1];
+    return element_map_block(c, e, en == e ? EC_SAME : EC_NEXT);
 }
 
 int run_solve_field(dpic_ctx* c) {
@@ -180,7 +189,15 @@ size_t workspace_layout(const dpic_dims& d, char* base, Workspace* ws) {
     w.pid = (int32_t*)take(cap * sizeof(int32_t));
     w.pid2 = (int32_t*)take(cap * sizeof(int32_t));
     w.key = (uint32_t*)take(cap * sizeof(uint32_t));
-    w.hist = (uint32_t*)take((size_t)(NUM_TILE_BINS_MAX + 1) * 2 * sizeof(uint32_t));
+    size_t nbins = 1;
+    for (size_t nd : {nx, ny, nz}) nbins *= (nd - 1 + TILE_EDGE - 1) / TILE_EDGE;
+    nbins += 1;
+    const size_t sort_blocks = (cap + SORT_PB - 1) / SORT_PB;
+    const size_t ncount = nbins * sort_blocks;
+    w.counts = (uint32_t*)take(ncount * sizeof(uint32_t));
+    w.seg = (uint32_t*)take(((ncount + 1023) / 1024 + 1) * sizeof(uint32_t));
+    w.chunks = (int4*)take((nbins + (cap + TILE_CHUNK - 1) / TILE_CHUNK + 1) * sizeof(int4));
+    w.nchunks = (uint32_t*)take(sizeof(uint32_t));
     w.rho = (double*)take(nx * ny * nz * NC * sizeof(double));
     w.phi = (double*)take((nx + 2) * (ny + 2) * (nz + 2) * NC * sizeof(double));
     w.E = (double*)take(nx * ny * nz * 3 * NC * sizeof(double));
@@ -281,6 +298,7 @@ int dpic_set_grid(dpic_ctx* c, const double lo[3], const double hi[3]) {
     HIPCHK(c, launch_green(c));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->grid_set = true;
+    c->chunks_valid = false;
     return DPIC_OK;
 }
 
@@ -361,6 +379,7 @@ int dpic_init_beam(dpic_ctx* c, int64_t n, const double* xi_dev, const double si
     HIPCHK(c, launch_zero(c, c->ws.rho, (size_t)c->dims.nx * c->dims.ny * c->dims.nz * NC));
     c->steps_done = 0;
     c->beam_init = true;
+    c->chunks_valid = false;
     return DPIC_OK;
 }
 
@@ -377,23 +396,27 @@ int dpic_step(dpic_ctx* c, int n) {
                     c->schedule.size());
     const int64_t s0 = c->steps_done, s1 = s0 + n;
     int r;
+    if (sc && c->sort_every > 0 && !c->chunks_valid)
+        if ((r = run_sort(c)) != DPIC_OK) return r;
     if (sc) {
         HIPCHK(c, launch_zero(c, c->ws.rho, (size_t)c->dims.nx * c->dims.ny * c->dims.nz * c->NC));
-        if ((r = run_particles(c, PF_HALF_NEXT | PF_DEPOSIT, 0, c->schedule[s0])) != DPIC_OK) return r;
+        const double* first = element_map_block(c, c->schedule[s0], EC_HALF);
+        if ((r = run_particles(c, PF_MAP | PF_DEPOSIT, c->schedule[s0], first)) != DPIC_OK) return r;
         for (int64_t s = s0; s < s1; ++s) {
             if ((r = run_solve_field(c)) != DPIC_OK) return r;
             const bool last = (s == s1 - 1);
-            const int flags = PF_KICK | PF_HALF_CUR | (last ? 0 : (PF_HALF_NEXT | PF_DEPOSIT));
-            if ((r = run_particles(c, flags, c->schedule[s], last ? 0 : c->schedule[s + 1])) != DPIC_OK) return r;
+            const int flags = PF_KICK | PF_MAP | (last ? 0 : PF_DEPOSIT);
+            if ((r = run_particles(c, flags, c->schedule[s], closing_map(c, s, last))) != DPIC_OK) return r;
             if (c->sort_every > 0 && !last && ((s + 1) % c->sort_every) == 0)
                 if ((r = run_sort(c)) != DPIC_OK) return r;
         }
     } else {
-        if ((r = run_particles(c, PF_HALF_NEXT | PF_COUNT, 0, c->schedule[s0])) != DPIC_OK) return r;
+        const double* first = element_map_block(c, c->schedule[s0], EC_HALF);
+        if ((r = run_particles(c, PF_MAP | PF_COUNT, c->schedule[s0], first)) != DPIC_OK) return r;
         for (int64_t s = s0; s < s1; ++s) {
             const bool last = (s == s1 - 1);
-            const int flags = PF_HALF_CUR | (last ? 0 : (PF_HALF_NEXT | PF_COUNT));
-            if ((r = run_particles(c, flags, c->schedule[s], last ? 0 : c->schedule[s + 1])) != DPIC_OK) return r;
+            const int flags = PF_MAP | (last ? 0 : PF_COUNT);
+            if ((r = run_particles(c, flags, c->schedule[s], closing_map(c, s, last))) != DPIC_OK) return r;
         }
     }
     c->steps_done = s1;
@@ -455,7 +478,7 @@ int dpic_stage(dpic_ctx* c, int stage) {
         case DPIC_STAGE_DEPOSIT:
             if (!c->beam_init || !c->grid_set) return fail(c, DPIC_ESTATE, "stage deposit: needs beam and grid");
             HIPCHK(c, launch_zero(c, c->ws.rho, (size_t)c->dims.nx * c->dims.ny * c->dims.nz * c->NC));
-            HIPCHK(c, launch_particles(c, PF_DEPOSIT, 0, 0));
+            HIPCHK(c, launch_particles(c, PF_DEPOSIT, 0, nullptr, false));
             return DPIC_OK;
         case DPIC_STAGE_SOLVE:
             if (!c->grid_set) return fail(c, DPIC_ESTATE, "stage solve: needs grid");
@@ -546,6 +569,7 @@ int dpic_load_state(dpic_ctx* c, const void* dev_buf) {
     c->n = hdr[0];
     c->steps_done = hdr[1];
     c->beam_init = true;
+    c->chunks_valid = false;
     return DPIC_OK;
 }
 

@@ -61,22 +61,24 @@ __device__ __forceinline__ LD ldload(const double* p, int c) {
 __device__ __forceinline__ double ldchan(LD a, int c) { return c ? a.t : a.v; }
 
 // ---------------------------------------------------------------- layout
-// Element constants: per element EC_N duals, each NC doubles.
+// Element constants: per element EC_N duals, each NC doubles. A "map block"
+// is 9 consecutive duals: the (x, px) 2x2 map row-major, the (y, py) map,
+// and the z slip coefficient (z += slip * delta).
 enum ElemSlot {
-    EC_TAU = 0,  // full step tau = L / n_steps
-    EC_AX = 1,   // 4 entries of the (x, px) half-step map, row-major
-    EC_AY = 5,   // 4 entries of the (y, py) half-step map
-    EC_SLIP = 9, // z += slip * delta per half step
-    EC_N = 10
+    EC_TAU = 0,    // full step tau = L / n_steps
+    EC_HALF = 1,   // map block of M1(tau/2)
+    EC_SAME = 10,  // map block of M1(tau/2) M1(tau/2) (two half steps of this element)
+    EC_NEXT = 19,  // map block of M1'(tau'/2) M1(tau/2) (this element, then the next one)
+    EC_N = 28
 };
+enum MapSlot { MB_AX = 0, MB_AY = 4, MB_SLIP = 8, MB_N = 9 };
 
 // Particle-kernel stage flags.
 enum PartFlags {
-    PF_KICK = 1,       // gather E with CIC weights and apply the kick of e_cur
-    PF_HALF_CUR = 2,   // M1(tau/2) of element e_cur
-    PF_HALF_NEXT = 4,  // M1(tau/2) of element e_next
-    PF_DEPOSIT = 8,    // CIC deposit at the resulting position (implies counting)
-    PF_COUNT = 16      // count out-of-box particles and track the extent
+    PF_KICK = 1,     // gather E with CIC weights and apply the kick of the current element
+    PF_MAP = 2,      // apply one map block (a half step, or two fused half steps)
+    PF_DEPOSIT = 4,  // CIC deposit at the resulting position (implies counting)
+    PF_COUNT = 8     // count out-of-box particles and track the extent
 };
 
 enum CounterSlot { CNT_OUTSIDE = 0, CNT_EXT_X = 1, CNT_EXT_Y = 2, CNT_EXT_Z = 3, CNT_N = 8 };

@@ -19,8 +19,11 @@ struct Workspace {
     double* st2 = nullptr;     // second state buffer (sort target, read-back staging)
     int32_t* pid = nullptr;    // original index of each stored particle
     int32_t* pid2 = nullptr;
-    uint32_t* key = nullptr;   // sort keys
-    uint32_t* hist = nullptr;  // sort histogram / offsets
+    uint32_t* key = nullptr;     // sort keys
+    uint32_t* counts = nullptr;  // per (bin, block) counts, then offsets
+    uint32_t* seg = nullptr;     // scan segment sums
+    int4* chunks = nullptr;      // tiled work list (tile, first, count, -)
+    uint32_t* nchunks = nullptr;
     double* rho = nullptr;     // node charges [nz][ny][nx][NC]
     double* phi = nullptr;     // potential [nz+2][ny+2][nx+2][NC]
     double* E = nullptr;       // field [nz][ny][nx][3][NC]
@@ -39,6 +42,11 @@ struct Workspace {
 
 constexpr int MOM_BLOCKS = 512;
 constexpr int NUM_TILE_BINS_MAX = 4096;
+constexpr int TILE_EDGE = 4;                             // cells per tile edge
+constexpr int TILE_HALO = 1;                             // drift allowance (cells) of the LDS deposit
+constexpr int TILE_R = TILE_EDGE + 2 * TILE_HALO + 1;    // LDS nodes per dimension
+constexpr int TILE_CHUNK = 512;                          // particles per tiled workgroup
+constexpr int SORT_PB = 1024;                            // particles per sort block
 
 size_t workspace_layout(const dpic_dims& d, char* base, Workspace* ws);
 
@@ -76,7 +84,8 @@ struct dpic_ctx {
     int64_t n = 0;
     int64_t steps_done = 0;
     // options
-    int64_t sort_every = 0;
+    int64_t sort_every = 20;
+    bool chunks_valid = false;  // the tiled work list matches the stored order
     bool stage_timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[DPIC_N_STAGE_TIMERS];
     size_t ev_used[DPIC_N_STAGE_TIMERS] = {0, 0, 0, 0};
@@ -88,10 +97,16 @@ namespace dpic {
 // ---- launchers (particles.hip)
 hipError_t launch_element_consts(dpic_ctx* c);
 hipError_t launch_init_beam(dpic_ctx* c, const double* xi, const double* sig_dual /*[6][NC] host-marshalled*/);
-hipError_t launch_particles(dpic_ctx* c, int flags, int e_cur, int e_next);
+// flags: PF_*; e_tau: element whose step size the kick uses; map: map block
+// to apply (element_map_block) or nullptr without PF_MAP.
+hipError_t launch_particles(dpic_ctx* c, int flags, int e_tau, const double* map, bool tiled);
+const double* element_map_block(const dpic_ctx* c, int e, int slot);
 hipError_t launch_canonical_state(dpic_ctx* c);  // st -> st2 in original order
-hipError_t launch_sort(dpic_ctx* c);
 hipError_t launch_zero(dpic_ctx* c, double* p, size_t n);
+
+// ---- launchers (sort.hip)
+bool sort_geometry(const dpic_ctx* c, int* tiles, int* nbins);
+hipError_t launch_sort(dpic_ctx* c);  // also rebuilds the tiled work list
 
 // ---- launchers (solver.hip)
 hipError_t launch_green(dpic_ctx* c);

@@ -1,10 +1,19 @@
 // Particle-side kernels: per-element dual constants, beam initialisation,
-// the fused gather / kick / half-map / deposit kernel, canonical read-back.
+// the fused gather / kick / map / deposit kernel, canonical read-back.
 //
-// Thread mapping: one lane per (particle, channel); a particle's NC lanes are
-// consecutive, so a wavefront handles 64/NC particles and every coordinate of
-// a particle is one contiguous NC*8-byte run (tangents interleaved, SoA over
-// coordinates).
+// Particle state is SoA over coordinates with the tangents interleaved:
+// st[coord][particle][NC]. In the fused step a particle owns a quad of G = 4
+// consecutive lanes (G = 1 when NC = 1); lane q of the quad holds channels
+// q*K .. q*K+K-1 (K = NC/G) of every dual plus the value, so one 16-byte load
+// per lane moves a particle's 64-byte coordinate and a wavefront touches one
+// contiguous kilobyte. The value reaches the other lanes of the quad by a DPP
+// quad broadcast. Lane 0's slot for channel 0 is kept at zero (its value is
+// the separate `v`), so the dual rules need no per-lane branch.
+//
+// The step runs storage-ordered (deposit by global atomics) or tiled: a
+// workgroup takes one chunk of particles sorted into one grid tile and
+// accumulates the deposit in LDS over the tile's nodes plus a halo, flushing
+// it once.
 #include "context.hpp"
 
 namespace dpic {
@@ -63,15 +72,47 @@ __global__ void k_element_consts(ElemTable tab, int n_elem, const double* __rest
     LD slip = s * inv_g2;
     double* o = ec + (size_t)e * EC_N * NC + c;
     o[EC_TAU * NC] = ldchan(tau, c);
-    o[(EC_AX + 0) * NC] = ldchan(ax.a, c);
-    o[(EC_AX + 1) * NC] = ldchan(ax.b, c);
-    o[(EC_AX + 2) * NC] = ldchan(ax.c, c);
-    o[(EC_AX + 3) * NC] = ldchan(ax.d, c);
-    o[(EC_AY + 0) * NC] = ldchan(ay.a, c);
-    o[(EC_AY + 1) * NC] = ldchan(ay.b, c);
-    o[(EC_AY + 2) * NC] = ldchan(ay.c, c);
-    o[(EC_AY + 3) * NC] = ldchan(ay.d, c);
-    o[EC_SLIP * NC] = ldchan(slip, c);
+    double* h = o + EC_HALF * NC;
+    h[(MB_AX + 0) * NC] = ldchan(ax.a, c);
+    h[(MB_AX + 1) * NC] = ldchan(ax.b, c);
+    h[(MB_AX + 2) * NC] = ldchan(ax.c, c);
+    h[(MB_AX + 3) * NC] = ldchan(ax.d, c);
+    h[(MB_AY + 0) * NC] = ldchan(ay.a, c);
+    h[(MB_AY + 1) * NC] = ldchan(ay.b, c);
+    h[(MB_AY + 2) * NC] = ldchan(ay.c, c);
+    h[(MB_AY + 3) * NC] = ldchan(ay.d, c);
+    h[MB_SLIP * NC] = ldchan(slip, c);
+}
+
+// Fused map blocks: B A for the half-step maps A (this element) and B (this
+// element again, or the next element of the period).
+template <int NC>
+__device__ void combine_block(const double* A, const double* B, double* out, int c) {
+#pragma unroll
+    for (int pl = 0; pl < 2; ++pl) {
+        const int o = pl * 4;
+        const LD a00 = ldload(A + (o + 0) * NC, c), a01 = ldload(A + (o + 1) * NC, c);
+        const LD a10 = ldload(A + (o + 2) * NC, c), a11 = ldload(A + (o + 3) * NC, c);
+        const LD b00 = ldload(B + (o + 0) * NC, c), b01 = ldload(B + (o + 1) * NC, c);
+        const LD b10 = ldload(B + (o + 2) * NC, c), b11 = ldload(B + (o + 3) * NC, c);
+        out[(o + 0) * NC] = ldchan(b00 * a00 + b01 * a10, c);
+        out[(o + 1) * NC] = ldchan(b00 * a01 + b01 * a11, c);
+        out[(o + 2) * NC] = ldchan(b10 * a00 + b11 * a10, c);
+        out[(o + 3) * NC] = ldchan(b10 * a01 + b11 * a11, c);
+    }
+    out[MB_SLIP * NC] = ldchan(ldload(A + MB_SLIP * NC, c) + ldload(B + MB_SLIP * NC, c), c);
+}
+
+template <int NC>
+__global__ void k_element_combine(int n_elem, double* __restrict__ ec) {
+    const int e = blockIdx.x;
+    const int c = threadIdx.x;
+    if (e >= n_elem || c >= NC) return;
+    const int en = (e + 1) % n_elem;
+    const double* A = ec + (size_t)e * EC_N * NC + EC_HALF * NC;
+    const double* Bn = ec + (size_t)en * EC_N * NC + EC_HALF * NC;
+    combine_block<NC>(A, A, ec + (size_t)e * EC_N * NC + EC_SAME * NC + c, c);
+    combine_block<NC>(A, Bn, ec + (size_t)e * EC_N * NC + EC_NEXT * NC + c, c);
 }
 
 hipError_t launch_element_consts(dpic_ctx* cx) {
@@ -81,11 +122,20 @@ hipError_t launch_element_consts(dpic_ctx* cx) {
         tab.nsteps[e] = cx->n_steps[e];
     }
     const double inv_g2 = 1.0 / (cx->gamma0 * cx->gamma0);
-    dim3 grid(cx->n_elem), block(cx->NC < 64 ? 64 : cx->NC);
+    dim3 grid(cx->n_elem), block(64);
     switch (cx->NC) {
-        case 1: hipLaunchKernelGGL(k_element_consts<1>, grid, block, 0, cx->stream, tab, cx->n_elem, cx->ws.elem_in, cx->ws.ec, inv_g2); break;
-        case 8: hipLaunchKernelGGL(k_element_consts<8>, grid, block, 0, cx->stream, tab, cx->n_elem, cx->ws.elem_in, cx->ws.ec, inv_g2); break;
-        default: hipLaunchKernelGGL(k_element_consts<16>, grid, block, 0, cx->stream, tab, cx->n_elem, cx->ws.elem_in, cx->ws.ec, inv_g2); break;
+        case 1:
+            hipLaunchKernelGGL(k_element_consts<1>, grid, block, 0, cx->stream, tab, cx->n_elem, cx->ws.elem_in, cx->ws.ec, inv_g2);
+            hipLaunchKernelGGL(k_element_combine<1>, grid, block, 0, cx->stream, cx->n_elem, cx->ws.ec);
+            break;
+        case 8:
+            hipLaunchKernelGGL(k_element_consts<8>, grid, block, 0, cx->stream, tab, cx->n_elem, cx->ws.elem_in, cx->ws.ec, inv_g2);
+            hipLaunchKernelGGL(k_element_combine<8>, grid, block, 0, cx->stream, cx->n_elem, cx->ws.ec);
+            break;
+        default:
+            hipLaunchKernelGGL(k_element_consts<16>, grid, block, 0, cx->stream, tab, cx->n_elem, cx->ws.elem_in, cx->ws.ec, inv_g2);
+            hipLaunchKernelGGL(k_element_combine<16>, grid, block, 0, cx->stream, cx->n_elem, cx->ws.ec);
+            break;
     }
     return hipGetLastError();
 }
@@ -122,12 +172,128 @@ hipError_t launch_init_beam(dpic_ctx* cx, const double* xi, const double* sig_du
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- quad duals
+// Lanes per particle and channels per lane.
+template <int NC>
+struct Quad {
+    static constexpr int G = NC == 1 ? 1 : 4;
+    static constexpr int K = NC / G;
+};
+
+template <int K>
+struct QD {
+    double v;     // value, equal in every lane of the quad
+    double t[K];  // this lane's channels (slot 0 of lane 0 stays 0)
+};
+
+// value of lane 0 of the quad, by DPP quad_perm [0,0,0,0]
+__device__ __forceinline__ double quad_bcast(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x00, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x00, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int K, int G>
+__device__ __forceinline__ QD<K> qd_load(const double* __restrict__ p, int q) {
+    QD<K> r;
+    const double* s = p + q * K;
+    if constexpr (K == 1) {
+        r.t[0] = s[0];
+    } else {
+#pragma unroll
+        for (int i = 0; i < K / 2; ++i) {
+            const double2 w = reinterpret_cast<const double2*>(s)[i];
+            r.t[2 * i] = w.x;
+            r.t[2 * i + 1] = w.y;
+        }
+    }
+    if constexpr (G == 1)
+        r.v = r.t[0];
+    else
+        r.v = quad_bcast(r.t[0]);
+    if (q == 0) r.t[0] = 0.0;
+    return r;
+}
+
+template <int K>
+__device__ __forceinline__ double qd_chan(const QD<K>& x, int q, int k) {
+    return (q == 0 && k == 0) ? x.v : x.t[k];
+}
+
+template <int K>
+__device__ __forceinline__ void qd_store(double* __restrict__ p, const QD<K>& x, int q) {
+    double* s = p + q * K;
+    if constexpr (K == 1) {
+        s[0] = qd_chan(x, q, 0);
+    } else {
+#pragma unroll
+        for (int i = 0; i < K / 2; ++i)
+            reinterpret_cast<double2*>(s)[i] = make_double2(qd_chan(x, q, 2 * i), x.t[2 * i + 1]);
+    }
+}
+
+// product rule
+template <int K>
+__device__ __forceinline__ QD<K> qd_mul(const QD<K>& x, const QD<K>& y) {
+    QD<K> r;
+    r.v = x.v * y.v;
+#pragma unroll
+    for (int k = 0; k < K; ++k) r.t[k] = fma(x.v, y.t[k], x.t[k] * y.v);
+    return r;
+}
+
+// acc + x y
+template <int K>
+__device__ __forceinline__ void qd_fmad(const QD<K>& x, const QD<K>& y, QD<K>& acc) {
+    acc.v = fma(x.v, y.v, acc.v);
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc.t[k] = fma(x.v, y.t[k], fma(x.t[k], y.v, acc.t[k]));
+}
+
+template <int K>
+__device__ __forceinline__ QD<K> qd_scale(const QD<K>& x, double s) {
+    QD<K> r;
+    r.v = x.v * s;
+#pragma unroll
+    for (int k = 0; k < K; ++k) r.t[k] = x.t[k] * s;
+    return r;
+}
+
+template <int K>
+__device__ __forceinline__ QD<K> qd_zero() {
+    QD<K> r;
+    r.v = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) r.t[k] = 0.0;
+    return r;
+}
+
+// CIC weight pair of one dimension: f = s - floor(s) with df = du / h, g = 1 - f.
+template <int K>
+__device__ __forceinline__ QD<K> qd_frac(const QD<K>& u, double s, int i, double ih) {
+    QD<K> f;
+    f.v = s - (double)i;
+#pragma unroll
+    for (int k = 0; k < K; ++k) f.t[k] = u.t[k] * ih;
+    return f;
+}
+
+template <int K>
+__device__ __forceinline__ QD<K> qd_one_minus(const QD<K>& f) {
+    QD<K> g;
+    g.v = 1.0 - f.v;
+#pragma unroll
+    for (int k = 0; k < K; ++k) g.t[k] = -f.t[k];
+    return g;
+}
+
 // ---------------------------------------------------------------- fused step
 struct PartArgs {
     double* st;
     int64_t n, cap;
-    const double* ec;
-    int e_cur, e_next;
+    const double* tau;  // dual step of the current element (NC doubles)
+    const double* map;  // map block (MB_N duals)
     const double* E;
     double* rho;
     int nx, ny, nz;
@@ -136,183 +302,264 @@ struct PartArgs {
     unsigned long long* cnt;
 };
 
-struct Cic {
+struct TiledArgs {
+    const int4* chunks;
+    const uint32_t* nchunks;
+    int tx, ty, nbins;
+};
+
+// LDS copy of the deposit tile, channel-major so that lanes depositing one
+// channel at different nodes fall into different banks.
+constexpr int TILE_NODES = TILE_R * TILE_R * TILE_R;
+constexpr int TILE_CSTRIDE = TILE_NODES + 1;
+constexpr int PART_THREADS = 256;
+
+// wavefront max of the extents (all 64 lanes take part), one atomic per wave
+__device__ __forceinline__ void extent_flush(const PartArgs& a, double e0, double e1, double e2) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        e0 = fmax(e0, __shfl_xor(e0, off, 64));
+        e1 = fmax(e1, __shfl_xor(e1, off, 64));
+        e2 = fmax(e2, __shfl_xor(e2, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(a.cnt + CNT_EXT_X, (unsigned long long)__double_as_longlong(e0));
+        atomicMax(a.cnt + CNT_EXT_Y, (unsigned long long)__double_as_longlong(e1));
+        atomicMax(a.cnt + CNT_EXT_Z, (unsigned long long)__double_as_longlong(e2));
+    }
+}
+
+struct CellPos {
+    double sx, sy, sz;
     int ix, iy, iz;
-    LD fx, fy, fz;
     bool inside;
 };
 
-// Cell and dual fractional offset per dimension: s = (u - lo)/h, cell floor(s),
-// inside iff 0 <= s < n-1 in every dimension.
-__device__ __forceinline__ Cic cic_of(LD x, LD y, LD z, const PartArgs& a) {
-    Cic r;
-    const double sx = (x.v - a.lo0) * a.ih0;
-    const double sy = (y.v - a.lo1) * a.ih1;
-    const double sz = (z.v - a.lo2) * a.ih2;
-    r.inside = (sx >= 0.0) && (sx < (double)(a.nx - 1)) && (sy >= 0.0) && (sy < (double)(a.ny - 1)) &&
-               (sz >= 0.0) && (sz < (double)(a.nz - 1));
-    const double flx = floor(sx), fly = floor(sy), flz = floor(sz);
-    r.ix = (int)flx;
-    r.iy = (int)fly;
-    r.iz = (int)flz;
-    r.fx = LD{sx - flx, x.t * a.ih0};
-    r.fy = LD{sy - fly, y.t * a.ih1};
-    r.fz = LD{sz - flz, z.t * a.ih2};
+// s = (u - lo)/h per dimension, cell floor(s), inside iff 0 <= s < n-1 in every dimension.
+__device__ __forceinline__ CellPos cell_of(double x, double y, double z, const PartArgs& a) {
+    CellPos r;
+    r.sx = (x - a.lo0) * a.ih0;
+    r.sy = (y - a.lo1) * a.ih1;
+    r.sz = (z - a.lo2) * a.ih2;
+    r.inside = (r.sx >= 0.0) && (r.sx < (double)(a.nx - 1)) && (r.sy >= 0.0) && (r.sy < (double)(a.ny - 1)) &&
+               (r.sz >= 0.0) && (r.sz < (double)(a.nz - 1));
+    r.ix = (int)floor(r.sx);
+    r.iy = (int)floor(r.sy);
+    r.iz = (int)floor(r.sz);
     return r;
 }
 
-template <int NC>
-__device__ __forceinline__ void half_map(LD& x, LD& px, LD& y, LD& py, LD& z, const LD& d,
-                                         const double* __restrict__ e, int c) {
-    LD a = ldload(e + (EC_AX + 0) * NC, c), b = ldload(e + (EC_AX + 1) * NC, c);
-    LD cc = ldload(e + (EC_AX + 2) * NC, c), dd = ldload(e + (EC_AX + 3) * NC, c);
-    LD nx = a * x + b * px;
-    LD npx = cc * x + dd * px;
-    x = nx;
-    px = npx;
-    a = ldload(e + (EC_AY + 0) * NC, c);
-    b = ldload(e + (EC_AY + 1) * NC, c);
-    cc = ldload(e + (EC_AY + 2) * NC, c);
-    dd = ldload(e + (EC_AY + 3) * NC, c);
-    LD ny = a * y + b * py;
-    LD npy = cc * y + dd * py;
-    y = ny;
-    py = npy;
-    LD slip = ldload(e + EC_SLIP * NC, c);
-    z = z + slip * d;
-}
-
-template <int NC, int F>
-__global__ __launch_bounds__(256) void k_particles(PartArgs a) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t p = gid / NC;
-    const int c = (int)(gid % NC);
-    const bool valid = p < a.n;
-    double e0 = 0.0, e1 = 0.0, e2 = 0.0;
-    if (valid) {
-        const int64_t cs = a.cap * NC;
-        double* sp = a.st + p * NC;
-        LD x = ldload(sp, c), px = ldload(sp + cs, c), y = ldload(sp + 2 * cs, c);
-        LD py = ldload(sp + 3 * cs, c), z = ldload(sp + 4 * cs, c), d = ldload(sp + 5 * cs, c);
-        const int64_t sxy = (int64_t)a.nx * a.ny;
-        if (F & PF_KICK) {
-            Cic g = cic_of(x, y, z, a);
-            if (g.inside) {
-                const LD wx0 = 1.0 - g.fx, wy0 = 1.0 - g.fy, wz0 = 1.0 - g.fz;
-                const int64_t n0 = ((int64_t)g.iz * a.ny + g.iy) * a.nx + g.ix;
-                LD ex = ldc(0.0), ey = ldc(0.0), ez = ldc(0.0);
+// One particle's share of a fused step, lane q of its quad: gather and kick
+// (PF_KICK), one map block (PF_MAP), then deposit (PF_DEPOSIT) or count
+// (PF_COUNT). With TILED the deposit goes to the workgroup's LDS copy `lr` of
+// the nodes [o, o + TILE_R) when all 8 corners fall inside it, else to global
+// memory.
+template <int NC, int F, bool TILED>
+__device__ __forceinline__ void particle_body(const PartArgs& a, const double* __restrict__ smap,
+                                              const double* __restrict__ stau, int64_t p, int q, double* lr,
+                                              int ox, int oy, int oz, bool use_tile, double& e0, double& e1,
+                                              double& e2) {
+    constexpr int G = Quad<NC>::G, K = Quad<NC>::K;
+    const int64_t cs = a.cap * NC;
+    double* sp = a.st + p * NC;
+    QD<K> x = qd_load<K, G>(sp, q), y = qd_load<K, G>(sp + 2 * cs, q), z = qd_load<K, G>(sp + 4 * cs, q);
+    QD<K> px = qd_load<K, G>(sp + cs, q), py = qd_load<K, G>(sp + 3 * cs, q), d = qd_load<K, G>(sp + 5 * cs, q);
+    const int64_t sxy = (int64_t)a.nx * a.ny;
+    if (F & PF_KICK) {
+        const CellPos g = cell_of(x.v, y.v, z.v, a);
+        if (g.inside) {
+            const QD<K> fx = qd_frac(x, g.sx, g.ix, a.ih0), fy = qd_frac(y, g.sy, g.iy, a.ih1),
+                        fz = qd_frac(z, g.sz, g.iz, a.ih2);
+            const int64_t n0 = ((int64_t)g.iz * a.ny + g.iy) * a.nx + g.ix;
+            QD<K> ex = qd_zero<K>(), ey = qd_zero<K>(), ez = qd_zero<K>();
 #pragma unroll
-                for (int kz = 0; kz < 2; ++kz) {
-                    const LD wz = kz ? g.fz : wz0;
+            for (int kz = 0; kz < 2; ++kz) {
 #pragma unroll
-                    for (int ky = 0; ky < 2; ++ky) {
-                        const LD wyz = (ky ? g.fy : wy0) * wz;
+                for (int ky = 0; ky < 2; ++ky) {
+                    const QD<K> wyz = qd_mul(ky ? fy : qd_one_minus(fy), kz ? fz : qd_one_minus(fz));
 #pragma unroll
-                        for (int kx = 0; kx < 2; ++kx) {
-                            const LD w = (kx ? g.fx : wx0) * wyz;
-                            const double* ep = a.E + (n0 + kx + ky * a.nx + kz * sxy) * 3 * NC;
-                            ex = fmad(w, ldload(ep, c), ex);
-                            ey = fmad(w, ldload(ep + NC, c), ey);
-                            ez = fmad(w, ldload(ep + 2 * NC, c), ez);
-                        }
+                    for (int kx = 0; kx < 2; ++kx) {
+                        const QD<K> w = qd_mul(kx ? fx : qd_one_minus(fx), wyz);
+                        const double* ep = a.E + (n0 + kx + ky * a.nx + kz * sxy) * 3 * NC;
+                        qd_fmad(w, qd_load<K, G>(ep, q), ex);
+                        qd_fmad(w, qd_load<K, G>(ep + NC, q), ey);
+                        qd_fmad(w, qd_load<K, G>(ep + 2 * NC, q), ez);
                     }
                 }
-                const LD tau = ldload(a.ec + (size_t)a.e_cur * EC_N * NC + EC_TAU * NC, c);
-                px = px + tau * (ex * a.kperp);
-                py = py + tau * (ey * a.kperp);
-                d = d + tau * (ez * a.kpar);
+                // keep at most one z-layer of corner loads in flight (register pressure)
+                __builtin_amdgcn_sched_barrier(0);
             }
+            const QD<K> tau = qd_load<K, G>(stau, q);
+            qd_fmad(tau, qd_scale(ex, a.kperp), px);
+            qd_fmad(tau, qd_scale(ey, a.kperp), py);
+            qd_fmad(tau, qd_scale(ez, a.kpar), d);
         }
-        if (F & PF_HALF_CUR) half_map<NC>(x, px, y, py, z, d, a.ec + (size_t)a.e_cur * EC_N * NC, c);
-        if (F & PF_HALF_NEXT) half_map<NC>(x, px, y, py, z, d, a.ec + (size_t)a.e_next * EC_N * NC, c);
-        if (F & (PF_DEPOSIT | PF_COUNT)) {
-            Cic g = cic_of(x, y, z, a);
-            if (g.inside) {
-                if (F & PF_DEPOSIT) {
-                    const LD wx0 = 1.0 - g.fx, wy0 = 1.0 - g.fy, wz0 = 1.0 - g.fz;
-                    const int64_t n0 = ((int64_t)g.iz * a.ny + g.iy) * a.nx + g.ix;
+    }
+    if (F & PF_MAP) {
+        {
+            const double* m = smap + MB_AX * NC;
+            QD<K> nu = qd_mul(qd_load<K, G>(m, q), x), np = qd_mul(qd_load<K, G>(m + 2 * NC, q), x);
+            qd_fmad(qd_load<K, G>(m + NC, q), px, nu);
+            qd_fmad(qd_load<K, G>(m + 3 * NC, q), px, np);
+            x = nu;
+            px = np;
+        }
+        {
+            const double* m = smap + MB_AY * NC;
+            QD<K> nu = qd_mul(qd_load<K, G>(m, q), y), np = qd_mul(qd_load<K, G>(m + 2 * NC, q), y);
+            qd_fmad(qd_load<K, G>(m + NC, q), py, nu);
+            qd_fmad(qd_load<K, G>(m + 3 * NC, q), py, np);
+            y = nu;
+            py = np;
+        }
+        qd_fmad(qd_load<K, G>(smap + MB_SLIP * NC, q), d, z);
+    }
+    if (F & (PF_DEPOSIT | PF_COUNT)) {
+        const CellPos g = cell_of(x.v, y.v, z.v, a);
+        if (g.inside) {
+            if (F & PF_DEPOSIT) {
+                const QD<K> fx = qd_frac(x, g.sx, g.ix, a.ih0), fy = qd_frac(y, g.sy, g.iy, a.ih1),
+                            fz = qd_frac(z, g.sz, g.iz, a.ih2);
+                const int lx = g.ix - ox, ly = g.iy - oy, lz = g.iz - oz;
+                const bool local = TILED && use_tile && lx >= 0 && lx <= TILE_R - 2 && ly >= 0 &&
+                                   ly <= TILE_R - 2 && lz >= 0 && lz <= TILE_R - 2;
+                const int64_t n0 = ((int64_t)g.iz * a.ny + g.iy) * a.nx + g.ix;
+                const int l0 = (lz * TILE_R + ly) * TILE_R + lx;
 #pragma unroll
-                    for (int kz = 0; kz < 2; ++kz) {
-                        const LD wz = kz ? g.fz : wz0;
+                for (int kz = 0; kz < 2; ++kz) {
 #pragma unroll
-                        for (int ky = 0; ky < 2; ++ky) {
-                            const LD wyz = (ky ? g.fy : wy0) * wz;
+                    for (int ky = 0; ky < 2; ++ky) {
+                        const QD<K> wyz = qd_mul(ky ? fy : qd_one_minus(fy), kz ? fz : qd_one_minus(fz));
 #pragma unroll
-                            for (int kx = 0; kx < 2; ++kx) {
-                                const LD w = (kx ? g.fx : wx0) * wyz;
-                                const int64_t node = n0 + kx + ky * a.nx + kz * sxy;
-                                unsafeAtomicAdd(a.rho + node * NC + c, ldchan(w, c) * a.q);
+                        for (int kx = 0; kx < 2; ++kx) {
+                            const QD<K> w = qd_mul(kx ? fx : qd_one_minus(fx), wyz);
+                            if (TILED && local) {
+                                double* l = lr + (q * K) * TILE_CSTRIDE + l0 + kx + ky * TILE_R + kz * TILE_R * TILE_R;
+#pragma unroll
+                                for (int k = 0; k < K; ++k) unsafeAtomicAdd(l + k * TILE_CSTRIDE, qd_chan(w, q, k) * a.q);
+                            } else {
+                                double* r = a.rho + (n0 + kx + ky * a.nx + kz * sxy) * NC + q * K;
+#pragma unroll
+                                for (int k = 0; k < K; ++k) unsafeAtomicAdd(r + k, qd_chan(w, q, k) * a.q);
                             }
                         }
                     }
                 }
-            } else if (c == 0) {
-                atomicAdd(a.cnt + CNT_OUTSIDE, 1ull);
             }
-            e0 = fabs(x.v);
-            e1 = fabs(y.v);
-            e2 = fabs(z.v);
+        } else if (q == 0) {
+            atomicAdd(a.cnt + CNT_OUTSIDE, 1ull);
         }
-        sp[0 * cs + c] = ldchan(x, c);
-        sp[1 * cs + c] = ldchan(px, c);
-        sp[2 * cs + c] = ldchan(y, c);
-        sp[3 * cs + c] = ldchan(py, c);
-        sp[4 * cs + c] = ldchan(z, c);
-        sp[5 * cs + c] = ldchan(d, c);
+        e0 = fmax(e0, fabs(x.v));
+        e1 = fmax(e1, fabs(y.v));
+        e2 = fmax(e2, fabs(z.v));
     }
-    if (F & (PF_DEPOSIT | PF_COUNT)) {
-        // wavefront max of the extents (all 64 lanes take part), one atomic per wave
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            e0 = fmax(e0, __shfl_xor(e0, off, 64));
-            e1 = fmax(e1, __shfl_xor(e1, off, 64));
-            e2 = fmax(e2, __shfl_xor(e2, off, 64));
-        }
-        if ((threadIdx.x & 63) == 0) {
-            atomicMax(a.cnt + CNT_EXT_X, (unsigned long long)__double_as_longlong(e0));
-            atomicMax(a.cnt + CNT_EXT_Y, (unsigned long long)__double_as_longlong(e1));
-            atomicMax(a.cnt + CNT_EXT_Z, (unsigned long long)__double_as_longlong(e2));
-        }
-    }
+    qd_store(sp, x, q);
+    qd_store(sp + cs, px, q);
+    qd_store(sp + 2 * cs, y, q);
+    qd_store(sp + 3 * cs, py, q);
+    qd_store(sp + 4 * cs, z, q);
+    qd_store(sp + 5 * cs, d, q);
 }
 
+// Copy the step's constants (tau and one map block) into LDS.
 template <int NC>
-static hipError_t launch_particles_nc(dpic_ctx* cx, int flags, const PartArgs& a) {
-    const int64_t threads = a.n * NC;
+__device__ __forceinline__ void stage_consts(const PartArgs& a, double* smap, double* stau) {
+    for (int j = threadIdx.x; j < MB_N * NC; j += PART_THREADS) smap[j] = a.map[j];
+    for (int j = threadIdx.x; j < NC; j += PART_THREADS) stau[j] = a.tau[j];
+}
+
+// Storage-order kernel: deposit by global atomics.
+template <int NC, int F>
+__global__ __launch_bounds__(PART_THREADS) void k_particles(PartArgs a) {
+    constexpr int G = Quad<NC>::G;
+    __shared__ __align__(16) double smap[MB_N * NC];
+    __shared__ __align__(16) double stau[NC];
+    stage_consts<NC>(a, smap, stau);
+    __syncthreads();
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = gid / G;
+    const int q = (int)(gid % G);
+    double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+    if (p < a.n) particle_body<NC, F, false>(a, smap, stau, p, q, nullptr, 0, 0, 0, false, e0, e1, e2);
+    if (F & (PF_DEPOSIT | PF_COUNT)) extent_flush(a, e0, e1, e2);
+}
+
+// Tiled kernel: workgroup = one chunk of particles sorted into one grid tile.
+// The deposit accumulates in LDS over the tile's nodes plus a TILE_HALO-cell
+// halo (particles drift between re-sorts) and is flushed once: only nodes
+// that received charge issue global atomics.
+template <int NC, int F>
+__global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, TiledArgs t) {
+    constexpr int G = Quad<NC>::G;
+    constexpr int LDSN = (F & PF_DEPOSIT) ? TILE_CSTRIDE * NC : 1;
+    __shared__ __align__(16) double lr[LDSN];
+    __shared__ __align__(16) double smap[MB_N * NC];
+    __shared__ __align__(16) double stau[NC];
+    if (blockIdx.x >= *t.nchunks) return;  // uniform per workgroup
+    const int4 ck = t.chunks[blockIdx.x];
+    const bool use_tile = ck.x < t.nbins - 1;
+    const int tx = ck.x % t.tx, ty = (ck.x / t.tx) % t.ty, tz = ck.x / (t.tx * t.ty);
+    const int ox = tx * TILE_EDGE - TILE_HALO, oy = ty * TILE_EDGE - TILE_HALO, oz = tz * TILE_EDGE - TILE_HALO;
+    stage_consts<NC>(a, smap, stau);
+    if (F & PF_DEPOSIT)
+        for (int j = threadIdx.x; j < LDSN; j += PART_THREADS) lr[j] = 0.0;
+    __syncthreads();
+    const int q = threadIdx.x % G;
+    double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+#pragma unroll 1
+    for (int i = threadIdx.x / G; i < ck.z; i += PART_THREADS / G)
+        particle_body<NC, F, true>(a, smap, stau, (int64_t)ck.y + i, q, lr, ox, oy, oz, use_tile, e0, e1, e2);
+    if (F & PF_DEPOSIT) {
+        __syncthreads();
+        for (int j = threadIdx.x; j < TILE_NODES * NC; j += PART_THREADS) {
+            const int ch = j / TILE_NODES, node = j - ch * TILE_NODES;
+            const double v = lr[ch * TILE_CSTRIDE + node];
+            if (v != 0.0) {
+                const int lx = node % TILE_R, ly = (node / TILE_R) % TILE_R, lz = node / (TILE_R * TILE_R);
+                const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+                if (gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz)
+                    unsafeAtomicAdd(a.rho + (((int64_t)gz * a.ny + gy) * a.nx + gx) * NC + ch, v);
+            }
+        }
+    }
+    if (F & (PF_DEPOSIT | PF_COUNT)) extent_flush(a, e0, e1, e2);
+}
+
+template <int NC, bool TL>
+static hipError_t launch_particles_nc(dpic_ctx* cx, int flags, const PartArgs& a, const TiledArgs& t,
+                                      unsigned tgrid) {
+    const int64_t threads = a.n * Quad<NC>::G;
     if (threads == 0) return hipSuccess;
-    dim3 block(256), grid((unsigned)((threads + 255) / 256));
+    dim3 block(PART_THREADS), grid(TL ? tgrid : (unsigned)((threads + PART_THREADS - 1) / PART_THREADS));
     hipStream_t s = cx->stream;
+#define DPIC_PART_CASE(FL)                                                              \
+    case FL:                                                                            \
+        if (TL)                                                                         \
+            hipLaunchKernelGGL((k_particles_tiled<NC, FL>), grid, block, 0, s, a, t);   \
+        else                                                                            \
+            hipLaunchKernelGGL((k_particles<NC, FL>), grid, block, 0, s, a);            \
+        break;
     switch (flags) {
-        case PF_HALF_NEXT | PF_DEPOSIT:
-            hipLaunchKernelGGL((k_particles<NC, PF_HALF_NEXT | PF_DEPOSIT>), grid, block, 0, s, a); break;
-        case PF_KICK | PF_HALF_CUR | PF_HALF_NEXT | PF_DEPOSIT:
-            hipLaunchKernelGGL((k_particles<NC, PF_KICK | PF_HALF_CUR | PF_HALF_NEXT | PF_DEPOSIT>), grid, block, 0, s, a); break;
-        case PF_KICK | PF_HALF_CUR:
-            hipLaunchKernelGGL((k_particles<NC, PF_KICK | PF_HALF_CUR>), grid, block, 0, s, a); break;
-        case PF_HALF_NEXT | PF_COUNT:
-            hipLaunchKernelGGL((k_particles<NC, PF_HALF_NEXT | PF_COUNT>), grid, block, 0, s, a); break;
-        case PF_HALF_CUR | PF_HALF_NEXT | PF_COUNT:
-            hipLaunchKernelGGL((k_particles<NC, PF_HALF_CUR | PF_HALF_NEXT | PF_COUNT>), grid, block, 0, s, a); break;
-        case PF_HALF_CUR:
-            hipLaunchKernelGGL((k_particles<NC, PF_HALF_CUR>), grid, block, 0, s, a); break;
-        case PF_DEPOSIT:
-            hipLaunchKernelGGL((k_particles<NC, PF_DEPOSIT>), grid, block, 0, s, a); break;
-        case PF_KICK:
-            hipLaunchKernelGGL((k_particles<NC, PF_KICK>), grid, block, 0, s, a); break;
+        DPIC_PART_CASE(PF_MAP | PF_DEPOSIT)
+        DPIC_PART_CASE(PF_KICK | PF_MAP | PF_DEPOSIT)
+        DPIC_PART_CASE(PF_KICK | PF_MAP)
+        DPIC_PART_CASE(PF_MAP | PF_COUNT)
+        DPIC_PART_CASE(PF_MAP)
+        DPIC_PART_CASE(PF_DEPOSIT)
         default:
             return hipErrorInvalidValue;
     }
+#undef DPIC_PART_CASE
     return hipGetLastError();
 }
 
-hipError_t launch_particles(dpic_ctx* cx, int flags, int e_cur, int e_next) {
+hipError_t launch_particles(dpic_ctx* cx, int flags, int e_tau, const double* map, bool tiled) {
     PartArgs a;
     a.st = cx->ws.st;
     a.n = cx->n;
     a.cap = cx->dims.n_particles;
-    a.ec = cx->ws.ec;
-    a.e_cur = e_cur;
-    a.e_next = e_next;
+    a.tau = cx->ws.ec + (size_t)e_tau * EC_N * cx->NC + EC_TAU * cx->NC;
+    a.map = map ? map : cx->ws.ec;
     a.E = cx->ws.E;
     a.rho = cx->ws.rho;
     a.nx = cx->dims.nx;
@@ -328,11 +575,27 @@ hipError_t launch_particles(dpic_ctx* cx, int flags, int e_cur, int e_next) {
     a.kpar = cx->kpar;
     a.q = cx->n > 0 ? cx->bunch_charge / (double)cx->n : 0.0;
     a.cnt = cx->ws.counters;
-    switch (cx->NC) {
-        case 1: return launch_particles_nc<1>(cx, flags, a);
-        case 8: return launch_particles_nc<8>(cx, flags, a);
-        default: return launch_particles_nc<16>(cx, flags, a);
+    TiledArgs t{};
+    unsigned tgrid = 0;
+    if (tiled) {
+        int tiles[3], nbins;
+        if (!cx->chunks_valid || !sort_geometry(cx, tiles, &nbins)) return hipErrorInvalidValue;
+        t.chunks = cx->ws.chunks;
+        t.nchunks = cx->ws.nchunks;
+        t.tx = tiles[0];
+        t.ty = tiles[1];
+        t.nbins = nbins;
+        tgrid = (unsigned)(nbins + (cx->n + TILE_CHUNK - 1) / TILE_CHUNK);
     }
+    switch (cx->NC) {
+        case 1: return tiled ? launch_particles_nc<1, true>(cx, flags, a, t, tgrid) : launch_particles_nc<1, false>(cx, flags, a, t, tgrid);
+        case 8: return tiled ? launch_particles_nc<8, true>(cx, flags, a, t, tgrid) : launch_particles_nc<8, false>(cx, flags, a, t, tgrid);
+        default: return tiled ? launch_particles_nc<16, true>(cx, flags, a, t, tgrid) : launch_particles_nc<16, false>(cx, flags, a, t, tgrid);
+    }
+}
+
+const double* element_map_block(const dpic_ctx* cx, int e, int slot) {
+    return cx->ws.ec + (size_t)e * EC_N * cx->NC + (size_t)slot * cx->NC;
 }
 
 // ---------------------------------------------------------------- read-back

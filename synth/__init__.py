@@ -187,12 +187,14 @@ class Workload:
         return dataclasses.replace(self, **kw)
 
 
-# Boxes are fixed per run and symmetric about the origin. They were chosen
-# to contain every particle at every step of the nominal run (checked by the
-# out-of-box counters, which the tests require to stay at zero) with margin
-# for the +-5% parameter perturbations used elsewhere.
+# Boxes are fixed per run and symmetric about the origin. They contain every
+# particle at every step of the nominal run (the out-of-box counters stay at
+# zero): synth/box_prepass.py iterates value-only runs, box <- 1.1 x extent.
+# c1 settles at extents (3.81, 6.63, 7.61) mm, recorded with extra margin for
+# the +-5% parameter perturbations used elsewhere; c2 (strong space charge
+# lengthens the bunch) settles at half-widths (13.87, 15.86, 29.62) mm.
 C1_HALF = (4.6e-3, 8.0e-3, 9.2e-3)
-C2_HALF = (14.0e-3, 14.0e-3, 12.0e-3)
+C2_HALF = (14.0e-3, 16.0e-3, 30.0e-3)
 
 
 def c1(ntan: int = 7, **kw) -> Workload:

@@ -15,7 +15,9 @@ VALUE_RTOL = 1e-10
 DERIV_RTOL = 1e-9
 
 
-def make_sim(w, capacity=None, sort_every=0, n_particles=None, xi=None):
+def make_sim(w, capacity=None, sort_every=None, n_particles=None, xi=None):
+    """sort_every None keeps the library default (tiled deposit, re-sort every
+    20 steps); 0 selects the storage-order kernel with global atomics."""
     from paper_2511_21839_amd import dpic
 
     sim = dpic.Simulation(capacity or w.n_particles, w.ntan, w.grid)
@@ -25,7 +27,7 @@ def make_sim(w, capacity=None, sort_every=0, n_particles=None, xi=None):
     sim.set_lattice(L.kind, L.n_steps, L.L, L.k, L.L_param, L.k_param, L.n_periods)
     sim.set_params(w.params, w.param_seed())
     sim.init_beam(w.xi() if xi is None else xi, w.sigma, w.sigma_seed())
-    if sort_every:
+    if sort_every is not None:
         sim.set_option(dpic.OPT_SORT_EVERY, sort_every)
     return sim
 

@@ -126,11 +126,21 @@ def test_zero_current_run_matches_oracle():
     np.testing.assert_allclose(ext, ref.max_extent, rtol=1e-10)
 
 
-@pytest.mark.parametrize("sort_every", [0, 3])
+@pytest.mark.parametrize("sort_every", [0, 1, 3, 50])
 def test_tiny_space_charge_run_matches_oracle(sort_every):
     w = synth.tiny(n_particles=3001, grid=16, steps_per_element=4)
     w = w.with_(bunch_charge_C=w.bunch_charge_C * 10)
     sim = make_sim(w, sort_every=sort_every)
+    sim.step(w.total_steps())
+    _compare_run(w, sim, _oracle(w))
+
+
+def test_tiled_deposit_with_drift_beyond_the_halo():
+    # large momentum spread and a single sort: many particles leave their
+    # tile's LDS window and take the global-atomic path of the tiled kernel
+    w = synth.tiny(n_particles=3000, grid=32, steps_per_element=4)
+    w = w.with_(sigma=(1e-3, 6e-3, 1e-3, 6e-3, 2e-3, 1e-3), bunch_charge_C=w.bunch_charge_C * 5)
+    sim = make_sim(w, sort_every=1000)
     sim.step(w.total_steps())
     _compare_run(w, sim, _oracle(w))
 
