@@ -45,7 +45,7 @@ constexpr int NUM_TILE_BINS_MAX = 4096;
 constexpr int TILE_EDGE = 4;                             // cells per tile edge
 constexpr int TILE_HALO = 1;                             // drift allowance (cells) of the LDS deposit
 constexpr int TILE_R = TILE_EDGE + 2 * TILE_HALO + 1;    // LDS nodes per dimension
-constexpr int TILE_CHUNK = 512;                          // particles per tiled workgroup
+constexpr int TILE_CHUNK = 1024;                         // particles per tiled workgroup
 constexpr int SORT_PB = 1024;                            // particles per sort block
 
 size_t workspace_layout(const dpic_dims& d, char* base, Workspace* ws);

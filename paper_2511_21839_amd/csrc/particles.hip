@@ -308,10 +308,12 @@ struct TiledArgs {
     int tx, ty, nbins;
 };
 
-// LDS copy of the deposit tile, channel-major so that lanes depositing one
-// channel at different nodes fall into different banks.
+// LDS copy of the deposit tile, channel-major. The channel stride is 1 mod 16
+// doubles, so channel c of node n sits in bank pair (c + n) mod 16: the lanes
+// of a quad (channels k, k+K, ..) and particles at different nodes spread
+// over the banks.
 constexpr int TILE_NODES = TILE_R * TILE_R * TILE_R;
-constexpr int TILE_CSTRIDE = TILE_NODES + 1;
+constexpr int TILE_CSTRIDE = ((TILE_NODES + 15) / 16) * 16 + 1;
 constexpr int PART_THREADS = 256;
 
 // wavefront max of the extents (all 64 lanes take part), one atomic per wave
@@ -354,16 +356,59 @@ __device__ __forceinline__ CellPos cell_of(double x, double y, double z, const P
 // (PF_COUNT). With TILED the deposit goes to the workgroup's LDS copy `lr` of
 // the nodes [o, o + TILE_R) when all 8 corners fall inside it, else to global
 // memory.
+// A particle's six coordinates as this lane's raw channels (no broadcast
+// yet), so that the loads of the next particle can be issued before the
+// current one is processed.
+template <int K>
+struct RawState {
+    double r[6][K];
+};
+
+template <int NC>
+__device__ __forceinline__ RawState<Quad<NC>::K> load_raw(const PartArgs& a, int64_t p, int q) {
+    constexpr int K = Quad<NC>::K;
+    RawState<K> s;
+    const int64_t cs = a.cap * NC;
+    const double* sp = a.st + p * NC + q * K;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        if constexpr (K == 1) {
+            s.r[j][0] = sp[j * cs];
+        } else {
+#pragma unroll
+            for (int i = 0; i < K / 2; ++i) {
+                const double2 w = reinterpret_cast<const double2*>(sp + j * cs)[i];
+                s.r[j][2 * i] = w.x;
+                s.r[j][2 * i + 1] = w.y;
+            }
+        }
+    }
+    return s;
+}
+
+template <int K, int G>
+__device__ __forceinline__ QD<K> raw_to_qd(const double* r, int q) {
+    QD<K> x;
+#pragma unroll
+    for (int k = 0; k < K; ++k) x.t[k] = r[k];
+    if constexpr (G == 1)
+        x.v = x.t[0];
+    else
+        x.v = quad_bcast(x.t[0]);
+    if (q == 0) x.t[0] = 0.0;
+    return x;
+}
+
 template <int NC, int F, bool TILED>
 __device__ __forceinline__ void particle_body(const PartArgs& a, const double* __restrict__ smap,
-                                              const double* __restrict__ stau, int64_t p, int q, double* lr,
-                                              int ox, int oy, int oz, bool use_tile, double& e0, double& e1,
-                                              double& e2) {
+                                              const double* __restrict__ stau, int64_t p, int q,
+                                              const RawState<Quad<NC>::K>& raw, double* lr, int ox, int oy,
+                                              int oz, bool use_tile, double& e0, double& e1, double& e2) {
     constexpr int G = Quad<NC>::G, K = Quad<NC>::K;
     const int64_t cs = a.cap * NC;
     double* sp = a.st + p * NC;
-    QD<K> x = qd_load<K, G>(sp, q), y = qd_load<K, G>(sp + 2 * cs, q), z = qd_load<K, G>(sp + 4 * cs, q);
-    QD<K> px = qd_load<K, G>(sp + cs, q), py = qd_load<K, G>(sp + 3 * cs, q), d = qd_load<K, G>(sp + 5 * cs, q);
+    QD<K> x = raw_to_qd<K, G>(raw.r[0], q), px = raw_to_qd<K, G>(raw.r[1], q), y = raw_to_qd<K, G>(raw.r[2], q);
+    QD<K> py = raw_to_qd<K, G>(raw.r[3], q), z = raw_to_qd<K, G>(raw.r[4], q), d = raw_to_qd<K, G>(raw.r[5], q);
     const int64_t sxy = (int64_t)a.nx * a.ny;
     if (F & PF_KICK) {
         const CellPos g = cell_of(x.v, y.v, z.v, a);
@@ -386,8 +431,6 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const double* _
                         qd_fmad(w, qd_load<K, G>(ep + 2 * NC, q), ez);
                     }
                 }
-                // keep at most one z-layer of corner loads in flight (register pressure)
-                __builtin_amdgcn_sched_barrier(0);
             }
             const QD<K> tau = qd_load<K, G>(stau, q);
             qd_fmad(tau, qd_scale(ex, a.kperp), px);
@@ -480,7 +523,10 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles(PartArgs a) {
     const int64_t p = gid / G;
     const int q = (int)(gid % G);
     double e0 = 0.0, e1 = 0.0, e2 = 0.0;
-    if (p < a.n) particle_body<NC, F, false>(a, smap, stau, p, q, nullptr, 0, 0, 0, false, e0, e1, e2);
+    if (p < a.n) {
+        const RawState<Quad<NC>::K> raw = load_raw<NC>(a, p, q);
+        particle_body<NC, F, false>(a, smap, stau, p, q, raw, nullptr, 0, 0, 0, false, e0, e1, e2);
+    }
     if (F & (PF_DEPOSIT | PF_COUNT)) extent_flush(a, e0, e1, e2);
 }
 
@@ -506,13 +552,28 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
     __syncthreads();
     const int q = threadIdx.x % G;
     double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+    // software pipeline: the next particle's state is loaded while the
+    // current one is gathered, pushed and deposited
+    constexpr int STRIDE = PART_THREADS / G;
+    int i = threadIdx.x / G;
+    RawState<Quad<NC>::K> next;
+    if (i < ck.z) next = load_raw<NC>(a, (int64_t)ck.y + i, q);
 #pragma unroll 1
-    for (int i = threadIdx.x / G; i < ck.z; i += PART_THREADS / G)
-        particle_body<NC, F, true>(a, smap, stau, (int64_t)ck.y + i, q, lr, ox, oy, oz, use_tile, e0, e1, e2);
+    for (; i < ck.z; i += STRIDE) {
+        const RawState<Quad<NC>::K> cur = next;
+        if (i + STRIDE < ck.z) next = load_raw<NC>(a, (int64_t)ck.y + i + STRIDE, q);
+        particle_body<NC, F, true>(a, smap, stau, (int64_t)ck.y + i, q, cur, lr, ox, oy, oz, use_tile, e0, e1, e2);
+    }
     if (F & PF_DEPOSIT) {
         __syncthreads();
+        // node-major walk (NC consecutive lanes write one node's channels),
+        // started at a chunk-dependent node so that chunks of the same tile
+        // flushing at the same time hit different addresses
+        const int rot = (int)((blockIdx.x * 61u) % TILE_NODES);
         for (int j = threadIdx.x; j < TILE_NODES * NC; j += PART_THREADS) {
-            const int ch = j / TILE_NODES, node = j - ch * TILE_NODES;
+            const int ch = j % NC;
+            int node = j / NC + rot;
+            node -= node >= TILE_NODES ? TILE_NODES : 0;
             const double v = lr[ch * TILE_CSTRIDE + node];
             if (v != 0.0) {
                 const int lx = node % TILE_R, ly = (node / TILE_R) % TILE_R, lz = node / (TILE_R * TILE_R);
