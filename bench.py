@@ -49,6 +49,29 @@ def _cpu_baseline(w, xi, steps: int):
     }
 
 
+PROFILE_RECORD = os.path.join(ROOT, "profiles", "k_particles_tiled_c2.md")
+
+
+def _recorded_traffic():
+    """HBM bytes per launch of the particle kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when
+    the kernel's sources changed since the counters were taken."""
+    import hashlib
+    import re
+
+    try:
+        text = open(PROFILE_RECORD).read()
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+        h = hashlib.sha256()
+        for p in rec["sources"]:
+            h.update(open(os.path.join(ROOT, p), "rb").read())
+        if h.hexdigest() != rec["source_sha256"]:
+            return None
+        return float(rec["traffic_bytes_per_launch"])
+    except (OSError, AttributeError, KeyError, ValueError):
+        return None
+
+
 def _copy_calibration(mib: int) -> int:
     """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give the
     factor that turns counter KiB into HBM bytes for the same profiler setup."""
@@ -157,7 +180,7 @@ def main(argv=None):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": _recorded_traffic(),
             "kernel": "k_particles (gather, kick, two half-maps, deposit)",
             "avg_launch_us": part_avg_s * 1e6,
         },

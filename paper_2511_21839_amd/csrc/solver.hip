@@ -33,6 +33,7 @@ namespace dpic {
 
 constexpr int FFT_THREADS = 256;
 constexpr int TILE = 1024;
+constexpr int CTILE = 1024;  // tile of the column passes (passes 2-4)
 
 // ---------------------------------------------------------------- FFT core
 template <int M, bool INV>
@@ -259,7 +260,7 @@ struct ColArgs {
 template <int M, int MODE>  // 0: forward, 1: forward * Ghat * inverse, 2: inverse
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_cols(const double2* __restrict__ in, double2* __restrict__ out,
                                                           ColArgs a, const double2* __restrict__ tw) {
-    __shared__ double s0r[TILE], s0i[TILE], s1r[TILE], s1i[TILE], twr[M], twi[M];
+    __shared__ double s0r[CTILE], s0i[CTILE], s1r[CTILE], s1i[CTILE], twr[M], twi[M];
     load_twiddles<M>(twr, twi, tw);
     const int B = 1 << a.lb;
     const int tiles = a.W >> a.lb;
@@ -306,7 +307,7 @@ template <int MODE>
 static hipError_t launch_cols(int M, int n_outer, const ColArgs& a0, const double2* in, double2* out,
                               const double2* tw, hipStream_t s) {
     ColArgs a = a0;
-    int B = TILE / M;
+    int B = CTILE / M;
     if (B > a.W) B = a.W;
     a.lb = 31 - __builtin_clz((unsigned)B);
     const unsigned blocks = (unsigned)n_outer * (unsigned)(a.W / B);
