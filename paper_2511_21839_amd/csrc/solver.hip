@@ -33,7 +33,6 @@ namespace dpic {
 
 constexpr int FFT_THREADS = 256;
 constexpr int TILE = 1024;
-constexpr int CTILE = 1024;  // tile of the column passes (passes 2-4)
 
 // ---------------------------------------------------------------- FFT core
 template <int M, bool INV>
@@ -245,7 +244,6 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_inv(const double2* __r
 // ---------------------------------------------------------------- passes 2-4
 struct ColArgs {
     int W;            // columns per outer index
-    int lb;           // log2 of columns per tile
     int64_t bstride;  // element stride between neighbouring columns
     int64_t in_outer, in_stride;
     int n_in;         // nonzero input rows
@@ -257,65 +255,216 @@ struct ColArgs {
     int ncc, gnx1, gny1, Mx, My;
 };
 
-template <int M, int MODE>  // 0: forward, 1: forward * Ghat * inverse, 2: inverse
-__global__ __launch_bounds__(FFT_THREADS) void k_fft_cols(const double2* __restrict__ in, double2* __restrict__ out,
-                                                          ColArgs a, const double2* __restrict__ tw) {
-    __shared__ double s0r[CTILE], s0i[CTILE], s1r[CTILE], s1i[CTILE], twr[M], twi[M];
-    load_twiddles<M>(twr, twi, tw);
-    const int B = 1 << a.lb;
-    const int tiles = a.W >> a.lb;
-    const int outer = blockIdx.x / tiles;
-    const int w0 = (blockIdx.x - outer * tiles) << a.lb;
-    const double2* src = in + (int64_t)outer * a.in_outer + (int64_t)w0 * a.bstride;
-    for (int t = threadIdx.x; t < (M << a.lb); t += FFT_THREADS) {
-        const int r = t >> a.lb;
-        const int b = t & (B - 1);
-        double2 v = make_double2(0.0, 0.0);
-        if (r < a.n_in) v = src[(int64_t)r * a.in_stride + (int64_t)b * a.bstride];
-        s0r[t] = v.x;
-        s0i[t] = v.y;
+// Column transforms (passes 2-4 and the Green's function) as two register
+// stages: M = R1 R2, n = R2 n1 + n2, k = k1 + R1 k2,
+//   X[k1 + R1 k2] = sum_n2 W_M^(n2 k1) W_R2^(n2 k2) sum_n1 x[R2 n1 + n2] W_R1^(n1 k1).
+// A thread owns one column b and one n2 (stage A, an R1-point DFT on values
+// loaded straight from global memory), then R1/R2 groups k1 (stage B, R2-point
+// DFTs) after one LDS exchange. The inverse runs the same split transposed:
+// per k1 over k2 first (the groups a thread holds after a forward), then per
+// n2 over k1 after one exchange, x[n2 + R2 n1] = sum_k1 W_R1^(-n1 k1) W_M^(-n2 k1)
+// sum_k2 X[k1 + R1 k2] W_R2^(-n2 k2). Forward-Ghat-inverse therefore needs
+// two exchanges and no global round trip in between.
+template <int M>
+struct ColCfg {
+    static constexpr int R1 = M >= 128 ? 16 : (M >= 32 ? 8 : 4);
+    static constexpr int R2 = M / R1;
+    static constexpr int NG = R1 / R2;    // stage-B groups per thread
+    static constexpr int BC = 2048 / M;   // columns per block
+    static constexpr int NT = BC * R2;    // threads per block
+};
+
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
+constexpr int bitrev(int i, int bits) {
+    int r = 0;
+    for (int b = 0; b < bits; ++b) r = (r << 1) | ((i >> b) & 1);
+    return r;
+}
+
+// R-point DFT in registers (radix-2 decimation in time, bit-reversed input
+// order, natural output order); W_R^j = tw[j M / R], conjugated for INV.
+template <int M, int R, bool INV>
+__device__ __forceinline__ void dft_reg(double (&re)[R], double (&im)[R], const double* twr, const double* twi) {
+    constexpr int LOG = ilog2c(R);
+    double ar[R], ai[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        ar[bitrev(i, LOG)] = re[i];
+        ai[bitrev(i, LOG)] = im[i];
     }
-    __syncthreads();
-    double *sr = s0r, *si = s0i, *dr = s1r, *di = s1i;
-    fft_tile<M, MODE == 2>(sr, si, dr, di, a.lb, twr, twi);
-    if (MODE == 1) {
-        const int ky = outer;
-        const int gy = ky <= a.My - ky ? ky : a.My - ky;
-        for (int t = threadIdx.x; t < (M << a.lb); t += FFT_THREADS) {
-            const int kz = t >> a.lb;
-            const int b = t & (B - 1);
-            const int kx = (w0 + b) / a.ncc;
-            const int gz = kz <= M - kz ? kz : M - kz;
-            const int gx = kx <= a.Mx - kx ? kx : a.Mx - kx;
-            const double g = a.ghat[((int64_t)gz * a.gny1 + gy) * a.gnx1 + gx];
-            sr[t] *= g;
-            si[t] *= g;
+#pragma unroll
+    for (int len = 2; len <= R; len <<= 1) {
+        const int half = len >> 1;
+#pragma unroll
+        for (int s = 0; s < R; s += len) {
+#pragma unroll
+            for (int j = 0; j < half; ++j) {
+                double vr = ar[s + j + half], vi = ai[s + j + half];
+                if (j != 0) {
+                    const int m = j * (M / len);
+                    const double wr = twr[m], wi = INV ? -twi[m] : twi[m];
+                    const double tr = vr * wr - vi * wi;
+                    vi = vr * wi + vi * wr;
+                    vr = tr;
+                }
+                ar[s + j + half] = ar[s + j] - vr;
+                ai[s + j + half] = ai[s + j] - vi;
+                ar[s + j] += vr;
+                ai[s + j] += vi;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        re[i] = ar[i];
+        im[i] = ai[i];
+    }
+}
+
+// multiply by W_M^(e) (conjugate for INV), e taken mod M
+template <int M, bool INV>
+__device__ __forceinline__ void twiddle(double& re, double& im, int e, const double* twr, const double* twi) {
+    const int m = e & (M - 1);
+    const double wr = twr[m], wi = INV ? -twi[m] : twi[m];
+    const double t = re * wr - im * wi;
+    im = re * wi + im * wr;
+    re = t;
+}
+
+template <int M, int MODE>  // 0: forward, 1: forward * Ghat * inverse, 2: inverse
+__global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_cols(const double2* __restrict__ in, double2* __restrict__ out,
+                                                            ColArgs a, const double2* __restrict__ tw) {
+    using C = ColCfg<M>;
+    constexpr int R1 = C::R1, R2 = C::R2, NG = C::NG, BC = C::BC;
+    __shared__ double er[M * BC], ei[M * BC], twr[M], twi[M];
+    for (int m = threadIdx.x; m < M; m += C::NT) {
+        const double2 w = tw[m];
+        twr[m] = w.x;
+        twi[m] = w.y;
+    }
+    const int b = threadIdx.x % BC;
+    const int r = threadIdx.x / BC;  // n2 in stage A / inverse stage 2; group base in the others
+    const int tiles = (a.W + BC - 1) / BC;
+    const int outer = blockIdx.x / tiles;
+    const int col = (blockIdx.x - outer * tiles) * BC + b;
+    const bool valid = col < a.W;
+    const double2* src = in + (int64_t)outer * a.in_outer + (int64_t)col * a.bstride;
+    double2* dst = out + (int64_t)outer * a.out_outer + (int64_t)col * a.bstride;
+    double hr[NG][R2], hi[NG][R2];  // groups k1 = r + R2 g, values over k2
+    if (MODE != 2) {
+        double xr[R1], xi[R1];
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) {
+            const int row = R2 * n1 + r;
+            double2 v = make_double2(0.0, 0.0);
+            if (valid && row < a.n_in) v = src[(int64_t)row * a.in_stride];
+            xr[n1] = v.x;
+            xi[n1] = v.y;
+        }
+        __syncthreads();  // twiddle table
+        dft_reg<M, R1, false>(xr, xi, twr, twi);
+#pragma unroll
+        for (int k1 = 1; k1 < R1; ++k1) twiddle<M, false>(xr[k1], xi[k1], r * k1, twr, twi);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            er[(k1 * R2 + r) * BC + b] = xr[k1];
+            ei[(k1 * R2 + r) * BC + b] = xi[k1];
         }
         __syncthreads();
-        fft_tile<M, true>(sr, si, dr, di, a.lb, twr, twi);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            const int k1 = r + R2 * g;
+#pragma unroll
+            for (int n2 = 0; n2 < R2; ++n2) {
+                hr[g][n2] = er[(k1 * R2 + n2) * BC + b];
+                hi[g][n2] = ei[(k1 * R2 + n2) * BC + b];
+            }
+            dft_reg<M, R2, false>(hr[g], hi[g], twr, twi);
+        }
+        if (MODE == 0) {
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2) {
+                    const int t = (r + R2 * g + R1 * k2 + a.out_shift) & (M - 1);
+                    if (valid && t < a.n_out) dst[(int64_t)t * a.out_stride] = make_double2(hr[g][k2], hi[g][k2]);
+                }
+            }
+            return;
+        }
+        // Ghat: outer index is ky, column is (kx, channel), row is kz
+        const int ky = outer, kx = col / a.ncc;
+        const int gy = ky <= a.My - ky ? ky : a.My - ky;
+        const int gx = kx <= a.Mx - kx ? kx : a.Mx - kx;
+        const double* grow = a.ghat + (int64_t)gy * a.gnx1 + gx;
+        const int64_t gzs = (int64_t)a.gny1 * a.gnx1;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) {
+                const int kz = r + R2 * g + R1 * k2;
+                const int gz = kz <= M - kz ? kz : M - kz;
+                const double gv = valid ? grow[gz * gzs] : 0.0;
+                hr[g][k2] *= gv;
+                hi[g][k2] *= gv;
+            }
+        }
+        __syncthreads();  // every stage-B read of the exchange buffer is done
+    } else {
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) {
+                const int row = r + R2 * g + R1 * k2;
+                double2 v = make_double2(0.0, 0.0);
+                if (valid && row < a.n_in) v = src[(int64_t)row * a.in_stride];
+                hr[g][k2] = v.x;
+                hi[g][k2] = v.y;
+            }
+        }
+        __syncthreads();  // twiddle table
     }
-    double2* dst = out + (int64_t)outer * a.out_outer + (int64_t)w0 * a.bstride;
-    for (int t = threadIdx.x; t < (a.n_out << a.lb); t += FFT_THREADS) {
-        const int r = t >> a.lb;
-        const int b = t & (B - 1);
-        const int rs = (r - a.out_shift + M) & (M - 1);
-        dst[(int64_t)r * a.out_stride + (int64_t)b * a.bstride] = make_double2(sr[(rs << a.lb) + b], si[(rs << a.lb) + b]);
+    // inverse: per k1 over k2, twiddle, exchange, per n2 over k1
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        const int k1 = r + R2 * g;
+        dft_reg<M, R2, true>(hr[g], hi[g], twr, twi);
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) {
+            double zr = hr[g][n2], zi = hi[g][n2];
+            twiddle<M, true>(zr, zi, n2 * k1, twr, twi);
+            er[(n2 * R1 + k1) * BC + b] = zr;
+            ei[(n2 * R1 + k1) * BC + b] = zi;
+        }
+    }
+    __syncthreads();
+    double xr[R1], xi[R1];
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+        xr[k1] = er[(r * R1 + k1) * BC + b];
+        xi[k1] = ei[(r * R1 + k1) * BC + b];
+    }
+    dft_reg<M, R1, true>(xr, xi, twr, twi);
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) {
+        const int t = (r + R2 * n1 + a.out_shift) & (M - 1);
+        if (valid && t < a.n_out) dst[(int64_t)t * a.out_stride] = make_double2(xr[n1], xi[n1]);
     }
 }
 
 template <int MODE>
-static hipError_t launch_cols(int M, int n_outer, const ColArgs& a0, const double2* in, double2* out,
+static hipError_t launch_cols(int M, int n_outer, const ColArgs& a, const double2* in, double2* out,
                               const double2* tw, hipStream_t s) {
-    ColArgs a = a0;
-    int B = CTILE / M;
-    if (B > a.W) B = a.W;
-    a.lb = 31 - __builtin_clz((unsigned)B);
-    const unsigned blocks = (unsigned)n_outer * (unsigned)(a.W / B);
     switch (M) {
-        case 16: hipLaunchKernelGGL((k_fft_cols<16, MODE>), dim3(blocks), dim3(FFT_THREADS), 0, s, in, out, a, tw); break;
-        case 32: hipLaunchKernelGGL((k_fft_cols<32, MODE>), dim3(blocks), dim3(FFT_THREADS), 0, s, in, out, a, tw); break;
-        case 64: hipLaunchKernelGGL((k_fft_cols<64, MODE>), dim3(blocks), dim3(FFT_THREADS), 0, s, in, out, a, tw); break;
-        case 128: hipLaunchKernelGGL((k_fft_cols<128, MODE>), dim3(blocks), dim3(FFT_THREADS), 0, s, in, out, a, tw); break;
+#define DPIC_COLS(MM)                                                                                 \
+    case MM: {                                                                                        \
+        using C = ColCfg<MM>;                                                                         \
+        const unsigned blocks = (unsigned)n_outer * (unsigned)((a.W + C::BC - 1) / C::BC);            \
+        hipLaunchKernelGGL((k_fft_cols<MM, MODE>), dim3(blocks), dim3(C::NT), 0, s, in, out, a, tw);  \
+        break;                                                                                        \
+    }
+        DPIC_COLS(16) DPIC_COLS(32) DPIC_COLS(64) DPIC_COLS(128)
+#undef DPIC_COLS
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
