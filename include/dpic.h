@@ -206,6 +206,29 @@ int dpic_set_option(dpic_ctx* ctx, int option, int64_t value);
 #define DPIC_N_STAGE_TIMERS 4
 int dpic_stage_times(dpic_ctx* ctx, double* ms, int64_t* launches);
 
+/*
+ * Reverse mode: gradients of J = w0 eps_x + w1 eps_y + w2 eps_z (raw
+ * emittances of the final beam, Sec. 4) with respect to the parameters of
+ * dpic_set_params (at most 15) and the six initial beam sizes, at a cost that
+ * does not grow with their number. Works on value-only contexts (ntan = 0).
+ *
+ * dpic_adjoint_query: device bytes for a run of up to n_steps steps with a
+ * state checkpoint every checkpoint_every steps (checkpoints, one segment of
+ * replayed states and fields, adjoint arrays).
+ * dpic_adjoint_bind: attach that caller-owned workspace (256-byte aligned);
+ * call before dpic_init_beam, which then keeps a copy of xi. While bound,
+ * dpic_step runs unfused steps, stores a checkpoint every checkpoint_every
+ * steps and does not re-sort particles after the first sort.
+ * dpic_adjoint_backward: after the forward dpic_step calls, sweep the steps
+ * in reverse (replaying each segment from its checkpoint) and write
+ * grad_params[np] and grad_sigma[6] (host, either may be NULL). The particle
+ * state is consumed: call dpic_init_beam before stepping again.
+ * Synchronises the stream.
+ */
+int dpic_adjoint_query(const dpic_dims* dims, int n_steps, int checkpoint_every, size_t* bytes);
+int dpic_adjoint_bind(dpic_ctx* ctx, void* adjoint_workspace_dev, size_t bytes, int n_steps, int checkpoint_every);
+int dpic_adjoint_backward(dpic_ctx* ctx, const double weights[3], double* grad_params, double* grad_sigma);
+
 #ifdef __cplusplus
 }
 #endif

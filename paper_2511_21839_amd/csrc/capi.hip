@@ -62,13 +62,13 @@ void timer_begin(dpic_ctx* c, int stage, hipEvent_t* out_end) {
         }
         pool.emplace_back(a, b);
     }
-    hipEventRecord(pool[i].first, c->stream);
+    (void)hipEventRecord(pool[i].first, c->stream);
     *out_end = pool[i].second;
 }
 
 void timer_end(dpic_ctx* c, int stage, hipEvent_t end) {
     if (!end) return;
-    hipEventRecord(end, c->stream);
+    (void)hipEventRecord(end, c->stream);
     c->stage_launches[stage]++;
 }
 
@@ -89,6 +89,26 @@ const double* closing_map(const dpic_ctx* c, int64_t s, bool last) {
     if (last) return element_map_block(c, e, EC_HALF);
     const int en = c->schedule[s + 1];
     return element_map_block(c, e, en == e ? EC_SAME : EC_NEXT);
+}
+
+int run_solve_field(dpic_ctx* c);
+
+// One unfused step s: half map + deposit, solve, field, kick + half map.
+// When e_store is given, the step's field is copied there (adjoint replay).
+int single_step(dpic_ctx* c, int64_t s, double* e_store) {
+    const int e = c->schedule[s];
+    const double* half = element_map_block(c, e, EC_HALF);
+    int r;
+    if (c->bunch_charge != 0.0) {
+        if ((r = run_particles(c, PF_MAP | PF_DEPOSIT, e, half)) != DPIC_OK) return r;
+        if ((r = run_solve_field(c)) != DPIC_OK) return r;
+        if (e_store)
+            HIPCHK(c, hipMemcpyAsync(e_store, c->ws.E, (size_t)c->dims.nx * c->dims.ny * c->dims.nz * 3 * c->NC * sizeof(double),
+                                     hipMemcpyDeviceToDevice, c->stream));
+        return run_particles(c, PF_KICK | PF_MAP, e, half);
+    }
+    if ((r = run_particles(c, PF_MAP | PF_COUNT, e, half)) != DPIC_OK) return r;
+    return run_particles(c, PF_MAP, e, half);
 }
 
 int run_solve_field(dpic_ctx* c) {
@@ -216,6 +236,32 @@ size_t workspace_layout(const dpic_dims& d, char* base, Workspace* ws) {
     return off;
 }
 
+size_t adjoint_layout(const dpic_dims& d, int nmax, int K, char* base, AdjointWs* out) {
+    const size_t cap = (size_t)d.n_particles;
+    const size_t nodes = (size_t)d.nx * d.ny * d.nz;
+    const size_t nck = ((size_t)nmax + K - 1) / K;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return base ? (double*)(base + o) : nullptr;
+    };
+    AdjointWs a;
+    a.K = K;
+    a.nmax = nmax;
+    a.ckpt = take(nck * 6 * cap * sizeof(double));
+    a.xi = take(6 * cap * sizeof(double));
+    a.states = take((size_t)K * 6 * cap * sizeof(double));
+    a.fields = take((size_t)K * 3 * nodes * sizeof(double));
+    a.lam = take(6 * cap * sizeof(double));
+    a.gacc = take((size_t)DPIC_MAX_ELEMENTS * 10 * sizeof(double));
+    a.ec_dual = take((size_t)DPIC_MAX_ELEMENTS * EC_N * 16 * sizeof(double));
+    a.elem_in_dual = take((size_t)DPIC_MAX_ELEMENTS * 2 * 16 * sizeof(double));
+    a.grad = take(((size_t)DPIC_MAX_PARAMS + 6) * sizeof(double));
+    if (out) *out = a;
+    return off;
+}
+
 }  // namespace dpic
 
 extern "C" {
@@ -252,8 +298,8 @@ int dpic_destroy(dpic_ctx* c) {
     if (!c) return DPIC_EINVAL;
     for (auto& pool : c->ev_pool)
         for (auto& pr : pool) {
-            hipEventDestroy(pr.first);
-            hipEventDestroy(pr.second);
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
         }
     delete c;
     return DPIC_OK;
@@ -375,6 +421,8 @@ int dpic_init_beam(dpic_ctx* c, int64_t n, const double* xi_dev, const double si
     }
     c->n = n;
     HIPCHK(c, launch_init_beam(c, xi_dev, sd.data()));
+    if (c->adj.bound && n > 0)  // the adjoint needs xi for d/dsigma
+        HIPCHK(c, hipMemcpyAsync(c->adj.xi, xi_dev, (size_t)n * 6 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, launch_zero(c, (double*)c->ws.counters, CNT_N));
     HIPCHK(c, launch_zero(c, c->ws.rho, (size_t)c->dims.nx * c->dims.ny * c->dims.nz * NC));
     c->steps_done = 0;
@@ -398,6 +446,22 @@ int dpic_step(dpic_ctx* c, int n) {
     int r;
     if (sc && c->sort_every > 0 && !c->chunks_valid)
         if ((r = run_sort(c)) != DPIC_OK) return r;
+    if (c->adj.bound) {
+        // reverse-mode forward: unfused steps (the backward replays the same
+        // sequence), a checkpoint every K steps, no re-sorting (the adjoint
+        // follows the stored particle order)
+        if (s1 > c->adj.nmax) return fail(c, DPIC_EINVAL, "step: the adjoint workspace covers %d steps", c->adj.nmax);
+        HIPCHK(c, launch_zero(c, c->ws.rho, (size_t)c->dims.nx * c->dims.ny * c->dims.nz * c->NC));
+        const size_t sbytes = (size_t)6 * c->dims.n_particles * sizeof(double);
+        for (int64_t s = s0; s < s1; ++s) {
+            if (s % c->adj.K == 0)
+                HIPCHK(c, hipMemcpyAsync(c->adj.ckpt + (size_t)(s / c->adj.K) * 6 * c->dims.n_particles, c->ws.st,
+                                         sbytes, hipMemcpyDeviceToDevice, c->stream));
+            if ((r = single_step(c, s, nullptr)) != DPIC_OK) return r;
+        }
+        c->steps_done = s1;
+        return DPIC_OK;
+    }
     if (sc) {
         HIPCHK(c, launch_zero(c, c->ws.rho, (size_t)c->dims.nx * c->dims.ny * c->dims.nz * c->NC));
         const double* first = element_map_block(c, c->schedule[s0], EC_HALF);
@@ -603,6 +667,92 @@ int dpic_stage_times(dpic_ctx* c, double* ms, int64_t* launches) {
         c->ev_used[s] = 0;
         c->stage_launches[s] = 0;
     }
+    return DPIC_OK;
+}
+
+int dpic_adjoint_query(const dpic_dims* dims, int n_steps, int checkpoint_every, size_t* bytes) {
+    int r = check_dims(dims);
+    if (r != DPIC_OK) return r;
+    if (!bytes || dims->ntan != 0 || n_steps < 1 || checkpoint_every < 1) return DPIC_EINVAL;
+    *bytes = adjoint_layout(*dims, n_steps, checkpoint_every, nullptr, nullptr);
+    return DPIC_OK;
+}
+
+int dpic_adjoint_bind(dpic_ctx* c, void* adj_dev, size_t bytes, int n_steps, int checkpoint_every) {
+    if (!c || !adj_dev) return DPIC_EINVAL;
+    if (c->ntan != 0) return fail(c, DPIC_EINVAL, "adjoint: the context must be value-only (ntan = 0)");
+    if (n_steps < 1 || checkpoint_every < 1) return fail(c, DPIC_EINVAL, "adjoint: n_steps and checkpoint_every >= 1");
+    if (((uintptr_t)adj_dev) % ALIGN != 0) return fail(c, DPIC_EINVAL, "adjoint: workspace not 256-byte aligned");
+    if (bytes < adjoint_layout(c->dims, n_steps, checkpoint_every, nullptr, nullptr))
+        return fail(c, DPIC_EINVAL, "adjoint: workspace too small");
+    adjoint_layout(c->dims, n_steps, checkpoint_every, (char*)adj_dev, &c->adj);
+    c->adj.bound = true;
+    c->beam_init = false;  // the initial normals must be captured by init_beam
+    return DPIC_OK;
+}
+
+int dpic_adjoint_backward(dpic_ctx* c, const double w[3], double* grad_params, double* grad_sigma) {
+    if (!c || !w) return DPIC_EINVAL;
+    if (!c->adj.bound) return fail(c, DPIC_ESTATE, "backward: no adjoint workspace bound");
+    if (!c->beam_init) return fail(c, DPIC_ESTATE, "backward: no forward run to differentiate");
+    const int np = (int)c->p.size();
+    if (np > 15) return fail(c, DPIC_EUNSUPPORTED, "backward: at most 15 parameters");
+    for (int k = 0; k < 3; ++k)
+        if (!isfinite(w[k])) return fail(c, DPIC_EINVAL, "backward: non-finite weight");
+    const bool sc = c->bunch_charge != 0.0;
+    const size_t cap = (size_t)c->dims.n_particles;
+    const size_t nodes = (size_t)c->dims.nx * c->dims.ny * c->dims.nz;
+    unsigned long long cnt[CNT_N];
+    HIPCHK(c, hipMemcpyAsync(cnt, c->ws.counters, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, launch_adj_terminal(c, w));
+    HIPCHK(c, launch_zero(c, c->adj.gacc, (size_t)DPIC_MAX_ELEMENTS * 10));
+    const int64_t nf = c->steps_done;
+    const int K = c->adj.K;
+    int r;
+    for (int64_t g = (nf + K - 1) / K - 1; g >= 0; --g) {
+        const int64_t sa = g * K, sb = std::min<int64_t>(sa + K, nf);
+        // replay the segment from its checkpoint, keeping each step's start state and field
+        HIPCHK(c, hipMemcpyAsync(c->ws.st, c->adj.ckpt + (size_t)g * 6 * cap, 6 * cap * sizeof(double),
+                                 hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, launch_zero(c, c->ws.rho, nodes));
+        for (int64_t s = sa; s < sb; ++s) {
+            HIPCHK(c, hipMemcpyAsync(c->adj.states + (size_t)(s - sa) * 6 * cap, c->ws.st, 6 * cap * sizeof(double),
+                                     hipMemcpyDeviceToDevice, c->stream));
+            if ((r = single_step(c, s, c->adj.fields + (size_t)(s - sa) * 3 * nodes)) != DPIC_OK) return r;
+        }
+        for (int64_t s = sb - 1; s >= sa; --s)
+            HIPCHK(c, launch_adj_step(c, c->schedule[s], c->adj.states + (size_t)(s - sa) * 6 * cap,
+                                      c->adj.fields + (size_t)(s - sa) * 3 * nodes, sc));
+    }
+    // element constants with one tangent per parameter (identity seeds)
+    std::vector<double> in((size_t)c->n_elem * 2 * 16, 0.0);
+    for (int e = 0; e < c->n_elem; ++e) {
+        double* Ld = &in[(size_t)(e * 2 + 0) * 16];
+        double* kd = &in[(size_t)(e * 2 + 1) * 16];
+        const int lp = c->L_param[e], kp = c->k_param[e];
+        Ld[0] = lp >= 0 ? c->p[lp] : c->L[e];
+        if (lp >= 0) Ld[1 + lp] = 1.0;
+        if (c->kind[e] == 1) {
+            kd[0] = kp >= 0 ? c->p[kp] : c->k[e];
+            if (kp >= 0) kd[1 + kp] = 1.0;
+        }
+    }
+    HIPCHK(c, hipMemcpyAsync(c->adj.elem_in_dual, in.data(), in.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_element_consts_into(c, 16, c->adj.elem_in_dual, c->adj.ec_dual));
+    c->adj.ncd = 16;
+    HIPCHK(c, launch_adj_finish(c, np));
+    std::vector<double> g(DPIC_MAX_PARAMS + 6);
+    HIPCHK(c, hipMemcpyAsync(g.data(), c->adj.grad, g.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->ws.counters, cnt, sizeof cnt, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (grad_params)
+        for (int j = 0; j < np; ++j) grad_params[j] = g[j];
+    if (grad_sigma)
+        for (int j = 0; j < 6; ++j) grad_sigma[j] = g[DPIC_MAX_PARAMS + j];
+    c->beam_init = false;  // the particle state now holds a replayed segment
+    for (int j = 0; j < np; ++j)
+        if (!isfinite(g[j])) return fail(c, DPIC_ENONFINITE, "backward: non-finite gradient");
     return DPIC_OK;
 }
 

@@ -50,9 +50,24 @@ constexpr int SORT_PB = 1024;                            // particles per sort b
 
 size_t workspace_layout(const dpic_dims& d, char* base, Workspace* ws);
 
-struct Timer {
-    hipEvent_t a = nullptr, b = nullptr;
+// Reverse-mode workspace (caller-owned, bound by dpic_adjoint_bind).
+struct AdjointWs {
+    bool bound = false;
+    int K = 0;                     // checkpoint interval (steps)
+    int nmax = 0;                  // steps the checkpoints cover
+    int ncd = 16;                  // channels of the dual element table
+    double* ckpt = nullptr;        // [ceil(nmax/K)][6][cap] state at steps 0, K, 2K, ...
+    double* xi = nullptr;          // [cap][6] initial standard normals, original order
+    double* states = nullptr;      // [K][6][cap] replayed state at each step's start
+    double* fields = nullptr;      // [K][nz][ny][nx][3] replayed field of each step
+    double* lam = nullptr;         // [6][cap] adjoint of the state
+    double* gacc = nullptr;        // [MAX_ELEM][10] dJ/dA (9 map entries), dJ/dtau per element
+    double* ec_dual = nullptr;     // [MAX_ELEM][EC_N][16] element constants with parameter tangents
+    double* elem_in_dual = nullptr;
+    double* grad = nullptr;        // [MAX_PARAMS + 6]
 };
+
+size_t adjoint_layout(const dpic_dims& d, int nmax, int K, char* base, AdjointWs* out);
 
 }  // namespace dpic
 
@@ -87,6 +102,7 @@ struct dpic_ctx {
     int64_t sort_every = 20;
     bool chunks_valid = false;  // the tiled work list matches the stored order
     bool stage_timing = false;
+    dpic::AdjointWs adj;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[DPIC_N_STAGE_TIMERS];
     size_t ev_used[DPIC_N_STAGE_TIMERS] = {0, 0, 0, 0};
     int64_t stage_launches[DPIC_N_STAGE_TIMERS] = {0, 0, 0, 0};
@@ -96,6 +112,7 @@ namespace dpic {
 
 // ---- launchers (particles.hip)
 hipError_t launch_element_consts(dpic_ctx* c);
+hipError_t launch_element_consts_into(dpic_ctx* c, int NC, const double* elem_in, double* ec);
 hipError_t launch_init_beam(dpic_ctx* c, const double* xi, const double* sig_dual /*[6][NC] host-marshalled*/);
 // flags: PF_*; e_tau: element whose step size the kick uses; map: map block
 // to apply (element_map_block) or nullptr without PF_MAP.
@@ -111,9 +128,15 @@ hipError_t launch_sort(dpic_ctx* c);  // also rebuilds the tiled work list
 // ---- launchers (solver.hip)
 hipError_t launch_green(dpic_ctx* c);
 hipError_t launch_solve(dpic_ctx* c);
+hipError_t launch_conv(dpic_ctx* c, double* in, const int nin[3], double* out, const int nout[3], int shift, int NC);
 hipError_t launch_field(dpic_ctx* c);
 
 // ---- launchers (moments.hip)
 hipError_t launch_moments(dpic_ctx* c);
+
+// ---- launchers (adjoint.hip)
+hipError_t launch_adj_terminal(dpic_ctx* c, const double w[3]);
+hipError_t launch_adj_step(dpic_ctx* c, int e, const double* st0, const double* E, bool space_charge);
+hipError_t launch_adj_finish(dpic_ctx* c, int np);
 
 }  // namespace dpic

@@ -115,7 +115,7 @@ __global__ void k_element_combine(int n_elem, double* __restrict__ ec) {
     combine_block<NC>(A, Bn, ec + (size_t)e * EC_N * NC + EC_NEXT * NC + c, c);
 }
 
-hipError_t launch_element_consts(dpic_ctx* cx) {
+hipError_t launch_element_consts_into(dpic_ctx* cx, int NC, const double* elem_in, double* ec) {
     ElemTable tab{};
     for (int e = 0; e < cx->n_elem; ++e) {
         tab.kind[e] = cx->kind[e];
@@ -123,21 +123,27 @@ hipError_t launch_element_consts(dpic_ctx* cx) {
     }
     const double inv_g2 = 1.0 / (cx->gamma0 * cx->gamma0);
     dim3 grid(cx->n_elem), block(64);
-    switch (cx->NC) {
+    switch (NC) {
         case 1:
-            hipLaunchKernelGGL(k_element_consts<1>, grid, block, 0, cx->stream, tab, cx->n_elem, cx->ws.elem_in, cx->ws.ec, inv_g2);
-            hipLaunchKernelGGL(k_element_combine<1>, grid, block, 0, cx->stream, cx->n_elem, cx->ws.ec);
+            hipLaunchKernelGGL(k_element_consts<1>, grid, block, 0, cx->stream, tab, cx->n_elem, elem_in, ec, inv_g2);
+            hipLaunchKernelGGL(k_element_combine<1>, grid, block, 0, cx->stream, cx->n_elem, ec);
             break;
         case 8:
-            hipLaunchKernelGGL(k_element_consts<8>, grid, block, 0, cx->stream, tab, cx->n_elem, cx->ws.elem_in, cx->ws.ec, inv_g2);
-            hipLaunchKernelGGL(k_element_combine<8>, grid, block, 0, cx->stream, cx->n_elem, cx->ws.ec);
+            hipLaunchKernelGGL(k_element_consts<8>, grid, block, 0, cx->stream, tab, cx->n_elem, elem_in, ec, inv_g2);
+            hipLaunchKernelGGL(k_element_combine<8>, grid, block, 0, cx->stream, cx->n_elem, ec);
+            break;
+        case 16:
+            hipLaunchKernelGGL(k_element_consts<16>, grid, block, 0, cx->stream, tab, cx->n_elem, elem_in, ec, inv_g2);
+            hipLaunchKernelGGL(k_element_combine<16>, grid, block, 0, cx->stream, cx->n_elem, ec);
             break;
         default:
-            hipLaunchKernelGGL(k_element_consts<16>, grid, block, 0, cx->stream, tab, cx->n_elem, cx->ws.elem_in, cx->ws.ec, inv_g2);
-            hipLaunchKernelGGL(k_element_combine<16>, grid, block, 0, cx->stream, cx->n_elem, cx->ws.ec);
-            break;
+            return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_element_consts(dpic_ctx* cx) {
+    return launch_element_consts_into(cx, cx->NC, cx->ws.elem_in, cx->ws.ec);
 }
 
 // ---------------------------------------------------------------- beam init

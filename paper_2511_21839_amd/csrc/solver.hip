@@ -203,7 +203,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_fwd(double* __restrict
 // ---------------------------------------------------------------- pass 5
 template <int M, int NC>
 __global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_inv(const double2* __restrict__ in, double* __restrict__ phi,
-                                                              int nx, int rows, const double2* __restrict__ tw) {
+                                                              int nxo, int shift, int rows, const double2* __restrict__ tw) {
     constexpr int NCC = NC == 1 ? 1 : NC / 2;
     constexpr int B = TILE / M;
     constexpr int RB = B / NCC;
@@ -225,7 +225,6 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_inv(const double2* __r
     __syncthreads();
     double *sr = s0r, *si = s0i, *dr = s1r, *di = s1i;
     fft_tile<M, true>(sr, si, dr, di, LB, twr, twi);
-    const int nxo = nx + 2;
     const int per_row = nxo * NC;
     for (int t = threadIdx.x; t < RB * per_row; t += FFT_THREADS) {
         const int r = t / per_row;
@@ -234,7 +233,7 @@ __global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_inv(const double2* __r
         const int ch = rem - xo * NC;
         const int row = row0 + r;
         if (row < rows) {
-            const int xs = (xo + M - 1) & (M - 1);  // output slot xo holds node xo - 1
+            const int xs = (xo - shift + M) & (M - 1);  // output slot xo holds position xo - shift
             const int col = r * NCC + (ch % NCC);
             phi[(size_t)row * per_row + rem] = (NC == 1 || ch < NCC) ? sr[xs * B + col] : si[xs * B + col];
         }
@@ -489,14 +488,15 @@ static hipError_t launch_rows_fwd_nc(int M, double* rho, double2* out, int nx, i
 }
 
 template <int NC>
-static hipError_t launch_rows_inv_nc(int M, const double2* in, double* phi, int nx, int rows, const double2* tw, hipStream_t s) {
+static hipError_t launch_rows_inv_nc(int M, const double2* in, double* phi, int nxo, int shift, int rows,
+                                     const double2* tw, hipStream_t s) {
     constexpr int NCC = NC == 1 ? 1 : NC / 2;
     switch (M) {
 #define DPIC_ROWS_INV(MM)                                                                                      \
     case MM: {                                                                                                 \
         constexpr int RB = (TILE / MM) / NCC;                                                                  \
         hipLaunchKernelGGL((k_fft_rows_inv<MM, NC>), dim3((rows + RB - 1) / RB), dim3(FFT_THREADS), 0, s, in, \
-                           phi, nx, rows, tw);                                                                 \
+                           phi, nxo, shift, rows, tw);                                                         \
         break;                                                                                                 \
     }
         DPIC_ROWS_INV(16) DPIC_ROWS_INV(32) DPIC_ROWS_INV(64) DPIC_ROWS_INV(128)
@@ -506,21 +506,26 @@ static hipError_t launch_rows_inv_nc(int M, const double2* in, double* phi, int 
     return hipGetLastError();
 }
 
-hipError_t launch_solve(dpic_ctx* cx) {
+// out(t) = sum_q in(q) G((t - shift) - q) per dimension, on windows of the
+// doubled grid: input window index q sits at grid position q, output window
+// index t holds grid position t - shift; both arrays are real [z][y][x][NC].
+// The forward solve uses nin = n (rho) and nout = n + 2 with shift 1 (the
+// ghost ring at position -1 = M - 1); the adjoint solve uses nin = n + 2 (its
+// source already shifted by one) and nout = n with shift -1.
+hipError_t launch_conv(dpic_ctx* cx, double* in, const int nin[3], double* out, const int nout[3], int shift, int NC) {
     const int nx = cx->dims.nx, ny = cx->dims.ny, nz = cx->dims.nz;
     const int Mx = 2 * nx, My = 2 * ny, Mz = 2 * nz;
-    const int NC = cx->NC;
     const int NCC = NC == 1 ? 1 : NC / 2;
     const double2* twx = cx->ws.tw;
     const double2* twy = cx->ws.tw + Mx;
     const double2* twz = cx->ws.tw + Mx + My;
     hipStream_t s = cx->stream;
     hipError_t e;
-    // 1: x forward, rho -> A
+    // 1: x forward, in -> A[nin_z][nin_y][Mx]
     switch (NC) {
-        case 1: e = launch_rows_fwd_nc<1>(Mx, cx->ws.rho, cx->ws.buf0, nx, ny * nz, twx, s); break;
-        case 8: e = launch_rows_fwd_nc<8>(Mx, cx->ws.rho, cx->ws.buf0, nx, ny * nz, twx, s); break;
-        default: e = launch_rows_fwd_nc<16>(Mx, cx->ws.rho, cx->ws.buf0, nx, ny * nz, twx, s); break;
+        case 1: e = launch_rows_fwd_nc<1>(Mx, in, cx->ws.buf0, nin[0], nin[1] * nin[2], twx, s); break;
+        case 8: e = launch_rows_fwd_nc<8>(Mx, in, cx->ws.buf0, nin[0], nin[1] * nin[2], twx, s); break;
+        default: e = launch_rows_fwd_nc<16>(Mx, in, cx->ws.buf0, nin[0], nin[1] * nin[2], twx, s); break;
     }
     if (e != hipSuccess) return e;
     const int64_t W = (int64_t)Mx * NCC;
@@ -533,39 +538,46 @@ hipError_t launch_solve(dpic_ctx* cx) {
     a.gny1 = ny + 1;
     a.Mx = Mx;
     a.My = My;
-    // 2: y forward, A -> B
-    a.in_outer = (int64_t)ny * W;
+    // 2: y forward, A -> B[nin_z][My][Mx]
+    a.in_outer = (int64_t)nin[1] * W;
     a.in_stride = W;
-    a.n_in = ny;
+    a.n_in = nin[1];
     a.out_outer = (int64_t)My * W;
     a.out_stride = W;
     a.n_out = My;
     a.out_shift = 0;
-    if ((e = launch_cols<0>(My, nz, a, cx->ws.buf0, cx->ws.buf1, twy, s)) != hipSuccess) return e;
-    // 3: z forward, Ghat, z inverse, B -> C
+    if ((e = launch_cols<0>(My, nin[2], a, cx->ws.buf0, cx->ws.buf1, twy, s)) != hipSuccess) return e;
+    // 3: z forward, Ghat, z inverse, B -> C[nout_z][My][Mx]
     a.in_outer = W;
     a.in_stride = (int64_t)My * W;
-    a.n_in = nz;
+    a.n_in = nin[2];
     a.out_outer = W;
     a.out_stride = (int64_t)My * W;
-    a.n_out = nz + 2;
-    a.out_shift = 1;
+    a.n_out = nout[2];
+    a.out_shift = shift;
     if ((e = launch_cols<1>(Mz, My, a, cx->ws.buf1, cx->ws.buf0, twz, s)) != hipSuccess) return e;
-    // 4: y inverse, C -> D
+    // 4: y inverse, C -> D[nout_z][nout_y][Mx]
     a.in_outer = (int64_t)My * W;
     a.in_stride = W;
     a.n_in = My;
-    a.out_outer = (int64_t)(ny + 2) * W;
+    a.out_outer = (int64_t)nout[1] * W;
     a.out_stride = W;
-    a.n_out = ny + 2;
-    a.out_shift = 1;
-    if ((e = launch_cols<2>(My, nz + 2, a, cx->ws.buf0, cx->ws.buf1, twy, s)) != hipSuccess) return e;
-    // 5: x inverse, D -> phi
+    a.n_out = nout[1];
+    a.out_shift = shift;
+    if ((e = launch_cols<2>(My, nout[2], a, cx->ws.buf0, cx->ws.buf1, twy, s)) != hipSuccess) return e;
+    // 5: x inverse, D -> out
+    const int rows = nout[1] * nout[2];
     switch (NC) {
-        case 1: return launch_rows_inv_nc<1>(Mx, cx->ws.buf1, cx->ws.phi, nx, (ny + 2) * (nz + 2), twx, s);
-        case 8: return launch_rows_inv_nc<8>(Mx, cx->ws.buf1, cx->ws.phi, nx, (ny + 2) * (nz + 2), twx, s);
-        default: return launch_rows_inv_nc<16>(Mx, cx->ws.buf1, cx->ws.phi, nx, (ny + 2) * (nz + 2), twx, s);
+        case 1: return launch_rows_inv_nc<1>(Mx, cx->ws.buf1, out, nout[0], shift, rows, twx, s);
+        case 8: return launch_rows_inv_nc<8>(Mx, cx->ws.buf1, out, nout[0], shift, rows, twx, s);
+        default: return launch_rows_inv_nc<16>(Mx, cx->ws.buf1, out, nout[0], shift, rows, twx, s);
     }
+}
+
+hipError_t launch_solve(dpic_ctx* cx) {
+    const int n[3] = {cx->dims.nx, cx->dims.ny, cx->dims.nz};
+    const int g[3] = {n[0] + 2, n[1] + 2, n[2] + 2};
+    return launch_conv(cx, cx->ws.rho, n, cx->ws.phi, g, 1, cx->NC);
 }
 
 // ---------------------------------------------------------------- Green's function

@@ -41,6 +41,7 @@ SYMBOLS = (
     "dpic_step", "dpic_read_moments", "dpic_read_emittance", "dpic_read_particles",
     "dpic_counters", "dpic_stage", "dpic_read_grid", "dpic_write_grid", "dpic_state_bytes",
     "dpic_save_state", "dpic_load_state", "dpic_set_option", "dpic_stage_times",
+    "dpic_adjoint_query", "dpic_adjoint_bind", "dpic_adjoint_backward",
 )
 
 
@@ -86,6 +87,10 @@ _SIGS = {
     "dpic_load_state": ([_P, _P], ctypes.c_int),
     "dpic_set_option": ([_P, ctypes.c_int, ctypes.c_int64], ctypes.c_int),
     "dpic_stage_times": ([_P, _D, _I64], ctypes.c_int),
+    "dpic_adjoint_query": ([ctypes.POINTER(dpic_dims), ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+                           ctypes.c_int),
+    "dpic_adjoint_bind": ([_P, _P, ctypes.c_size_t, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "dpic_adjoint_backward": ([_P, _D, _D, _D], ctypes.c_int),
 }
 
 
@@ -276,6 +281,24 @@ def dpic_stage_times(ctx):
     return ms, np.array(list(n), dtype=np.int64)
 
 
+def dpic_adjoint_query(dims: dpic_dims, n_steps: int, checkpoint_every: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(None, lib().dpic_adjoint_query(ctypes.byref(dims), int(n_steps), int(checkpoint_every), ctypes.byref(b)))
+    return b.value
+
+
+def dpic_adjoint_bind(ctx, dev_ptr: int, nbytes: int, n_steps: int, checkpoint_every: int):
+    _check(ctx, lib().dpic_adjoint_bind(ctx, _P(dev_ptr), nbytes, int(n_steps), int(checkpoint_every)))
+
+
+def dpic_adjoint_backward(ctx, weights, n_params: int):
+    w = _f64(weights, (3,))
+    gp = np.zeros(max(n_params, 1))
+    gs = np.zeros(6)
+    _check(ctx, lib().dpic_adjoint_backward(ctx, _dp(w), _dp(gp), _dp(gs)))
+    return gp[:n_params], gs
+
+
 # ---------------------------------------------------------------- convenience
 class Simulation:
     """One context with its torch-owned workspace, on torch's current stream."""
@@ -364,3 +387,15 @@ class Simulation:
 
     def synchronize(self):
         self.stream.synchronize()
+
+    # -- reverse mode (value-only contexts) --------------------------------
+    def bind_adjoint(self, n_steps: int, checkpoint_every: int):
+        """Allocate (torch) and attach the reverse-mode workspace; call before init_beam."""
+        nbytes = dpic_adjoint_query(self.dims, n_steps, checkpoint_every)
+        self.adjoint_workspace = self.torch.empty(nbytes + 256, dtype=self.torch.uint8,
+                                                  device=self.workspace.device)
+        ptr = (self.adjoint_workspace.data_ptr() + 255) // 256 * 256
+        dpic_adjoint_bind(self.ctx, ptr, nbytes, n_steps, checkpoint_every)
+
+    def backward(self, weights, n_params: int):
+        return dpic_adjoint_backward(self.ctx, weights, n_params)
