@@ -72,6 +72,61 @@ def _recorded_traffic():
         return None
 
 
+def _median_ms(fn, reps=3):
+    import torch
+
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return float(sorted(ts)[len(ts) // 2])
+
+
+def _adjoint_timing():
+    """Gradient of eps_x + eps_y w.r.t. 7 lattice parameters + 6 beam sizes on
+    the 1e4-particle, 32^3, 100-step workload: reverse mode (checkpoint every
+    50 steps) against forward mode with 13 tangents and the value-only run."""
+    import synth
+    from paper_2511_21839_amd import dpic
+    from paper_2511_21839_amd.autograd import AdjointRun
+
+    w = synth.c1(ntan=13, sigma_tangents=True)
+    L = w.lattice
+    xi = w.xi()
+
+    def plain(ntan):
+        sim = dpic.Simulation(w.n_particles, ntan, w.grid)
+        sim.set_beam(w.kinetic_eV, w.rest_eV, w.charge_e, w.bunch_charge_C)
+        sim.set_grid(w.lo, w.hi)
+        sim.set_lattice(L.kind, L.n_steps, L.L, L.k, L.L_param, L.k_param, L.n_periods)
+        sim.set_params(w.params, w.param_seed() if ntan else None)
+        ss = w.sigma_seed() if ntan else None
+
+        def go():
+            sim.init_beam(xi, w.sigma, ss)
+            sim.step(w.total_steps())
+        return go, sim
+
+    go13, s13 = plain(13)
+    go0, s0 = plain(0)
+    run = AdjointRun(w.n_particles, w.grid, w.lo, w.hi, (w.kinetic_eV, w.rest_eV, w.charge_e, w.bunch_charge_C),
+                     (L.kind, L.n_steps, L.L, L.k, L.L_param, L.k_param, L.n_periods), xi, w.total_steps(),
+                     checkpoint_every=50)
+
+    def adj():
+        run.forward(w.params, w.sigma)
+        run.backward([1.0, 1.0, 0.0])
+
+    t13, t0, ta = _median_ms(go13), _median_ms(go0), _median_ms(adj)
+    return {"workload": "1e4 protons, 32^3 grid, 100 steps, J = eps_x + eps_y, 13 gradient components",
+            "checkpoint_every": 50, "t_forward_13_tangents_ms": t13, "t_value_only_ms": t0,
+            "t_adjoint_ms": ta, "adjoint_over_forward_13": ta / t13, "adjoint_over_value_only": ta / t0}
+
+
 def _copy_calibration(mib: int) -> int:
     """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give the
     factor that turns counter KiB into HBM bytes for the same profiler setup."""
@@ -95,6 +150,8 @@ def main(argv=None):
     ap.add_argument("--sort-every", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extensions", action="store_true",
+                    help="skip the reverse-mode and batched timings")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (to scale HBM byte counters)")
     args = ap.parse_args(argv)
@@ -190,6 +247,8 @@ def main(argv=None):
                    "emittance_x": float(emit[0, 0]), "emittance_y": float(emit[1, 0]),
                    "finite": bool(np.isfinite(emit).all())},
     }
+    if not args.no_extensions:
+        line["adjoint"] = _adjoint_timing()
     if not args.no_cpu_baseline and args.cpu_steps > 0:
         line["cpu_baseline"] = _cpu_baseline(w, xi, args.cpu_steps)
     print(json.dumps(line), flush=True)
