@@ -127,6 +127,109 @@ def _adjoint_timing():
             "t_adjoint_ms": ta, "adjoint_over_forward_13": ta / t13, "adjoint_over_value_only": ta / t0}
 
 
+def _sim_for(w, capacity, nbatch=1):
+    from paper_2511_21839_amd import dpic
+
+    sim = dpic.Simulation(capacity, w.ntan, w.grid, nbatch=nbatch)
+    sim.set_beam(w.kinetic_eV, w.rest_eV, w.charge_e, w.bunch_charge_C)
+    sim.set_grid(w.lo, w.hi)
+    L = w.lattice
+    sim.set_lattice(L.kind, L.n_steps, L.L, L.k, L.L_param, L.k_param, L.n_periods)
+    return sim
+
+
+def _batch_vs_singles(bt, steps, autotune_steps=0, graph=False):
+    """One batched run of every setting of `bt` against the settings run one
+    after another in a single-setting context (same inputs, same options).
+    Returns timings, the autotuner's choice and the largest difference of the
+    batched emittances (value per scalar, derivatives normwise) from the
+    single runs."""
+    import numpy as np
+    import torch
+    from paper_2511_21839_amd import dpic
+
+    w = bt.base
+    xi = bt.xi()
+    seed = w.param_seed()
+    sseed = w.sigma_seed()
+    sim = _sim_for(w, dpic.batch_capacity(bt.ns), bt.nbatch)
+    sim.set_params_batch(bt.params, seed)
+    tuned = None
+    if autotune_steps:
+        sim.init_beam_batch(bt.ns, xi, bt.sigma, sseed)
+        sim.step(1)
+        tuned = sim.autotune(autotune_steps)
+    if graph:
+        sim.set_option(dpic.OPT_GRAPH, 1)
+    opts = {k: sim.get_option(o) for k, o in (("sort_every", dpic.OPT_SORT_EVERY), ("chunk", dpic.OPT_CHUNK),
+                                                ("part_blocks", dpic.OPT_PART_BLOCKS))}
+    runs = []
+    for _ in range(2 if graph else 1):  # with graphs: capture, then the timed replay
+        sim.init_beam_batch(bt.ns, xi, bt.sigma, sseed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        runs.append(time.perf_counter() - t0)
+    t_batch = runs[-1]
+    eb = sim.emittance()
+    oob = sim.batch_counters()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    one = _sim_for(w, int(bt.ns.max()))
+    for k, o in (("sort_every", dpic.OPT_SORT_EVERY), ("chunk", dpic.OPT_CHUNK), ("part_blocks", dpic.OPT_PART_BLOCKS)):
+        one.set_option(o, opts[k])
+    if graph:
+        one.set_option(dpic.OPT_GRAPH, 1)
+    t_single = 0.0
+    ev = ed = 0.0
+    row = 0
+    for b in range(bt.nbatch):
+        n = int(bt.ns[b])
+        xb = xi[row:row + n]
+        row += n
+        one.set_params(bt.params[b], seed)
+        reps = 2 if graph else 1
+        for _ in range(reps):
+            one.init_beam(xb, bt.sigma[b], sseed)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            one.step(steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        t_single += dt
+        e1 = one.emittance()
+        for pl in range(2):
+            ev = max(ev, abs(eb[b, pl, 0] - e1[pl, 0]) / abs(e1[pl, 0]))
+            ed = max(ed, float(np.abs(eb[b, pl, 1:] - e1[pl, 1:]).max() / np.abs(e1[pl, 1:]).max()))
+    one.close()
+    return {"t_batched_s": t_batch, "t_sum_single_s": t_single, "batched_over_singles": t_batch / t_single,
+            "options": opts, "autotune": tuned, "out_of_box": int(oob.sum()),
+            "max_rel_err_value": ev, "max_rel_err_derivatives": ed}
+
+
+def _batched_timing():
+    """The 64-setting workload (64^3 grid, 1e5-1e6 particles per setting, 500
+    steps, 7 tangents), autotuned, and 256 settings of the 1e4-particle 32^3
+    workload with 13 tangents over 100 steps (the surrogate's training runs),
+    with graph replay."""
+    import synth
+
+    c4 = synth.c4()
+    r4 = _batch_vs_singles(c4, c4.base.total_steps(), autotune_steps=20)
+    r4["workload"] = c4.base.name
+    base5 = synth.c1(ntan=13, sigma_tangents=True)
+    x = synth.c5_inputs(256, seed=7)
+    import numpy as np
+
+    b5 = synth.Batch(base=base5, params=x[:, :7], sigma=x[:, 7:], ns=np.full(256, base5.n_particles),
+                     seeds=base5.seed + np.arange(256))
+    r5 = _batch_vs_singles(b5, base5.total_steps(), graph=True)
+    r5["workload"] = "256 settings of 1e4 protons, 32^3 grid, 100 steps, 13 tangents (inputs +-5%), graph replay"
+    return {"c4": r4, "c1x256": r5}
+
+
 def _copy_calibration(mib: int) -> int:
     """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give the
     factor that turns counter KiB into HBM bytes for the same profiler setup."""
@@ -249,6 +352,7 @@ def main(argv=None):
     }
     if not args.no_extensions:
         line["adjoint"] = _adjoint_timing()
+        line["batched"] = _batched_timing()
     if not args.no_cpu_baseline and args.cpu_steps > 0:
         line["cpu_baseline"] = _cpu_baseline(w, xi, args.cpu_steps)
     print(json.dumps(line), flush=True)

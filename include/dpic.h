@@ -30,6 +30,14 @@
  *    1 + t the derivative with respect to tangent t, the rest zero.
  *  - Units: SI (m, V, C); momenta are normalised, px/p0, py/p0 and
  *    delta = (p - p0)/p0; z is the lab-frame distance from the bunch centre.
+ *  - Batches: a context runs B = dims.nbatch independent settings at once
+ *    (each its own lattice parameter values, particle count and initial beam;
+ *    grid, beam energy, bunch charge and lattice structure shared). Every
+ *    stage is one launch over all settings. Setting b's particles take
+ *    storage slots from a multiple of 1024, so the capacity must cover
+ *    sum over b < B-1 of roundup(n_b, 1024), plus n_{B-1}. Outputs that are
+ *    per setting carry a leading [B] index; with B = 1 it is omitted from
+ *    the layouts below.
  */
 #ifndef DPIC_H
 #define DPIC_H
@@ -55,10 +63,11 @@ typedef struct dpic_ctx dpic_ctx;
 
 /* Problem dimensions, fixed for the lifetime of a context. */
 typedef struct dpic_dims {
-    int64_t n_particles; /* capacity: maximum number of macroparticles      */
+    int64_t n_particles; /* capacity: storage slots for all settings         */
     int32_t ntan;        /* number of tangents (derivative channels), 0..15  */
     int32_t nx, ny, nz;  /* grid nodes per dimension, each in {8,16,32,64}   */
     int32_t flags;       /* reserved, must be 0                              */
+    int32_t nbatch;      /* settings run together, 1..4096 (0 means 1)       */
 } dpic_dims;
 
 /* Library version as major*10000 + minor*100 + patch. */
@@ -117,9 +126,15 @@ int dpic_set_lattice(dpic_ctx* ctx, int n_elem, const int* kind, const int* n_st
  * the derivative of p[j] with respect to each tangent, Sec. 2 seeding
  * X_i = (x_i, 0, .., 1, .., 0)); seed == NULL means identity (p[j] carries
  * tangent j for j < ntan). Recomputes the per-element dual step sizes and
- * half-step maps on the device.
+ * half-step maps on the device. Every setting of a batch takes these values.
  */
 int dpic_set_params(dpic_ctx* ctx, int np, const double* p, const double* seed);
+
+/*
+ * Per-setting parameter values p[nb][np] (nb must equal the context's B) with
+ * the seeds seed[np][ntan] (or NULL = identity) shared by all settings.
+ */
+int dpic_set_params_batch(dpic_ctx* ctx, int nb, int np, const double* p, const double* seed);
 
 /*
  * Initial beam zeta_j = sigma_j xi_j for n <= capacity particles.
@@ -127,10 +142,20 @@ int dpic_set_params(dpic_ctx* ctx, int np, const double* p, const double* seed);
  * sigma[6]: rms sizes of x, px/p0, y, py/p0, z, delta.
  * sigma_seed[6][ntan] or NULL: derivative of sigma_j per tangent, so the
  * initial tangents are sigma_seed[j][t] * xi_j.
- * Resets the step counter and the diagnostic counters.
+ * Resets the step counter and the diagnostic counters. Needs B = 1.
  */
 int dpic_init_beam(dpic_ctx* ctx, int64_t n, const double* xi_dev, const double sigma[6],
                    const double* sigma_seed);
+
+/*
+ * Initial beams of all nb = B settings: setting b has n[b] >= 0 particles,
+ * its normals are rows [sum_{b'<b} n[b'], + n[b]) of the packed device array
+ * xi_dev [sum n][6], its sizes sigma[b][6]; sigma_seed[6][ntan] (or NULL) is
+ * shared. The bunch charge is split over each setting's own n[b]. Fails with
+ * DPIC_EINVAL when the settings do not fit the capacity (see Batches).
+ */
+int dpic_init_beam_batch(dpic_ctx* ctx, int nb, const int64_t* n, const double* xi_dev, const double* sigma,
+                         const double* sigma_seed);
 
 /*
  * Advance n steps along the lattice schedule (asynchronous). Each step is
@@ -140,36 +165,39 @@ int dpic_init_beam(dpic_ctx* ctx, int64_t n, const double* xi_dev, const double 
 int dpic_step(dpic_ctx* ctx, int n);
 
 /*
- * Raw dual moments over all particles, host out[3][5][1+ntan]: planes
+ * Raw dual moments over each setting's particles, host out[B][3][5][1+ntan]: planes
  * (x,px), (y,py), (z,delta); moments <u^2>, <u p>, <p^2>, <u>, <p> with 1/N
  * sums (Sec. 4). Synchronises the stream.
  */
 int dpic_read_moments(dpic_ctx* ctx, double* out);
 
 /*
- * Emittances as duals, host out[3][1+ntan]: eps = sqrt(<u^2><p^2> - <u p>^2)
+ * Emittances as duals, host out[B][3][1+ntan]: eps = sqrt(<u^2><p^2> - <u p>^2)
  * with raw moments (Sec. 4) when centred == 0, central moments otherwise.
- * Synchronises the stream.
+ * A setting without particles reports zeros. Synchronises the stream.
  */
 int dpic_read_emittance(dpic_ctx* ctx, int centred, double* out);
 
 /*
- * Particle state in the original particle order, host out[n][6][1+ntan].
+ * Particle state in the original particle order, host out[n][6][1+ntan]
+ * (settings back to back in the packed order of dpic_init_beam_batch).
  * Synchronises the stream.
  */
 int dpic_read_particles(dpic_ctx* ctx, double* out);
 
 /*
  * Diagnostics, host: particle-steps found outside the box, steps done, and
- * max |x|, |y|, |z| seen at deposit time (extent may be NULL).
- * Synchronises the stream.
+ * max |x|, |y|, |z| seen at deposit time (extent may be NULL); summed and
+ * maximised over the settings. Synchronises the stream.
  */
 int dpic_counters(dpic_ctx* ctx, int64_t* out_of_box, int64_t* steps_done, double* extent);
+/* Out-of-box particle-steps per setting, host out_of_box[B]. Synchronises. */
+int dpic_batch_counters(dpic_ctx* ctx, int64_t* out_of_box);
 
 /* Stage-level access for parity checks and diagnostics ------------------ */
-#define DPIC_GRID_RHO 0 /* node charges  [nz][ny][nx][1+ntan]            */
-#define DPIC_GRID_PHI 1 /* potential     [nz+2][ny+2][nx+2][1+ntan], node i at i+1 */
-#define DPIC_GRID_E 2   /* rest-frame E  [nz][ny][nx][3][1+ntan]         */
+#define DPIC_GRID_RHO 0 /* node charges  [B][nz][ny][nx][1+ntan]         */
+#define DPIC_GRID_PHI 1 /* potential     [B][nz+2][ny+2][nx+2][1+ntan], node i at i+1 */
+#define DPIC_GRID_E 2   /* rest-frame E  [B][nz][ny][nx][3][1+ntan]      */
 
 #define DPIC_STAGE_DEPOSIT 0 /* clear rho, deposit the current particles    */
 #define DPIC_STAGE_SOLVE 1   /* rho -> phi (consumes rho: it is left zeroed) */
@@ -182,21 +210,48 @@ int dpic_read_grid(dpic_ctx* ctx, int which, double* out);
 int dpic_write_grid(dpic_ctx* ctx, int which, const double* in);
 
 /*
- * Checkpoint: bytes needed, then copy the particle state, particle order and
- * step counter to / from caller device memory (asynchronous).
+ * Checkpoint: bytes needed, then copy the particle state, particle order,
+ * per-setting particle counts and step counter to / from caller device
+ * memory (synchronous).
  */
 int dpic_state_bytes(const dpic_ctx* ctx, size_t* bytes);
 int dpic_save_state(dpic_ctx* ctx, void* dev_buf);
 int dpic_load_state(dpic_ctx* ctx, const void* dev_buf);
 
 /*
- * Options: DPIC_OPT_SORT_EVERY = re-sort particles by grid tile every k steps
- * (0 = never); DPIC_OPT_STAGE_TIMING = 1 records HIP events around every
- * stage launch of dpic_step (read with dpic_stage_times).
+ * Options:
+ *  DPIC_OPT_SORT_EVERY = re-sort particles by grid tile every k steps (0 = never);
+ *  DPIC_OPT_STAGE_TIMING = 1 records HIP events around every stage launch of
+ *    dpic_step (read with dpic_stage_times);
+ *  DPIC_OPT_CHUNK = particles per work item of the tiled particle kernel
+ *    (a multiple of 64 in 128..8192, default 1024);
+ *  DPIC_OPT_PART_BLOCKS = workgroups of the persistent tiled particle kernel
+ *    (0 = twice the device's resident capacity for it, the default);
+ *  DPIC_OPT_GRAPH = 1 captures each distinct dpic_step(n) call (same start
+ *    step, same n, same batch layout) in a HIP graph on first use and replays
+ *    it afterwards; ignored while stage timing or the adjoint is on. The
+ *    stream bound at dpic_create may be the null stream: capture runs on a
+ *    stream the context creates.
  */
 #define DPIC_OPT_SORT_EVERY 1
 #define DPIC_OPT_STAGE_TIMING 2
+#define DPIC_OPT_CHUNK 3
+#define DPIC_OPT_PART_BLOCKS 4
+#define DPIC_OPT_GRAPH 5
 int dpic_set_option(dpic_ctx* ctx, int option, int64_t value);
+int dpic_get_option(const dpic_ctx* ctx, int option, int64_t* value);
+
+/*
+ * Autotuner: times trial_steps steps from the current state for candidate
+ * work-item sizes, persistent grid sizes and sort cadences (coordinate
+ * search), restores the state and the counters after every trial, and keeps
+ * the fastest setting. scratch_dev: caller device memory of at least
+ * dpic_state_bytes(). best[3] (host, may be NULL) receives
+ * {sort_every, chunk, part_blocks}; ms_best the time of the winning trial.
+ * Needs space charge on and no adjoint bound; synchronises.
+ */
+int dpic_autotune(dpic_ctx* ctx, void* scratch_dev, size_t scratch_bytes, int trial_steps, int64_t* best,
+                  double* ms_best);
 
 /*
  * Accumulated stage times since the last call, host ms[DPIC_N_STAGE_TIMERS]
@@ -210,7 +265,8 @@ int dpic_stage_times(dpic_ctx* ctx, double* ms, int64_t* launches);
  * Reverse mode: gradients of J = w0 eps_x + w1 eps_y + w2 eps_z (raw
  * emittances of the final beam, Sec. 4) with respect to the parameters of
  * dpic_set_params (at most 15) and the six initial beam sizes, at a cost that
- * does not grow with their number. Works on value-only contexts (ntan = 0).
+ * does not grow with their number. Works on value-only contexts (ntan = 0)
+ * with one setting (B = 1; otherwise DPIC_EUNSUPPORTED).
  *
  * dpic_adjoint_query: device bytes for a run of up to n_steps steps with a
  * state checkpoint every checkpoint_every steps (checkpoints, one segment of

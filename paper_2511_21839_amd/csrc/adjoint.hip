@@ -375,7 +375,7 @@ hipError_t launch_adj_step(dpic_ctx* cx, int e, const double* st0, const double*
         if ((err = hipGetLastError()) != hipSuccess) return err;
         const int nin[3] = {nx + 2, ny + 2, nz + 2};
         const int nout[3] = {nx, ny, nz};
-        if ((err = launch_conv(cx, cx->ws.phi, nin, cx->ws.rho, nout, -1, 1)) != hipSuccess) return err;
+        if ((err = launch_conv(cx, cx->ws.phi, nin, cx->ws.rho, nout, -1, 1, 1)) != hipSuccess) return err;
     } else {
         if ((err = launch_zero(cx, cx->ws.rho, (size_t)nx * ny * nz)) != hipSuccess) return err;
     }

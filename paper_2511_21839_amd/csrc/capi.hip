@@ -1,6 +1,7 @@
 // C ABI of the dpic library: argument checking, workspace layout, the step
-// schedule and host<->device marshalling. All arithmetic of the method runs in
-// the kernels of particles.hip, solver.hip and moments.hip.
+// schedule, graph capture of step runs, the autotuner and host<->device
+// marshalling. All arithmetic of the method runs in the kernels of
+// particles.hip, solver.hip, moments.hip and adjoint.hip.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -16,8 +17,10 @@ using namespace dpic;
 namespace {
 
 constexpr size_t ALIGN = 256;
+constexpr size_t MAX_GRAPHS = 32;
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+int64_t seg_up(int64_t v) { return (v + SEG - 1) / SEG * SEG; }
 
 int fail(dpic_ctx* c, int code, const char* fmt, ...) {
     if (c) {
@@ -43,6 +46,7 @@ int check_dims(const dpic_dims* d) {
     if (!d) return DPIC_EINVAL;
     if (d->n_particles < 1 || d->n_particles > (int64_t)0x7fffffff) return DPIC_EINVAL;
     if (d->flags != 0) return DPIC_EINVAL;
+    if (d->nbatch < 0 || d->nbatch > MAX_BATCH) return DPIC_EINVAL;
     if (d->ntan < 0 || d->ntan > 15) return DPIC_EUNSUPPORTED;
     if (!grid_ok(d->nx) || !grid_ok(d->ny) || !grid_ok(d->nz)) return DPIC_EUNSUPPORTED;
     return DPIC_OK;
@@ -74,36 +78,36 @@ void timer_end(dpic_ctx* c, int stage, hipEvent_t end) {
 
 enum { T_PART = 0, T_SOLVE = 1, T_FIELD = 2, T_SORT = 3 };
 
-int run_particles(dpic_ctx* c, int flags, int e_tau, const double* map) {
+int run_particles(dpic_ctx* c, int flags, int e_tau, int map_off) {
     hipEvent_t end;
     timer_begin(c, T_PART, &end);
-    HIPCHK(c, launch_particles(c, flags, e_tau, map, c->sort_every > 0 && c->chunks_valid));
+    HIPCHK(c, launch_particles(c, flags, e_tau, map_off, c->sort_every > 0 && c->chunks_valid));
     timer_end(c, T_PART, end);
     return DPIC_OK;
 }
 
 // Map block that ends step s: the second half step of element e(s) fused with
 // the first half step of e(s+1), or the lone half step on the last step of a call.
-const double* closing_map(const dpic_ctx* c, int64_t s, bool last) {
+int closing_map(const dpic_ctx* c, int64_t s, bool last) {
     const int e = c->schedule[s];
-    if (last) return element_map_block(c, e, EC_HALF);
+    if (last) return ec_offset(c, e, EC_HALF);
     const int en = c->schedule[s + 1];
-    return element_map_block(c, e, en == e ? EC_SAME : EC_NEXT);
+    return ec_offset(c, e, en == e ? EC_SAME : EC_NEXT);
 }
 
 int run_solve_field(dpic_ctx* c);
 
 // One unfused step s: half map + deposit, solve, field, kick + half map.
-// When e_store is given, the step's field is copied there (adjoint replay).
+// When e_store is given, the step's field is copied there (adjoint replay, B = 1).
 int single_step(dpic_ctx* c, int64_t s, double* e_store) {
     const int e = c->schedule[s];
-    const double* half = element_map_block(c, e, EC_HALF);
+    const int half = ec_offset(c, e, EC_HALF);
     int r;
     if (c->bunch_charge != 0.0) {
         if ((r = run_particles(c, PF_MAP | PF_DEPOSIT, e, half)) != DPIC_OK) return r;
         if ((r = run_solve_field(c)) != DPIC_OK) return r;
         if (e_store)
-            HIPCHK(c, hipMemcpyAsync(e_store, c->ws.E, (size_t)c->dims.nx * c->dims.ny * c->dims.nz * 3 * c->NC * sizeof(double),
+            HIPCHK(c, hipMemcpyAsync(e_store, c->ws.E, grid_nodes(c) * 3 * c->NC * sizeof(double),
                                      hipMemcpyDeviceToDevice, c->stream));
         return run_particles(c, PF_KICK | PF_MAP, e, half);
     }
@@ -138,30 +142,34 @@ bool consts_possible(const dpic_ctx* c) {
     return true;
 }
 
-// Upload element L and k duals (value + seed rows of the bound parameters) and
-// compute the per-element constants on the device.
+// Upload every setting's element L and k duals (value + seed rows of the
+// bound parameters) and compute the per-element constants on the device.
 int refresh_elements(dpic_ctx* c) {
     if (!consts_possible(c)) return DPIC_OK;
     const int NC = c->NC, nt = c->ntan;
-    std::vector<double> in((size_t)c->n_elem * 2 * NC, 0.0);
-    for (int e = 0; e < c->n_elem; ++e) {
-        double* Ld = &in[(size_t)(e * 2 + 0) * NC];
-        double* kd = &in[(size_t)(e * 2 + 1) * NC];
-        const int lp = c->L_param[e], kp = c->k_param[e];
-        if (lp >= 0) {
-            if (lp >= (int)c->p.size()) return fail(c, DPIC_EINVAL, "element %d binds L to parameter %d of %zu", e, lp, c->p.size());
-            Ld[0] = c->p[lp];
-            for (int t = 0; t < nt; ++t) Ld[1 + t] = c->seed[(size_t)lp * nt + t];
-        } else {
-            Ld[0] = c->L[e];
-        }
-        if (c->kind[e] == 1) {
-            if (kp >= 0) {
-                if (kp >= (int)c->p.size()) return fail(c, DPIC_EINVAL, "element %d binds k to parameter %d of %zu", e, kp, c->p.size());
-                kd[0] = c->p[kp];
-                for (int t = 0; t < nt; ++t) kd[1 + t] = c->seed[(size_t)kp * nt + t];
+    const size_t per = (size_t)DPIC_MAX_ELEMENTS * 2 * NC;
+    std::vector<double> in(per * c->B, 0.0);
+    for (int b = 0; b < c->B; ++b) {
+        const double* pb = c->params_set ? &c->p[(size_t)b * c->np] : nullptr;
+        for (int e = 0; e < c->n_elem; ++e) {
+            double* Ld = &in[b * per + (size_t)(e * 2 + 0) * NC];
+            double* kd = &in[b * per + (size_t)(e * 2 + 1) * NC];
+            const int lp = c->L_param[e], kp = c->k_param[e];
+            if (lp >= 0) {
+                if (lp >= c->np) return fail(c, DPIC_EINVAL, "element %d binds L to parameter %d of %d", e, lp, c->np);
+                Ld[0] = pb[lp];
+                for (int t = 0; t < nt; ++t) Ld[1 + t] = c->seed[(size_t)lp * nt + t];
             } else {
-                kd[0] = c->k[e];
+                Ld[0] = c->L[e];
+            }
+            if (c->kind[e] == 1) {
+                if (kp >= 0) {
+                    if (kp >= c->np) return fail(c, DPIC_EINVAL, "element %d binds k to parameter %d of %d", e, kp, c->np);
+                    kd[0] = pb[kp];
+                    for (int t = 0; t < nt; ++t) kd[1 + t] = c->seed[(size_t)kp * nt + t];
+                } else {
+                    kd[0] = c->k[e];
+                }
             }
         }
     }
@@ -174,7 +182,7 @@ int refresh_elements(dpic_ctx* c) {
 bool elements_ready(const dpic_ctx* c) { return consts_possible(c); }
 
 // copy a device array with channel stride NC into host [rows][1+ntan]
-void repack_out(const std::vector<double>& dev, size_t rows, int NC, int nt, double* out) {
+void repack_out(const double* dev, size_t rows, int NC, int nt, double* out) {
     for (size_t r = 0; r < rows; ++r)
         for (int ch = 0; ch <= nt; ++ch) out[r * (nt + 1) + ch] = dev[r * NC + ch];
 }
@@ -185,6 +193,208 @@ bool all_finite(const double* v, size_t n) {
     return true;
 }
 
+void clear_graphs(dpic_ctx* c) {
+    for (auto& g : c->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+}
+
+// Storage slots that settings with these particle counts need.
+int64_t slots_needed(const std::vector<int64_t>& nb) {
+    int64_t s = 0;
+    for (size_t b = 0; b < nb.size(); ++b) s += (b + 1 < nb.size()) ? seg_up(nb[b]) : nb[b];
+    return s;
+}
+
+// Per-setting table (offsets, packed-row shifts, charge per macroparticle)
+// and the segment owner table, uploaded synchronously.
+int upload_settings(dpic_ctx* c) {
+    const int B = c->B;
+    std::vector<SettingDev> t(B);
+    c->off.assign(B, 0);
+    int64_t slot = 0, packed = 0;
+    for (int b = 0; b < B; ++b) {
+        c->off[b] = slot;
+        t[b].off = slot;
+        t[b].n = c->nb[b];
+        t[b].delta = slot - packed;
+        t[b].q = c->nb[b] > 0 ? c->bunch_charge / (double)c->nb[b] : 0.0;
+        t[b].E = c->ws.E + (size_t)b * grid_nodes(c) * 3 * c->NC;
+        t[b].rho = c->ws.rho + (size_t)b * grid_nodes(c) * c->NC;
+        t[b].cnt = c->ws.counters + (size_t)b * CNT_N;
+        t[b].ec = c->ws.ec + (size_t)b * ec_stride(c);
+        packed += c->nb[b];
+        slot += seg_up(c->nb[b]);
+    }
+    c->n = packed;
+    c->used = B > 0 ? c->off[B - 1] + c->nb[B - 1] : 0;
+    const int64_t nseg = (c->used + SEG - 1) / SEG;
+    std::vector<int32_t> own((size_t)std::max<int64_t>(nseg, 1), 0);
+    for (int b = 0; b < B; ++b)
+        for (int64_t k = c->off[b] / SEG; k < (c->off[b] + c->nb[b] + SEG - 1) / SEG; ++k) own[(size_t)k] = b;
+    HIPCHK(c, hipMemcpyAsync(c->ws.set, t.data(), t.size() * sizeof(SettingDev), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->ws.owner, own.data(), own.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DPIC_OK;
+}
+
+void set_swapped(dpic_ctx* c, bool swapped) {
+    if (c->swapped != swapped) {
+        std::swap(c->ws.st, c->ws.st2);
+        std::swap(c->ws.pid, c->ws.pid2);
+        c->swapped = swapped;
+    }
+}
+
+// dpic_step from c->steps_done for n steps, launching on c->stream.
+int step_body(dpic_ctx* c, int n) {
+    const bool sc = c->bunch_charge != 0.0;
+    const int64_t s0 = c->steps_done, s1 = s0 + n;
+    const size_t rho_n = grid_nodes(c) * c->NC * c->B;
+    int r;
+    if (sc && c->sort_every > 0 && !c->chunks_valid)
+        if ((r = run_sort(c)) != DPIC_OK) return r;
+    if (c->adj.bound) {
+        // reverse-mode forward: unfused steps (the backward replays the same
+        // sequence), a checkpoint every K steps, no re-sorting (the adjoint
+        // follows the stored particle order)
+        HIPCHK(c, launch_zero(c, c->ws.rho, rho_n));
+        const size_t sbytes = (size_t)6 * c->dims.n_particles * sizeof(double);
+        for (int64_t s = s0; s < s1; ++s) {
+            if (s % c->adj.K == 0)
+                HIPCHK(c, hipMemcpyAsync(c->adj.ckpt + (size_t)(s / c->adj.K) * 6 * c->dims.n_particles, c->ws.st,
+                                         sbytes, hipMemcpyDeviceToDevice, c->stream));
+            if ((r = single_step(c, s, nullptr)) != DPIC_OK) return r;
+        }
+        c->steps_done = s1;
+        return DPIC_OK;
+    }
+    if (sc) {
+        HIPCHK(c, launch_zero(c, c->ws.rho, rho_n));
+        if ((r = run_particles(c, PF_MAP | PF_DEPOSIT, c->schedule[s0], ec_offset(c, c->schedule[s0], EC_HALF))) != DPIC_OK)
+            return r;
+        for (int64_t s = s0; s < s1; ++s) {
+            if ((r = run_solve_field(c)) != DPIC_OK) return r;
+            const bool last = (s == s1 - 1);
+            const int flags = PF_KICK | PF_MAP | (last ? 0 : PF_DEPOSIT);
+            if ((r = run_particles(c, flags, c->schedule[s], closing_map(c, s, last))) != DPIC_OK) return r;
+            if (c->sort_every > 0 && !last && ((s + 1) % c->sort_every) == 0)
+                if ((r = run_sort(c)) != DPIC_OK) return r;
+        }
+    } else {
+        if ((r = run_particles(c, PF_MAP | PF_COUNT, c->schedule[s0], ec_offset(c, c->schedule[s0], EC_HALF))) != DPIC_OK)
+            return r;
+        for (int64_t s = s0; s < s1; ++s) {
+            const bool last = (s == s1 - 1);
+            const int flags = PF_MAP | (last ? 0 : PF_COUNT);
+            if ((r = run_particles(c, flags, c->schedule[s], closing_map(c, s, last))) != DPIC_OK) return r;
+        }
+    }
+    c->steps_done = s1;
+    return DPIC_OK;
+}
+
+// Replay a captured run of the same call, or capture it: the host logic of
+// step_body runs once under stream capture on the context's own stream and
+// its end state is recorded, so replays only launch the graph and set that
+// state. Work is ordered on c->stream by launching the graph there.
+int step_graph(dpic_ctx* c, int n) {
+    for (auto& g : c->graphs) {
+        if (g.s0 == c->steps_done && g.n == n && g.swapped_in == c->swapped && g.chunks_in == c->chunks_valid &&
+            g.layout == c->layout_gen) {
+            HIPCHK(c, hipGraphLaunch(g.exec, c->stream));
+            set_swapped(c, g.swapped_out);
+            c->chunks_valid = g.chunks_out;
+            c->steps_done += n;
+            return DPIC_OK;
+        }
+    }
+    if (c->graphs.size() >= MAX_GRAPHS) clear_graphs(c);
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    GraphEntry ge;
+    ge.s0 = c->steps_done;
+    ge.n = n;
+    ge.swapped_in = c->swapped;
+    ge.chunks_in = c->chunks_valid;
+    ge.layout = c->layout_gen;
+    const Workspace ws0 = c->ws;
+    const bool sw0 = c->swapped, ck0 = c->chunks_valid;
+    const int64_t sd0 = c->steps_done;
+    hipStream_t orig = c->stream;
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    c->stream = c->cap_stream;
+    int r = step_body(c, n);
+    c->stream = orig;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+    if (r == DPIC_OK && e == hipSuccess && graph) e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (r != DPIC_OK || e != hipSuccess) {
+        // nothing ran: restore the host state of before the call
+        c->ws = ws0;
+        c->swapped = sw0;
+        c->chunks_valid = ck0;
+        c->steps_done = sd0;
+        if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
+        if (r != DPIC_OK) return r;
+        return fail(c, DPIC_EHIP, "step: graph capture failed: %s", hipGetErrorString(e));
+    }
+    ge.swapped_out = c->swapped;
+    ge.chunks_out = c->chunks_valid;
+    e = hipGraphLaunch(ge.exec, c->stream);
+    if (e != hipSuccess) {
+        (void)hipGraphExecDestroy(ge.exec);
+        c->ws = ws0;
+        c->swapped = sw0;
+        c->chunks_valid = ck0;
+        c->steps_done = sd0;
+        return fail(c, DPIC_EHIP, "step: graph launch failed: %s", hipGetErrorString(e));
+    }
+    c->graphs.push_back(ge);
+    return DPIC_OK;
+}
+
+int init_beams(dpic_ctx* c, const std::vector<int64_t>& nb, const double* xi_dev, const double* sigma,
+               const double* sigma_seed) {
+    const int NC = c->NC, nt = c->ntan, B = c->B;
+    int64_t total = 0;
+    for (int b = 0; b < B; ++b) {
+        if (nb[b] < 0) return fail(c, DPIC_EINVAL, "init_beam: n[%d] < 0", b);
+        total += nb[b];
+    }
+    if (slots_needed(nb) > c->dims.n_particles)
+        return fail(c, DPIC_EINVAL, "init_beam: %lld storage slots needed, capacity %lld",
+                    (long long)slots_needed(nb), (long long)c->dims.n_particles);
+    if (total > 0 && !xi_dev) return fail(c, DPIC_EINVAL, "init_beam: xi_dev is NULL");
+    std::vector<double> sd((size_t)B * 6 * NC, 0.0);
+    for (int b = 0; b < B; ++b)
+        for (int j = 0; j < 6; ++j) {
+            const double v = sigma[(size_t)b * 6 + j];
+            if (!isfinite(v)) return fail(c, DPIC_EINVAL, "init_beam: sigma[%d][%d] not finite", b, j);
+            sd[((size_t)b * 6 + j) * NC] = v;
+            if (sigma_seed)
+                for (int t = 0; t < nt; ++t) sd[((size_t)b * 6 + j) * NC + 1 + t] = sigma_seed[(size_t)j * nt + t];
+        }
+    if (nb != c->nb) {
+        c->nb = nb;
+        ++c->layout_gen;
+        clear_graphs(c);
+    }
+    int r;
+    if ((r = upload_settings(c)) != DPIC_OK) return r;
+    HIPCHK(c, hipMemcpyAsync(c->ws.sig, sd.data(), sd.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, launch_init_beam(c, xi_dev));
+    if (c->adj.bound && c->n > 0)  // the adjoint needs xi for d/dsigma
+        HIPCHK(c, hipMemcpyAsync(c->adj.xi, xi_dev, (size_t)c->n * 6 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, launch_zero(c, (double*)c->ws.counters, (size_t)CNT_N * B));
+    HIPCHK(c, launch_zero(c, c->ws.rho, grid_nodes(c) * NC * B));
+    c->steps_done = 0;
+    c->beam_init = true;
+    c->chunks_valid = false;
+    return DPIC_OK;
+}
+
 }  // namespace
 
 namespace dpic {
@@ -192,11 +402,13 @@ namespace dpic {
 size_t workspace_layout(const dpic_dims& d, char* base, Workspace* ws) {
     const int NC = channels_for(d.ntan);
     const int NCC = NC == 1 ? 1 : NC / 2;
+    const size_t B = (size_t)batch_of(d);
     const size_t cap = (size_t)d.n_particles;
     const size_t nx = d.nx, ny = d.ny, nz = d.nz;
     const size_t Mx = 2 * nx, My = 2 * ny, Mz = 2 * nz;
     const size_t W = Mx * NCC;
-    size_t fft = std::max({nz * ny * W, nz * My * W, (nz + 2) * My * W, (nz + 2) * (ny + 2) * W, Mx * My * Mz});
+    const size_t fft1 = std::max({nz * ny * W, nz * My * W, (nz + 2) * My * W, (nz + 2) * (ny + 2) * W});
+    const size_t fft = std::max(B * fft1, Mx * My * Mz);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -212,25 +424,28 @@ size_t workspace_layout(const dpic_dims& d, char* base, Workspace* ws) {
     size_t nbins = 1;
     for (size_t nd : {nx, ny, nz}) nbins *= (nd - 1 + TILE_EDGE - 1) / TILE_EDGE;
     nbins += 1;
-    const size_t sort_blocks = (cap + SORT_PB - 1) / SORT_PB;
-    const size_t ncount = nbins * sort_blocks;
+    const size_t segs = (cap + SEG - 1) / SEG;
+    const size_t ncount = nbins * segs;
     w.counts = (uint32_t*)take(ncount * sizeof(uint32_t));
     w.seg = (uint32_t*)take(((ncount + 1023) / 1024 + 1) * sizeof(uint32_t));
-    w.chunks = (int4*)take((nbins + (cap + TILE_CHUNK - 1) / TILE_CHUNK + 1) * sizeof(int4));
+    w.chunks = (int4*)take((std::min(B * nbins, cap) + cap / CHUNK_MIN + 1) * sizeof(int4));
     w.nchunks = (uint32_t*)take(sizeof(uint32_t));
-    w.rho = (double*)take(nx * ny * nz * NC * sizeof(double));
-    w.phi = (double*)take((nx + 2) * (ny + 2) * (nz + 2) * NC * sizeof(double));
-    w.E = (double*)take(nx * ny * nz * 3 * NC * sizeof(double));
+    w.set = (SettingDev*)take(B * sizeof(SettingDev));
+    w.owner = (int32_t*)take(segs * sizeof(int32_t));
+    w.sig = (double*)take(B * 6 * NC * sizeof(double));
+    w.rho = (double*)take(B * nx * ny * nz * NC * sizeof(double));
+    w.phi = (double*)take(B * (nx + 2) * (ny + 2) * (nz + 2) * NC * sizeof(double));
+    w.E = (double*)take(B * nx * ny * nz * 3 * NC * sizeof(double));
     w.buf0 = (double2*)take(fft * sizeof(double2));
     w.buf1 = (double2*)take(fft * sizeof(double2));
     w.ghat = (double*)take((nx + 1) * (ny + 1) * (nz + 1) * sizeof(double));
     w.tw = (double2*)take((Mx + My + Mz) * sizeof(double2));
-    w.ec = (double*)take((size_t)DPIC_MAX_ELEMENTS * EC_N * NC * sizeof(double));
-    w.elem_in = (double*)take((size_t)DPIC_MAX_ELEMENTS * 2 * NC * sizeof(double));
-    w.counters = (unsigned long long*)take(CNT_N * sizeof(unsigned long long));
-    w.mom_part = (double*)take((size_t)MOM_BLOCKS * MOM_N * NC * sizeof(double));
-    w.mom = (double*)take((size_t)MOM_N * NC * sizeof(double));
-    w.emit = (double*)take((size_t)6 * NC * sizeof(double));
+    w.ec = (double*)take(B * DPIC_MAX_ELEMENTS * EC_N * NC * sizeof(double));
+    w.elem_in = (double*)take(B * DPIC_MAX_ELEMENTS * 2 * NC * sizeof(double));
+    w.counters = (unsigned long long*)take(B * CNT_N * sizeof(unsigned long long));
+    w.mom_part = (double*)take(B * (size_t)mom_blocks_for((int)B) * MOM_N * NC * sizeof(double));
+    w.mom = (double*)take(B * MOM_N * NC * sizeof(double));
+    w.emit = (double*)take(B * 6 * NC * sizeof(double));
     w.bytes = off;
     if (ws) *ws = w;
     return off;
@@ -266,7 +481,7 @@ size_t adjoint_layout(const dpic_dims& d, int nmax, int K, char* base, AdjointWs
 
 extern "C" {
 
-int dpic_version(void) { return 10000; }
+int dpic_version(void) { return 10100; }
 
 int dpic_query_workspace(const dpic_dims* dims, size_t* bytes) {
     int r = check_dims(dims);
@@ -288,14 +503,24 @@ int dpic_create(const dpic_dims* dims, void* workspace_dev, size_t workspace_byt
     c->dims = *dims;
     c->ntan = dims->ntan;
     c->NC = channels_for(dims->ntan);
+    c->B = batch_of(*dims);
     c->stream = (hipStream_t)hip_stream;
+    c->nb.assign(c->B, 0);
+    c->p.clear();
     workspace_layout(*dims, (char*)workspace_dev, &c->ws);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        c->cu_count = 0;
+    (void)particle_resident_blocks(c);  // occupancy queries happen here, never under capture
     *out = c;
     return DPIC_OK;
 }
 
 int dpic_destroy(dpic_ctx* c) {
     if (!c) return DPIC_EINVAL;
+    clear_graphs(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto& pool : c->ev_pool)
         for (auto& pr : pool) {
             (void)hipEventDestroy(pr.first);
@@ -316,6 +541,7 @@ int dpic_set_beam(dpic_ctx* c, double kinetic_eV, double rest_eV, double charge_
     if (!(kinetic_eV > 0) || !(rest_eV > 0) || !isfinite(kinetic_eV) || !isfinite(rest_eV) || !isfinite(charge_e) ||
         !isfinite(bunch_charge_C))
         return fail(c, DPIC_EINVAL, "beam: energies must be positive and all values finite");
+    clear_graphs(c);
     c->gamma0 = 1.0 + kinetic_eV / rest_eV;
     c->beta0 = sqrt(1.0 - 1.0 / (c->gamma0 * c->gamma0));
     const double q_over_mc2 = charge_e / rest_eV;  // (q/e) / (mc^2 / e) in 1/V
@@ -327,6 +553,10 @@ int dpic_set_beam(dpic_ctx* c, double kinetic_eV, double rest_eV, double charge_
         HIPCHK(c, launch_green(c));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
+    if (c->beam_init) {
+        int r = upload_settings(c);  // charge per macroparticle
+        if (r != DPIC_OK) return r;
+    }
     return refresh_elements(c);
 }
 
@@ -334,9 +564,11 @@ int dpic_set_grid(dpic_ctx* c, const double lo[3], const double hi[3]) {
     if (!c || !lo || !hi) return DPIC_EINVAL;
     if (!c->beam_set) return fail(c, DPIC_ESTATE, "set_grid needs set_beam first (the kernel depends on gamma0)");
     const int n[3] = {c->dims.nx, c->dims.ny, c->dims.nz};
-    for (int d = 0; d < 3; ++d) {
+    for (int d = 0; d < 3; ++d)
         if (!isfinite(lo[d]) || !isfinite(hi[d]) || !(hi[d] > lo[d]))
             return fail(c, DPIC_EINVAL, "grid: need finite lo < hi in dimension %d", d);
+    clear_graphs(c);
+    for (int d = 0; d < 3; ++d) {
         c->lo[d] = lo[d];
         c->hi[d] = hi[d];
         c->h[d] = (hi[d] - lo[d]) / (double)(n[d] - 1);
@@ -367,6 +599,7 @@ int dpic_set_lattice(dpic_ctx* c, int n_elem, const int* kind, const int* n_step
     }
     total *= n_periods;
     if (total > (int64_t)100000000) return fail(c, DPIC_EINVAL, "lattice: schedule too long");
+    clear_graphs(c);
     c->n_elem = n_elem;
     c->n_periods = n_periods;
     c->kind.assign(kind, kind + n_elem);
@@ -389,46 +622,48 @@ int dpic_set_lattice(dpic_ctx* c, int n_elem, const int* kind, const int* n_step
     return refresh_elements(c);
 }
 
-int dpic_set_params(dpic_ctx* c, int np, const double* p, const double* seed) {
+int dpic_set_params_batch(dpic_ctx* c, int nb, int np, const double* p, const double* seed) {
     if (!c) return DPIC_EINVAL;
+    if (nb != c->B) return fail(c, DPIC_EINVAL, "params: %d settings given, the context has %d", nb, c->B);
     if (np < 0 || np > DPIC_MAX_PARAMS || (np > 0 && !p)) return fail(c, DPIC_EINVAL, "params: 0..%d values", DPIC_MAX_PARAMS);
     const int nt = c->ntan;
-    c->p.assign(p, p + np);
-    c->seed.assign((size_t)np * nt, 0.0);
-    for (int j = 0; j < np; ++j) {
-        if (!isfinite(p[j])) return fail(c, DPIC_EINVAL, "params: p[%d] not finite", j);
+    for (size_t i = 0; i < (size_t)nb * np; ++i)
+        if (!isfinite(p[i])) return fail(c, DPIC_EINVAL, "params: p[%zu] not finite", i);
+    std::vector<double> sd((size_t)np * nt, 0.0);
+    for (int j = 0; j < np; ++j)
         for (int t = 0; t < nt; ++t) {
             const double v = seed ? seed[(size_t)j * nt + t] : (j == t ? 1.0 : 0.0);
             if (!isfinite(v)) return fail(c, DPIC_EINVAL, "params: seed[%d][%d] not finite", j, t);
-            c->seed[(size_t)j * nt + t] = v;
+            sd[(size_t)j * nt + t] = v;
         }
-    }
+    c->np = np;
+    c->p.assign(p, p + (size_t)nb * np);
+    c->seed = sd;
     c->params_set = true;
     return refresh_elements(c);
 }
 
+int dpic_set_params(dpic_ctx* c, int np, const double* p, const double* seed) {
+    if (!c) return DPIC_EINVAL;
+    if (np < 0 || np > DPIC_MAX_PARAMS || (np > 0 && !p)) return fail(c, DPIC_EINVAL, "params: 0..%d values", DPIC_MAX_PARAMS);
+    std::vector<double> all((size_t)c->B * np);
+    for (int b = 0; b < c->B; ++b)
+        for (int j = 0; j < np; ++j) all[(size_t)b * np + j] = p[j];
+    return dpic_set_params_batch(c, c->B, np, all.data(), seed);
+}
+
 int dpic_init_beam(dpic_ctx* c, int64_t n, const double* xi_dev, const double sigma[6], const double* sigma_seed) {
     if (!c || !sigma) return DPIC_EINVAL;
+    if (c->B != 1) return fail(c, DPIC_ESTATE, "init_beam: the context holds %d settings; use init_beam_batch", c->B);
     if (n < 0 || n > c->dims.n_particles) return fail(c, DPIC_EINVAL, "init_beam: n=%lld outside 0..capacity", (long long)n);
-    if (n > 0 && !xi_dev) return fail(c, DPIC_EINVAL, "init_beam: xi_dev is NULL");
-    const int NC = c->NC, nt = c->ntan;
-    std::vector<double> sd((size_t)6 * NC, 0.0);
-    for (int j = 0; j < 6; ++j) {
-        if (!isfinite(sigma[j])) return fail(c, DPIC_EINVAL, "init_beam: sigma[%d] not finite", j);
-        sd[(size_t)j * NC] = sigma[j];
-        if (sigma_seed)
-            for (int t = 0; t < nt; ++t) sd[(size_t)j * NC + 1 + t] = sigma_seed[(size_t)j * nt + t];
-    }
-    c->n = n;
-    HIPCHK(c, launch_init_beam(c, xi_dev, sd.data()));
-    if (c->adj.bound && n > 0)  // the adjoint needs xi for d/dsigma
-        HIPCHK(c, hipMemcpyAsync(c->adj.xi, xi_dev, (size_t)n * 6 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, launch_zero(c, (double*)c->ws.counters, CNT_N));
-    HIPCHK(c, launch_zero(c, c->ws.rho, (size_t)c->dims.nx * c->dims.ny * c->dims.nz * NC));
-    c->steps_done = 0;
-    c->beam_init = true;
-    c->chunks_valid = false;
-    return DPIC_OK;
+    return init_beams(c, std::vector<int64_t>{n}, xi_dev, sigma, sigma_seed);
+}
+
+int dpic_init_beam_batch(dpic_ctx* c, int nb, const int64_t* n, const double* xi_dev, const double* sigma,
+                         const double* sigma_seed) {
+    if (!c || !n || !sigma) return DPIC_EINVAL;
+    if (nb != c->B) return fail(c, DPIC_EINVAL, "init_beam_batch: %d settings given, the context has %d", nb, c->B);
+    return init_beams(c, std::vector<int64_t>(n, n + nb), xi_dev, sigma, sigma_seed);
 }
 
 int dpic_step(dpic_ctx* c, int n) {
@@ -442,60 +677,21 @@ int dpic_step(dpic_ctx* c, int n) {
     if (c->steps_done + n > (int64_t)c->schedule.size())
         return fail(c, DPIC_EINVAL, "step: %d steps from %lld exceed the schedule of %zu", n, (long long)c->steps_done,
                     c->schedule.size());
-    const int64_t s0 = c->steps_done, s1 = s0 + n;
-    int r;
-    if (sc && c->sort_every > 0 && !c->chunks_valid)
-        if ((r = run_sort(c)) != DPIC_OK) return r;
-    if (c->adj.bound) {
-        // reverse-mode forward: unfused steps (the backward replays the same
-        // sequence), a checkpoint every K steps, no re-sorting (the adjoint
-        // follows the stored particle order)
-        if (s1 > c->adj.nmax) return fail(c, DPIC_EINVAL, "step: the adjoint workspace covers %d steps", c->adj.nmax);
-        HIPCHK(c, launch_zero(c, c->ws.rho, (size_t)c->dims.nx * c->dims.ny * c->dims.nz * c->NC));
-        const size_t sbytes = (size_t)6 * c->dims.n_particles * sizeof(double);
-        for (int64_t s = s0; s < s1; ++s) {
-            if (s % c->adj.K == 0)
-                HIPCHK(c, hipMemcpyAsync(c->adj.ckpt + (size_t)(s / c->adj.K) * 6 * c->dims.n_particles, c->ws.st,
-                                         sbytes, hipMemcpyDeviceToDevice, c->stream));
-            if ((r = single_step(c, s, nullptr)) != DPIC_OK) return r;
-        }
-        c->steps_done = s1;
-        return DPIC_OK;
-    }
-    if (sc) {
-        HIPCHK(c, launch_zero(c, c->ws.rho, (size_t)c->dims.nx * c->dims.ny * c->dims.nz * c->NC));
-        const double* first = element_map_block(c, c->schedule[s0], EC_HALF);
-        if ((r = run_particles(c, PF_MAP | PF_DEPOSIT, c->schedule[s0], first)) != DPIC_OK) return r;
-        for (int64_t s = s0; s < s1; ++s) {
-            if ((r = run_solve_field(c)) != DPIC_OK) return r;
-            const bool last = (s == s1 - 1);
-            const int flags = PF_KICK | PF_MAP | (last ? 0 : PF_DEPOSIT);
-            if ((r = run_particles(c, flags, c->schedule[s], closing_map(c, s, last))) != DPIC_OK) return r;
-            if (c->sort_every > 0 && !last && ((s + 1) % c->sort_every) == 0)
-                if ((r = run_sort(c)) != DPIC_OK) return r;
-        }
-    } else {
-        const double* first = element_map_block(c, c->schedule[s0], EC_HALF);
-        if ((r = run_particles(c, PF_MAP | PF_COUNT, c->schedule[s0], first)) != DPIC_OK) return r;
-        for (int64_t s = s0; s < s1; ++s) {
-            const bool last = (s == s1 - 1);
-            const int flags = PF_MAP | (last ? 0 : PF_COUNT);
-            if ((r = run_particles(c, flags, c->schedule[s], closing_map(c, s, last))) != DPIC_OK) return r;
-        }
-    }
-    c->steps_done = s1;
-    return DPIC_OK;
+    if (c->adj.bound && c->steps_done + n > c->adj.nmax)
+        return fail(c, DPIC_EINVAL, "step: the adjoint workspace covers %d steps", c->adj.nmax);
+    if (c->use_graph && !c->stage_timing && !c->adj.bound) return step_graph(c, n);
+    return step_body(c, n);
 }
 
 int dpic_read_moments(dpic_ctx* c, double* out) {
     if (!c || !out) return DPIC_EINVAL;
     if (!c->beam_init) return fail(c, DPIC_ESTATE, "read_moments: no beam");
     HIPCHK(c, launch_moments(c));
-    std::vector<double> h((size_t)MOM_N * c->NC);
+    std::vector<double> h((size_t)c->B * MOM_N * c->NC);
     HIPCHK(c, hipMemcpyAsync(h.data(), c->ws.mom, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    repack_out(h, MOM_N, c->NC, c->ntan, out);
-    if (!all_finite(out, (size_t)MOM_N * (c->ntan + 1))) return fail(c, DPIC_ENONFINITE, "read_moments: non-finite moment");
+    repack_out(h.data(), (size_t)c->B * MOM_N, c->NC, c->ntan, out);
+    if (!all_finite(out, (size_t)c->B * MOM_N * (c->ntan + 1))) return fail(c, DPIC_ENONFINITE, "read_moments: non-finite moment");
     return DPIC_OK;
 }
 
@@ -503,12 +699,20 @@ int dpic_read_emittance(dpic_ctx* c, int centred, double* out) {
     if (!c || !out) return DPIC_EINVAL;
     if (!c->beam_init) return fail(c, DPIC_ESTATE, "read_emittance: no beam");
     HIPCHK(c, launch_moments(c));
-    std::vector<double> h((size_t)6 * c->NC);
+    const int NC = c->NC;
+    std::vector<double> h((size_t)c->B * 6 * NC);
     HIPCHK(c, hipMemcpyAsync(h.data(), c->ws.emit, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    std::vector<double> part(h.begin() + (centred ? 3 * c->NC : 0), h.begin() + (centred ? 6 : 3) * c->NC);
-    repack_out(part, 3, c->NC, c->ntan, out);
-    if (!all_finite(out, (size_t)3 * (c->ntan + 1))) return fail(c, DPIC_ENONFINITE, "read_emittance: non-finite emittance");
+    const size_t per = (size_t)3 * (c->ntan + 1);
+    for (int b = 0; b < c->B; ++b) {
+        double* o = out + (size_t)b * per;
+        if (c->nb[b] == 0) {  // an empty setting reports zeros
+            for (size_t i = 0; i < per; ++i) o[i] = 0.0;
+            continue;
+        }
+        repack_out(h.data() + ((size_t)b * 6 + (centred ? 3 : 0)) * NC, 3, NC, c->ntan, o);
+        if (!all_finite(o, per)) return fail(c, DPIC_ENONFINITE, "read_emittance: non-finite emittance in setting %d", b);
+    }
     return DPIC_OK;
 }
 
@@ -520,19 +724,40 @@ int dpic_read_particles(dpic_ctx* c, double* out) {
     std::vector<double> h((size_t)c->n * 6 * c->NC);
     HIPCHK(c, hipMemcpyAsync(h.data(), c->ws.st2, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    repack_out(h, (size_t)c->n * 6, c->NC, c->ntan, out);
+    repack_out(h.data(), (size_t)c->n * 6, c->NC, c->ntan, out);
     return DPIC_OK;
 }
 
 int dpic_counters(dpic_ctx* c, int64_t* out_of_box, int64_t* steps_done, double* extent) {
     if (!c) return DPIC_EINVAL;
-    unsigned long long h[CNT_N];
-    HIPCHK(c, hipMemcpyAsync(h, c->ws.counters, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    std::vector<unsigned long long> h((size_t)c->B * CNT_N);
+    HIPCHK(c, hipMemcpyAsync(h.data(), c->ws.counters, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                             c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (out_of_box) *out_of_box = (int64_t)h[CNT_OUTSIDE];
+    int64_t outside = 0;
+    double ext[3] = {0, 0, 0};
+    for (int b = 0; b < c->B; ++b) {
+        outside += (int64_t)h[(size_t)b * CNT_N + CNT_OUTSIDE];
+        for (int d = 0; d < 3; ++d) {
+            double v;
+            memcpy(&v, &h[(size_t)b * CNT_N + CNT_EXT_X + d], sizeof(double));
+            ext[d] = std::max(ext[d], v);
+        }
+    }
+    if (out_of_box) *out_of_box = outside;
     if (steps_done) *steps_done = c->steps_done;
     if (extent)
-        for (int d = 0; d < 3; ++d) memcpy(&extent[d], &h[CNT_EXT_X + d], sizeof(double));
+        for (int d = 0; d < 3; ++d) extent[d] = ext[d];
+    return DPIC_OK;
+}
+
+int dpic_batch_counters(dpic_ctx* c, int64_t* out_of_box) {
+    if (!c || !out_of_box) return DPIC_EINVAL;
+    std::vector<unsigned long long> h((size_t)c->B * CNT_N);
+    HIPCHK(c, hipMemcpyAsync(h.data(), c->ws.counters, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int b = 0; b < c->B; ++b) out_of_box[b] = (int64_t)h[(size_t)b * CNT_N + CNT_OUTSIDE];
     return DPIC_OK;
 }
 
@@ -541,8 +766,8 @@ int dpic_stage(dpic_ctx* c, int stage) {
     switch (stage) {
         case DPIC_STAGE_DEPOSIT:
             if (!c->beam_init || !c->grid_set) return fail(c, DPIC_ESTATE, "stage deposit: needs beam and grid");
-            HIPCHK(c, launch_zero(c, c->ws.rho, (size_t)c->dims.nx * c->dims.ny * c->dims.nz * c->NC));
-            HIPCHK(c, launch_particles(c, PF_DEPOSIT, 0, nullptr, false));
+            HIPCHK(c, launch_zero(c, c->ws.rho, grid_nodes(c) * c->NC * c->B));
+            HIPCHK(c, launch_particles(c, PF_DEPOSIT, 0, 0, false));
             return DPIC_OK;
         case DPIC_STAGE_SOLVE:
             if (!c->grid_set) return fail(c, DPIC_ESTATE, "stage solve: needs grid");
@@ -557,12 +782,12 @@ int dpic_stage(dpic_ctx* c, int stage) {
     }
 }
 
-static int grid_geom(const dpic_ctx* c, int which, double** dev, size_t* rows, int* per_row) {
-    const size_t nx = c->dims.nx, ny = c->dims.ny, nz = c->dims.nz;
+static int grid_geom(const dpic_ctx* c, int which, double** dev, size_t* rows) {
+    const size_t nx = c->dims.nx, ny = c->dims.ny, nz = c->dims.nz, B = c->B;
     switch (which) {
-        case DPIC_GRID_RHO: *dev = c->ws.rho; *rows = nx * ny * nz; *per_row = 1; return DPIC_OK;
-        case DPIC_GRID_PHI: *dev = c->ws.phi; *rows = (nx + 2) * (ny + 2) * (nz + 2); *per_row = 1; return DPIC_OK;
-        case DPIC_GRID_E: *dev = c->ws.E; *rows = nx * ny * nz * 3; *per_row = 1; return DPIC_OK;
+        case DPIC_GRID_RHO: *dev = c->ws.rho; *rows = B * nx * ny * nz; return DPIC_OK;
+        case DPIC_GRID_PHI: *dev = c->ws.phi; *rows = B * (nx + 2) * (ny + 2) * (nz + 2); return DPIC_OK;
+        case DPIC_GRID_E: *dev = c->ws.E; *rows = B * nx * ny * nz * 3; return DPIC_OK;
         default: return DPIC_EINVAL;
     }
 }
@@ -571,12 +796,11 @@ int dpic_read_grid(dpic_ctx* c, int which, double* out) {
     if (!c || !out) return DPIC_EINVAL;
     double* dev;
     size_t rows;
-    int per;
-    if (grid_geom(c, which, &dev, &rows, &per) != DPIC_OK) return fail(c, DPIC_EINVAL, "read_grid: unknown array %d", which);
+    if (grid_geom(c, which, &dev, &rows) != DPIC_OK) return fail(c, DPIC_EINVAL, "read_grid: unknown array %d", which);
     std::vector<double> h(rows * c->NC);
     HIPCHK(c, hipMemcpyAsync(h.data(), dev, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    repack_out(h, rows, c->NC, c->ntan, out);
+    repack_out(h.data(), rows, c->NC, c->ntan, out);
     return DPIC_OK;
 }
 
@@ -584,8 +808,7 @@ int dpic_write_grid(dpic_ctx* c, int which, const double* in) {
     if (!c || !in) return DPIC_EINVAL;
     double* dev;
     size_t rows;
-    int per;
-    if (grid_geom(c, which, &dev, &rows, &per) != DPIC_OK) return fail(c, DPIC_EINVAL, "write_grid: unknown array %d", which);
+    if (grid_geom(c, which, &dev, &rows) != DPIC_OK) return fail(c, DPIC_EINVAL, "write_grid: unknown array %d", which);
     const int NC = c->NC, nt = c->ntan;
     std::vector<double> h(rows * NC, 0.0);
     for (size_t r = 0; r < rows; ++r)
@@ -595,11 +818,18 @@ int dpic_write_grid(dpic_ctx* c, int which, const double* in) {
     return DPIC_OK;
 }
 
-// checkpoint layout: int64 header[2] = {n, steps_done}, pid[cap] (int32), state [6][cap][NC]
+// checkpoint layout: int64 header[4] = {magic, B, steps_done, 0}, int64 n[B],
+// then (256-aligned) pid[cap] (int32), then (256-aligned) state [6][cap][NC]
+static const int64_t STATE_MAGIC = 0x6470696373743031ll;
+
+static size_t state_pid_off(const dpic_ctx* c) { return align_up(32 + (size_t)c->B * 8); }
+static size_t state_st_off(const dpic_ctx* c) {
+    return align_up(state_pid_off(c) + (size_t)c->dims.n_particles * sizeof(int32_t));
+}
+
 int dpic_state_bytes(const dpic_ctx* c, size_t* bytes) {
     if (!c || !bytes) return DPIC_EINVAL;
-    const size_t cap = (size_t)c->dims.n_particles;
-    *bytes = align_up(16 + cap * sizeof(int32_t)) + 6 * cap * c->NC * sizeof(double);
+    *bytes = state_st_off(c) + 6 * (size_t)c->dims.n_particles * c->NC * sizeof(double);
     return DPIC_OK;
 }
 
@@ -607,12 +837,16 @@ int dpic_save_state(dpic_ctx* c, void* dev_buf) {
     if (!c || !dev_buf) return DPIC_EINVAL;
     if (!c->beam_init) return fail(c, DPIC_ESTATE, "save_state: no beam");
     const size_t cap = (size_t)c->dims.n_particles;
-    int64_t hdr[2] = {c->n, c->steps_done};
+    std::vector<int64_t> hdr(4 + c->B, 0);
+    hdr[0] = STATE_MAGIC;
+    hdr[1] = c->B;
+    hdr[2] = c->steps_done;
+    for (int b = 0; b < c->B; ++b) hdr[4 + b] = c->nb[b];
     char* b = (char*)dev_buf;
-    HIPCHK(c, hipMemcpyAsync(b, hdr, sizeof hdr, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(b + 16, c->ws.pid, cap * sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(b + align_up(16 + cap * sizeof(int32_t)), c->ws.st, 6 * cap * c->NC * sizeof(double),
-                             hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(b, hdr.data(), hdr.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(b + state_pid_off(c), c->ws.pid, cap * sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(b + state_st_off(c), c->ws.st, 6 * cap * c->NC * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return DPIC_OK;
 }
@@ -620,18 +854,28 @@ int dpic_save_state(dpic_ctx* c, void* dev_buf) {
 int dpic_load_state(dpic_ctx* c, const void* dev_buf) {
     if (!c || !dev_buf) return DPIC_EINVAL;
     const size_t cap = (size_t)c->dims.n_particles;
-    int64_t hdr[2];
+    std::vector<int64_t> hdr(4 + c->B, 0);
     const char* b = (const char*)dev_buf;
-    HIPCHK(c, hipMemcpyAsync(hdr, b, sizeof hdr, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(hdr.data(), b, hdr.size() * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (hdr[0] < 0 || hdr[0] > c->dims.n_particles || hdr[1] < 0)
+    if (hdr[0] != STATE_MAGIC || hdr[1] != c->B || hdr[2] < 0)
         return fail(c, DPIC_EINVAL, "load_state: buffer does not hold a checkpoint of this context");
-    HIPCHK(c, hipMemcpyAsync(c->ws.pid, b + 16, cap * sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->ws.st, b + align_up(16 + cap * sizeof(int32_t)), 6 * cap * c->NC * sizeof(double),
-                             hipMemcpyDeviceToDevice, c->stream));
+    std::vector<int64_t> nb(hdr.begin() + 4, hdr.end());
+    for (int64_t v : nb)
+        if (v < 0) return fail(c, DPIC_EINVAL, "load_state: bad particle count");
+    if (slots_needed(nb) > c->dims.n_particles) return fail(c, DPIC_EINVAL, "load_state: checkpoint exceeds the capacity");
+    if (nb != c->nb) {
+        c->nb = nb;
+        ++c->layout_gen;
+        clear_graphs(c);
+    }
+    int r;
+    if ((r = upload_settings(c)) != DPIC_OK) return r;
+    HIPCHK(c, hipMemcpyAsync(c->ws.pid, b + state_pid_off(c), cap * sizeof(int32_t), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->ws.st, b + state_st_off(c), 6 * cap * c->NC * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->n = hdr[0];
-    c->steps_done = hdr[1];
+    c->steps_done = hdr[2];
     c->beam_init = true;
     c->chunks_valid = false;
     return DPIC_OK;
@@ -642,13 +886,44 @@ int dpic_set_option(dpic_ctx* c, int option, int64_t value) {
     switch (option) {
         case DPIC_OPT_SORT_EVERY:
             if (value < 0) return fail(c, DPIC_EINVAL, "sort_every must be >= 0");
+            if (value != c->sort_every) clear_graphs(c);
             c->sort_every = value;
             return DPIC_OK;
         case DPIC_OPT_STAGE_TIMING:
             c->stage_timing = value != 0;
             return DPIC_OK;
+        case DPIC_OPT_CHUNK:
+            if (value < CHUNK_MIN || value > CHUNK_MAX || value % 64 != 0)
+                return fail(c, DPIC_EINVAL, "chunk must be a multiple of 64 in %d..%d", CHUNK_MIN, CHUNK_MAX);
+            if (value != c->chunk) {
+                clear_graphs(c);
+                c->chunks_valid = false;  // the work list is cut with the old size
+            }
+            c->chunk = value;
+            return DPIC_OK;
+        case DPIC_OPT_PART_BLOCKS:
+            if (value < 0 || value > (1 << 20)) return fail(c, DPIC_EINVAL, "part_blocks must be in 0..2^20");
+            if (value != c->part_blocks) clear_graphs(c);
+            c->part_blocks = value;
+            return DPIC_OK;
+        case DPIC_OPT_GRAPH:
+            c->use_graph = value != 0;
+            if (!c->use_graph) clear_graphs(c);
+            return DPIC_OK;
         default:
             return fail(c, DPIC_EINVAL, "unknown option %d", option);
+    }
+}
+
+int dpic_get_option(const dpic_ctx* c, int option, int64_t* value) {
+    if (!c || !value) return DPIC_EINVAL;
+    switch (option) {
+        case DPIC_OPT_SORT_EVERY: *value = c->sort_every; return DPIC_OK;
+        case DPIC_OPT_STAGE_TIMING: *value = c->stage_timing; return DPIC_OK;
+        case DPIC_OPT_CHUNK: *value = c->chunk; return DPIC_OK;
+        case DPIC_OPT_PART_BLOCKS: *value = c->part_blocks; return DPIC_OK;
+        case DPIC_OPT_GRAPH: *value = c->use_graph; return DPIC_OK;
+        default: return DPIC_EINVAL;
     }
 }
 
@@ -670,16 +945,103 @@ int dpic_stage_times(dpic_ctx* c, double* ms, int64_t* launches) {
     return DPIC_OK;
 }
 
+int dpic_autotune(dpic_ctx* c, void* scratch, size_t scratch_bytes, int trial_steps, int64_t* best, double* ms_best) {
+    if (!c || !scratch) return DPIC_EINVAL;
+    size_t need = 0;
+    dpic_state_bytes(c, &need);
+    if (scratch_bytes < need) return fail(c, DPIC_EINVAL, "autotune: scratch needs %zu bytes", need);
+    if (((uintptr_t)scratch) % ALIGN != 0) return fail(c, DPIC_EINVAL, "autotune: scratch not 256-byte aligned");
+    if (!c->beam_init || !c->grid_set || c->bunch_charge == 0.0 || !elements_ready(c))
+        return fail(c, DPIC_ESTATE, "autotune: needs a space-charge run ready to step");
+    if (c->adj.bound) return fail(c, DPIC_ESTATE, "autotune: not with the adjoint bound");
+    if (trial_steps < 1 || c->steps_done + trial_steps > (int64_t)c->schedule.size())
+        return fail(c, DPIC_EINVAL, "autotune: %d trial steps do not fit the schedule", trial_steps);
+    int r;
+    std::vector<unsigned long long> cnt((size_t)c->B * CNT_N);
+    HIPCHK(c, hipMemcpyAsync(cnt.data(), c->ws.counters, cnt.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    if ((r = dpic_save_state(c, scratch)) != DPIC_OK) return r;
+    const bool graph0 = c->use_graph, timing0 = c->stage_timing;
+    c->use_graph = false;
+    c->stage_timing = false;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    auto trial = [&](int64_t se, int64_t ch, int64_t pb, double* ms) -> int {
+        int rr;
+        if ((rr = dpic_set_option(c, DPIC_OPT_SORT_EVERY, se)) != DPIC_OK) return rr;
+        if ((rr = dpic_set_option(c, DPIC_OPT_CHUNK, ch)) != DPIC_OK) return rr;
+        if ((rr = dpic_set_option(c, DPIC_OPT_PART_BLOCKS, pb)) != DPIC_OK) return rr;
+        if ((rr = dpic_load_state(c, scratch)) != DPIC_OK) return rr;
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        if ((rr = step_body(c, trial_steps)) != DPIC_OK) return rr;
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float t = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&t, e0, e1));
+        *ms = t;
+        return DPIC_OK;
+    };
+    int64_t se = c->sort_every > 0 ? c->sort_every : 20, ch = c->chunk, pb = c->part_blocks;
+    double bms = 0.0, t = 0.0;
+    const int64_t resident = particle_resident_blocks(c);
+    r = trial(se, ch, pb, &t);  // warm-up, then the incumbent
+    if (r == DPIC_OK) r = trial(se, ch, pb, &bms);
+    for (int64_t v : {256, 512, 1024, 2048}) {
+        if (r != DPIC_OK || v == ch) continue;
+        if ((r = trial(se, v, pb, &t)) == DPIC_OK && t < bms) {
+            bms = t;
+            ch = v;
+        }
+    }
+    for (int64_t v : {resident / 2, resident, 2 * resident, 4 * resident}) {
+        const int64_t cur = pb == 0 ? resident : pb;
+        if (r != DPIC_OK || v < 1 || v == cur) continue;
+        if ((r = trial(se, ch, v, &t)) == DPIC_OK && t < bms) {
+            bms = t;
+            pb = v;
+        }
+    }
+    for (int64_t v : {5, 10, 20, 40}) {
+        if (r != DPIC_OK || v == se) continue;
+        if ((r = trial(v, ch, pb, &t)) == DPIC_OK && t < bms) {
+            bms = t;
+            se = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // restore the state and counters, keep the winner
+    int r2 = dpic_set_option(c, DPIC_OPT_SORT_EVERY, se);
+    if (r2 == DPIC_OK) r2 = dpic_set_option(c, DPIC_OPT_CHUNK, ch);
+    if (r2 == DPIC_OK) r2 = dpic_set_option(c, DPIC_OPT_PART_BLOCKS, pb);
+    if (r2 == DPIC_OK) r2 = dpic_load_state(c, scratch);
+    c->use_graph = graph0;
+    c->stage_timing = timing0;
+    if (r != DPIC_OK) return r;
+    if (r2 != DPIC_OK) return r2;
+    HIPCHK(c, hipMemcpyAsync(c->ws.counters, cnt.data(), cnt.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (best) {
+        best[0] = se;
+        best[1] = ch;
+        best[2] = pb;
+    }
+    if (ms_best) *ms_best = bms;
+    return DPIC_OK;
+}
+
 int dpic_adjoint_query(const dpic_dims* dims, int n_steps, int checkpoint_every, size_t* bytes) {
     int r = check_dims(dims);
     if (r != DPIC_OK) return r;
     if (!bytes || dims->ntan != 0 || n_steps < 1 || checkpoint_every < 1) return DPIC_EINVAL;
+    if (batch_of(*dims) != 1) return DPIC_EUNSUPPORTED;
     *bytes = adjoint_layout(*dims, n_steps, checkpoint_every, nullptr, nullptr);
     return DPIC_OK;
 }
 
 int dpic_adjoint_bind(dpic_ctx* c, void* adj_dev, size_t bytes, int n_steps, int checkpoint_every) {
     if (!c || !adj_dev) return DPIC_EINVAL;
+    if (c->B != 1) return fail(c, DPIC_EUNSUPPORTED, "adjoint: one setting per context");
     if (c->ntan != 0) return fail(c, DPIC_EINVAL, "adjoint: the context must be value-only (ntan = 0)");
     if (n_steps < 1 || checkpoint_every < 1) return fail(c, DPIC_EINVAL, "adjoint: n_steps and checkpoint_every >= 1");
     if (((uintptr_t)adj_dev) % ALIGN != 0) return fail(c, DPIC_EINVAL, "adjoint: workspace not 256-byte aligned");
@@ -688,6 +1050,7 @@ int dpic_adjoint_bind(dpic_ctx* c, void* adj_dev, size_t bytes, int n_steps, int
     adjoint_layout(c->dims, n_steps, checkpoint_every, (char*)adj_dev, &c->adj);
     c->adj.bound = true;
     c->beam_init = false;  // the initial normals must be captured by init_beam
+    clear_graphs(c);
     return DPIC_OK;
 }
 
@@ -695,13 +1058,13 @@ int dpic_adjoint_backward(dpic_ctx* c, const double w[3], double* grad_params, d
     if (!c || !w) return DPIC_EINVAL;
     if (!c->adj.bound) return fail(c, DPIC_ESTATE, "backward: no adjoint workspace bound");
     if (!c->beam_init) return fail(c, DPIC_ESTATE, "backward: no forward run to differentiate");
-    const int np = (int)c->p.size();
+    const int np = c->np;
     if (np > 15) return fail(c, DPIC_EUNSUPPORTED, "backward: at most 15 parameters");
     for (int k = 0; k < 3; ++k)
         if (!isfinite(w[k])) return fail(c, DPIC_EINVAL, "backward: non-finite weight");
     const bool sc = c->bunch_charge != 0.0;
     const size_t cap = (size_t)c->dims.n_particles;
-    const size_t nodes = (size_t)c->dims.nx * c->dims.ny * c->dims.nz;
+    const size_t nodes = grid_nodes(c);
     unsigned long long cnt[CNT_N];
     HIPCHK(c, hipMemcpyAsync(cnt, c->ws.counters, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -726,7 +1089,7 @@ int dpic_adjoint_backward(dpic_ctx* c, const double w[3], double* grad_params, d
                                       c->adj.fields + (size_t)(s - sa) * 3 * nodes, sc));
     }
     // element constants with one tangent per parameter (identity seeds)
-    std::vector<double> in((size_t)c->n_elem * 2 * 16, 0.0);
+    std::vector<double> in((size_t)DPIC_MAX_ELEMENTS * 2 * 16, 0.0);
     for (int e = 0; e < c->n_elem; ++e) {
         double* Ld = &in[(size_t)(e * 2 + 0) * 16];
         double* kd = &in[(size_t)(e * 2 + 1) * 16];
@@ -739,7 +1102,7 @@ int dpic_adjoint_backward(dpic_ctx* c, const double w[3], double* grad_params, d
         }
     }
     HIPCHK(c, hipMemcpyAsync(c->adj.elem_in_dual, in.data(), in.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, launch_element_consts_into(c, 16, c->adj.elem_in_dual, c->adj.ec_dual));
+    HIPCHK(c, launch_element_consts_into(c, 16, 1, c->adj.elem_in_dual, c->adj.ec_dual));
     c->adj.ncd = 16;
     HIPCHK(c, launch_adj_finish(c, np));
     std::vector<double> g(DPIC_MAX_PARAMS + 6);

@@ -1,5 +1,12 @@
 // Host-side context of the dpic library and the launchers each kernel file
 // exports to the C-ABI layer.
+//
+// A context holds B >= 1 independent settings (lattice parameter points and
+// beams) that share the grid, the beam energy, the bunch charge and the
+// lattice structure. Every stage launch covers all settings: particle
+// storage is one array whose setting b occupies slots [off_b, off_b + n_b),
+// off_b a multiple of SEG, and every grid array carries a leading setting
+// index. With B = 1 the layout is the plain single-run layout.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,29 +21,47 @@
 
 namespace dpic {
 
+constexpr int SEG = 1024;  // storage segment: settings start on segment boundaries
+
+// Per-setting device record (the particle kernels take a setting's arrays
+// from here, which keeps their bases out of the kernel arguments).
+struct SettingDev {
+    int64_t off;    // first storage slot (multiple of SEG)
+    int64_t n;      // macroparticles
+    int64_t delta;  // off minus the particles of earlier settings: packed row = slot - delta
+    double q;       // charge per macroparticle, bunch charge / n
+    const double* E;           // the setting's field [nz][ny][nx][3][NC]
+    double* rho;               // its node charges [nz][ny][nx][NC]
+    unsigned long long* cnt;   // its counters [CNT_N]
+    const double* ec;          // its element constants [MAX_ELEM][EC_N][NC]
+};
+
 struct Workspace {
     double* st = nullptr;      // particle state [6][cap][NC]
     double* st2 = nullptr;     // second state buffer (sort target, read-back staging)
-    int32_t* pid = nullptr;    // original index of each stored particle
+    int32_t* pid = nullptr;    // packed original row of each stored particle
     int32_t* pid2 = nullptr;
     uint32_t* key = nullptr;     // sort keys
-    uint32_t* counts = nullptr;  // per (bin, block) counts, then offsets
+    uint32_t* counts = nullptr;  // per (setting, bin, segment) counts, then offsets
     uint32_t* seg = nullptr;     // scan segment sums
-    int4* chunks = nullptr;      // tiled work list (tile, first, count, -)
+    int4* chunks = nullptr;      // tiled work list (tile, first, count, setting)
     uint32_t* nchunks = nullptr;
-    double* rho = nullptr;     // node charges [nz][ny][nx][NC]
-    double* phi = nullptr;     // potential [nz+2][ny+2][nx+2][NC]
-    double* E = nullptr;       // field [nz][ny][nx][3][NC]
-    double2* buf0 = nullptr;   // FFT work arrays
+    SettingDev* set = nullptr;   // [B]
+    int32_t* owner = nullptr;    // [cap / SEG] setting of each storage segment
+    double* sig = nullptr;       // [B][6][NC] initial beam sizes as duals
+    double* rho = nullptr;     // node charges [B][nz][ny][nx][NC]
+    double* phi = nullptr;     // potential [B][nz+2][ny+2][nx+2][NC]
+    double* E = nullptr;       // field [B][nz][ny][nx][3][NC]
+    double2* buf0 = nullptr;   // FFT work arrays (B settings)
     double2* buf1 = nullptr;
-    double* ghat = nullptr;    // transform of G on the (nx+1)(ny+1)(nz+1) octant
+    double* ghat = nullptr;    // transform of G on the (nx+1)(ny+1)(nz+1) octant (shared)
     double2* tw = nullptr;     // twiddles exp(-2 pi i m / M) for M = 2nx, 2ny, 2nz
-    double* ec = nullptr;      // element constants [MAX_ELEM][EC_N][NC]
-    double* elem_in = nullptr; // uploaded element L and k duals [MAX_ELEM][2][NC]
-    unsigned long long* counters = nullptr;
-    double* mom_part = nullptr;  // moment partial sums [MOM_BLOCKS][MOM_N][NC]
-    double* mom = nullptr;       // moments [MOM_N][NC]
-    double* emit = nullptr;      // emittance [2][3][NC] (raw, centred)
+    double* ec = nullptr;      // element constants [B][MAX_ELEM][EC_N][NC]
+    double* elem_in = nullptr; // uploaded element L and k duals [B][MAX_ELEM][2][NC]
+    unsigned long long* counters = nullptr;  // [B][CNT_N]
+    double* mom_part = nullptr;  // moment partial sums [B][mom_blocks][MOM_N][NC]
+    double* mom = nullptr;       // moments [B][MOM_N][NC]
+    double* emit = nullptr;      // emittance [B][2][3][NC] (raw, centred)
     size_t bytes = 0;
 };
 
@@ -45,8 +70,18 @@ constexpr int NUM_TILE_BINS_MAX = 4096;
 constexpr int TILE_EDGE = 4;                             // cells per tile edge
 constexpr int TILE_HALO = 1;                             // drift allowance (cells) of the LDS deposit
 constexpr int TILE_R = TILE_EDGE + 2 * TILE_HALO + 1;    // LDS nodes per dimension
-constexpr int TILE_CHUNK = 1024;                         // particles per tiled workgroup
-constexpr int SORT_PB = 1024;                            // particles per sort block
+constexpr int TILE_CHUNK = 1024;                         // default particles per tiled work item
+constexpr int CHUNK_MIN = 128;                           // smallest work item (sizes the work list)
+constexpr int CHUNK_MAX = 8192;
+constexpr int SORT_PB = SEG;                             // particles per sort block
+constexpr int MAX_BATCH = 4096;
+
+inline int batch_of(const dpic_dims& d) { return d.nbatch > 0 ? d.nbatch : 1; }
+// moment partial rows per setting
+inline int mom_blocks_for(int B) {
+    const int m = 4096 / B;
+    return m > MOM_BLOCKS ? MOM_BLOCKS : (m < 1 ? 1 : m);
+}
 
 size_t workspace_layout(const dpic_dims& d, char* base, Workspace* ws);
 
@@ -69,12 +104,23 @@ struct AdjointWs {
 
 size_t adjoint_layout(const dpic_dims& d, int nmax, int K, char* base, AdjointWs* out);
 
+// One captured run of dpic_step(n) from step s0 and the host state it leaves.
+struct GraphEntry {
+    int64_t s0 = 0;
+    int n = 0;
+    bool swapped_in = false, chunks_in = false;
+    uint64_t layout = 0;
+    hipGraphExec_t exec = nullptr;
+    bool swapped_out = false, chunks_out = false;
+};
+
 }  // namespace dpic
 
 struct dpic_ctx {
     dpic_dims dims{};
     int NC = 1;
     int ntan = 0;
+    int B = 1;
     hipStream_t stream = nullptr;
     dpic::Workspace ws;
     std::string err;
@@ -93,16 +139,29 @@ struct dpic_ctx {
     std::vector<int> schedule;  // element index of every step
     // parameters
     bool params_set = false;
-    std::vector<double> p, seed;  // seed [np][ntan]
+    int np = 0;
+    std::vector<double> p;     // [B][np]
+    std::vector<double> seed;  // [np][ntan], shared by the settings
     // beam state
     bool beam_init = false;
-    int64_t n = 0;
+    int64_t n = 0;                    // particles over all settings
+    int64_t used = 0;                 // storage slots in use (off + n of the last setting)
+    std::vector<int64_t> nb, off;     // per setting
     int64_t steps_done = 0;
+    bool swapped = false;             // ws.st holds the second state buffer
     // options
     int64_t sort_every = 20;
+    int64_t chunk = dpic::TILE_CHUNK;  // particles per tiled work item
+    int64_t part_blocks = 0;           // workgroups of the tiled particle kernel (0: resident capacity)
     bool chunks_valid = false;  // the tiled work list matches the stored order
     bool stage_timing = false;
+    bool use_graph = false;
+    int cu_count = 0;
     dpic::AdjointWs adj;
+    // captured runs
+    uint64_t layout_gen = 1;
+    hipStream_t cap_stream = nullptr;
+    std::vector<dpic::GraphEntry> graphs;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[DPIC_N_STAGE_TIMERS];
     size_t ev_used[DPIC_N_STAGE_TIMERS] = {0, 0, 0, 0};
     int64_t stage_launches[DPIC_N_STAGE_TIMERS] = {0, 0, 0, 0};
@@ -110,25 +169,34 @@ struct dpic_ctx {
 
 namespace dpic {
 
+inline size_t grid_nodes(const dpic_ctx* c) { return (size_t)c->dims.nx * c->dims.ny * c->dims.nz; }
+inline size_t ec_stride(const dpic_ctx* c) { return (size_t)DPIC_MAX_ELEMENTS * EC_N * c->NC; }
+// offset of a map block (or of the step tau) inside one setting's element table
+inline int ec_offset(const dpic_ctx* c, int e, int slot) { return (e * EC_N + slot) * c->NC; }
+
 // ---- launchers (particles.hip)
 hipError_t launch_element_consts(dpic_ctx* c);
-hipError_t launch_element_consts_into(dpic_ctx* c, int NC, const double* elem_in, double* ec);
-hipError_t launch_init_beam(dpic_ctx* c, const double* xi, const double* sig_dual /*[6][NC] host-marshalled*/);
-// flags: PF_*; e_tau: element whose step size the kick uses; map: map block
-// to apply (element_map_block) or nullptr without PF_MAP.
-hipError_t launch_particles(dpic_ctx* c, int flags, int e_tau, const double* map, bool tiled);
-const double* element_map_block(const dpic_ctx* c, int e, int slot);
-hipError_t launch_canonical_state(dpic_ctx* c);  // st -> st2 in original order
+// element constants of nb settings with NC channels from elem_in [nb][MAX_ELEM][2][NC]
+hipError_t launch_element_consts_into(dpic_ctx* c, int NC, int nb, const double* elem_in, double* ec);
+hipError_t launch_init_beam(dpic_ctx* c, const double* xi);
+// flags: PF_*; e_tau: element whose step size the kick uses; map_off: map
+// block to apply (ec_offset) when PF_MAP is set.
+hipError_t launch_particles(dpic_ctx* c, int flags, int e_tau, int map_off, bool tiled);
+hipError_t launch_canonical_state(dpic_ctx* c);  // st -> st2 in packed original order
+int particle_resident_blocks(dpic_ctx* c);       // resident tiled-kernel workgroups on the device
 hipError_t launch_zero(dpic_ctx* c, double* p, size_t n);
 
 // ---- launchers (sort.hip)
 bool sort_geometry(const dpic_ctx* c, int* tiles, int* nbins);
+size_t max_chunks(const dpic_ctx* c);
 hipError_t launch_sort(dpic_ctx* c);  // also rebuilds the tiled work list
 
 // ---- launchers (solver.hip)
 hipError_t launch_green(dpic_ctx* c);
 hipError_t launch_solve(dpic_ctx* c);
-hipError_t launch_conv(dpic_ctx* c, double* in, const int nin[3], double* out, const int nout[3], int shift, int NC);
+// nb settings of real [z][y][x][NC] windows, back to back
+hipError_t launch_conv(dpic_ctx* c, double* in, const int nin[3], double* out, const int nout[3], int shift, int NC,
+                       int nb);
 hipError_t launch_field(dpic_ctx* c);
 
 // ---- launchers (moments.hip)

@@ -4,6 +4,7 @@
 // Pass 1: each block accumulates, per lane channel, the 15 sums
 // (u^2, u p, p^2, u, p for the planes (x,px), (y,py), (z,delta)) over a
 // grid-stride range of particles and writes one partial row per block.
+// Each setting of a batch has its own partial rows and result.
 // Pass 2: one block adds the partial rows in a fixed order (the result is
 // bitwise reproducible for a given particle order), divides by N and forms
 // the raw and the centred emittances with the dual rules.
@@ -13,16 +14,21 @@ namespace dpic {
 
 constexpr int MOM_THREADS = 256;
 
+// grid (blocks per setting, B): block x of setting y sums a grid-stride part
+// of the setting's slots [off, off + n)
 template <int NC>
-__global__ __launch_bounds__(MOM_THREADS) void k_moments_partial(const double* __restrict__ st, int64_t n, int64_t cap,
+__global__ __launch_bounds__(MOM_THREADS) void k_moments_partial(const double* __restrict__ st, int64_t cap,
+                                                                 const SettingDev* __restrict__ set,
                                                                  double* __restrict__ part) {
     constexpr int PPB = MOM_THREADS / NC;  // particles per block per sweep
     const int c = threadIdx.x % NC;
     const int64_t cs = cap * NC;
+    const SettingDev sd = set[blockIdx.y];
+    const int64_t end = sd.off + sd.n;
     double acc[MOM_N];
 #pragma unroll
     for (int m = 0; m < MOM_N; ++m) acc[m] = 0.0;
-    for (int64_t p = (int64_t)blockIdx.x * PPB + threadIdx.x / NC; p < n; p += (int64_t)gridDim.x * PPB) {
+    for (int64_t p = sd.off + (int64_t)blockIdx.x * PPB + threadIdx.x / NC; p < end; p += (int64_t)gridDim.x * PPB) {
         const double* sp = st + p * NC;
 #pragma unroll
         for (int pl = 0; pl < 3; ++pl) {
@@ -53,14 +59,20 @@ __global__ __launch_bounds__(MOM_THREADS) void k_moments_partial(const double* _
         const int m = i / NC, ch = i % NC;
         double s = 0.0;
         for (int w = 0; w < MOM_THREADS / 64; ++w) s += red[w][m][ch];
-        part[(size_t)blockIdx.x * MOM_N * NC + i] = s;
+        part[((size_t)blockIdx.y * gridDim.x + blockIdx.x) * MOM_N * NC + i] = s;
     }
 }
 
+// one block per setting
 template <int NC>
-__global__ void k_moments_final(const double* __restrict__ part, int nblocks, double inv_n, double* __restrict__ mom,
-                                double* __restrict__ emit) {
+__global__ void k_moments_final(const double* __restrict__ part, int nblocks, const SettingDev* __restrict__ set,
+                                double* __restrict__ mom, double* __restrict__ emit) {
     __shared__ double sm[MOM_N * NC];
+    const int sb = blockIdx.x;
+    const double inv_n = set[sb].n > 0 ? 1.0 / (double)set[sb].n : 0.0;
+    part += (size_t)sb * nblocks * MOM_N * NC;
+    mom += (size_t)sb * MOM_N * NC;
+    emit += (size_t)sb * 6 * NC;
     for (int i = threadIdx.x; i < MOM_N * NC; i += blockDim.x) {
         double s = 0.0;
         for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * MOM_N * NC + i];
@@ -84,22 +96,27 @@ __global__ void k_moments_final(const double* __restrict__ part, int nblocks, do
 }
 
 hipError_t launch_moments(dpic_ctx* cx) {
-    int64_t want = (cx->n * cx->NC + MOM_THREADS - 1) / MOM_THREADS;
-    int nblocks = (int)(want < MOM_BLOCKS ? (want < 1 ? 1 : want) : MOM_BLOCKS);
-    const double inv_n = cx->n > 0 ? 1.0 / (double)cx->n : 0.0;
+    int64_t nmax = 0;
+    for (int b = 0; b < cx->B; ++b) nmax = nmax > cx->nb[b] ? nmax : cx->nb[b];
+    const int64_t want = (nmax * cx->NC + MOM_THREADS - 1) / MOM_THREADS;
+    const int cap_blocks = mom_blocks_for(cx->B);
+    const int nblocks = (int)(want < cap_blocks ? (want < 1 ? 1 : want) : cap_blocks);
     hipStream_t s = cx->stream;
+    const Workspace& w = cx->ws;
+    const int64_t cap = cx->dims.n_particles;
+    const dim3 g1(nblocks, cx->B), g2(cx->B);
     switch (cx->NC) {
         case 1:
-            hipLaunchKernelGGL(k_moments_partial<1>, dim3(nblocks), dim3(MOM_THREADS), 0, s, cx->ws.st, cx->n, cx->dims.n_particles, cx->ws.mom_part);
-            hipLaunchKernelGGL(k_moments_final<1>, dim3(1), dim3(256), 0, s, cx->ws.mom_part, nblocks, inv_n, cx->ws.mom, cx->ws.emit);
+            hipLaunchKernelGGL(k_moments_partial<1>, g1, dim3(MOM_THREADS), 0, s, w.st, cap, w.set, w.mom_part);
+            hipLaunchKernelGGL(k_moments_final<1>, g2, dim3(256), 0, s, w.mom_part, nblocks, w.set, w.mom, w.emit);
             break;
         case 8:
-            hipLaunchKernelGGL(k_moments_partial<8>, dim3(nblocks), dim3(MOM_THREADS), 0, s, cx->ws.st, cx->n, cx->dims.n_particles, cx->ws.mom_part);
-            hipLaunchKernelGGL(k_moments_final<8>, dim3(1), dim3(256), 0, s, cx->ws.mom_part, nblocks, inv_n, cx->ws.mom, cx->ws.emit);
+            hipLaunchKernelGGL(k_moments_partial<8>, g1, dim3(MOM_THREADS), 0, s, w.st, cap, w.set, w.mom_part);
+            hipLaunchKernelGGL(k_moments_final<8>, g2, dim3(256), 0, s, w.mom_part, nblocks, w.set, w.mom, w.emit);
             break;
         default:
-            hipLaunchKernelGGL(k_moments_partial<16>, dim3(nblocks), dim3(MOM_THREADS), 0, s, cx->ws.st, cx->n, cx->dims.n_particles, cx->ws.mom_part);
-            hipLaunchKernelGGL(k_moments_final<16>, dim3(1), dim3(256), 0, s, cx->ws.mom_part, nblocks, inv_n, cx->ws.mom, cx->ws.emit);
+            hipLaunchKernelGGL(k_moments_partial<16>, g1, dim3(MOM_THREADS), 0, s, w.st, cap, w.set, w.mom_part);
+            hipLaunchKernelGGL(k_moments_final<16>, g2, dim3(256), 0, s, w.mom_part, nblocks, w.set, w.mom, w.emit);
             break;
     }
     return hipGetLastError();

@@ -56,6 +56,8 @@ __global__ void k_element_consts(ElemTable tab, int n_elem, const double* __rest
     const int e = blockIdx.x;
     const int c = threadIdx.x;
     if (e >= n_elem || c >= NC) return;
+    elem_in += (size_t)blockIdx.y * DPIC_MAX_ELEMENTS * 2 * NC;  // setting
+    ec += (size_t)blockIdx.y * DPIC_MAX_ELEMENTS * EC_N * NC;
     LD L = ldload(elem_in + (e * 2 + 0) * NC, c);
     LD k = ldload(elem_in + (e * 2 + 1) * NC, c);
     const double ns = (double)tab.nsteps[e];
@@ -108,6 +110,7 @@ __global__ void k_element_combine(int n_elem, double* __restrict__ ec) {
     const int e = blockIdx.x;
     const int c = threadIdx.x;
     if (e >= n_elem || c >= NC) return;
+    ec += (size_t)blockIdx.y * DPIC_MAX_ELEMENTS * EC_N * NC;  // setting
     const int en = (e + 1) % n_elem;
     const double* A = ec + (size_t)e * EC_N * NC + EC_HALF * NC;
     const double* Bn = ec + (size_t)en * EC_N * NC + EC_HALF * NC;
@@ -115,14 +118,14 @@ __global__ void k_element_combine(int n_elem, double* __restrict__ ec) {
     combine_block<NC>(A, Bn, ec + (size_t)e * EC_N * NC + EC_NEXT * NC + c, c);
 }
 
-hipError_t launch_element_consts_into(dpic_ctx* cx, int NC, const double* elem_in, double* ec) {
+hipError_t launch_element_consts_into(dpic_ctx* cx, int NC, int nb, const double* elem_in, double* ec) {
     ElemTable tab{};
     for (int e = 0; e < cx->n_elem; ++e) {
         tab.kind[e] = cx->kind[e];
         tab.nsteps[e] = cx->n_steps[e];
     }
     const double inv_g2 = 1.0 / (cx->gamma0 * cx->gamma0);
-    dim3 grid(cx->n_elem), block(64);
+    dim3 grid(cx->n_elem, nb), block(64);
     switch (NC) {
         case 1:
             hipLaunchKernelGGL(k_element_consts<1>, grid, block, 0, cx->stream, tab, cx->n_elem, elem_in, ec, inv_g2);
@@ -143,37 +146,39 @@ hipError_t launch_element_consts_into(dpic_ctx* cx, int NC, const double* elem_i
 }
 
 hipError_t launch_element_consts(dpic_ctx* cx) {
-    return launch_element_consts_into(cx, cx->NC, cx->ws.elem_in, cx->ws.ec);
+    return launch_element_consts_into(cx, cx->NC, cx->B, cx->ws.elem_in, cx->ws.ec);
 }
 
 // ---------------------------------------------------------------- beam init
-struct SigmaDual {
-    double s[6][16];  // [coord][channel]: sigma_j value and its seed row
-};
-
+// Storage slot p of setting b = owner[p / SEG] takes packed row p - delta_b of
+// xi; slots past the setting's n (segment padding) are left alone.
 template <int NC>
-__global__ void k_init_beam(const double* __restrict__ xi, int64_t n, int64_t cap, SigmaDual sig,
-                            double* __restrict__ st, int32_t* __restrict__ pid) {
+__global__ void k_init_beam(const double* __restrict__ xi, int64_t used, int64_t cap,
+                            const SettingDev* __restrict__ set, const int32_t* __restrict__ owner,
+                            const double* __restrict__ sig, double* __restrict__ st, int32_t* __restrict__ pid) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t p = gid / NC;
     const int c = (int)(gid % NC);
-    if (p >= n) return;
+    if (p >= used) return;
+    const int b = owner[p / SEG];
+    const SettingDev sd = set[b];
+    if (p - sd.off >= sd.n) return;
+    const int64_t row = p - sd.delta;
+    const double* sg = sig + (size_t)b * 6 * NC;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) st[((int64_t)j * cap + p) * NC + c] = sig.s[j][c] * xi[p * 6 + j];
-    if (c == 0) pid[p] = (int32_t)p;
+    for (int j = 0; j < 6; ++j) st[((int64_t)j * cap + p) * NC + c] = sg[j * NC + c] * xi[row * 6 + j];
+    if (c == 0) pid[p] = (int32_t)row;
 }
 
-hipError_t launch_init_beam(dpic_ctx* cx, const double* xi, const double* sig_dual) {
-    SigmaDual sd{};
-    for (int j = 0; j < 6; ++j)
-        for (int c = 0; c < cx->NC; ++c) sd.s[j][c] = sig_dual[j * cx->NC + c];
-    const int64_t threads = cx->n * cx->NC;
+hipError_t launch_init_beam(dpic_ctx* cx, const double* xi) {
+    const int64_t threads = cx->used * cx->NC;
     dim3 block(256), grid((unsigned)((threads + 255) / 256));
     if (threads == 0) return hipSuccess;
+    const Workspace& w = cx->ws;
     switch (cx->NC) {
-        case 1: hipLaunchKernelGGL(k_init_beam<1>, grid, block, 0, cx->stream, xi, cx->n, cx->dims.n_particles, sd, cx->ws.st, cx->ws.pid); break;
-        case 8: hipLaunchKernelGGL(k_init_beam<8>, grid, block, 0, cx->stream, xi, cx->n, cx->dims.n_particles, sd, cx->ws.st, cx->ws.pid); break;
-        default: hipLaunchKernelGGL(k_init_beam<16>, grid, block, 0, cx->stream, xi, cx->n, cx->dims.n_particles, sd, cx->ws.st, cx->ws.pid); break;
+        case 1: hipLaunchKernelGGL(k_init_beam<1>, grid, block, 0, cx->stream, xi, cx->used, cx->dims.n_particles, w.set, w.owner, w.sig, w.st, w.pid); break;
+        case 8: hipLaunchKernelGGL(k_init_beam<8>, grid, block, 0, cx->stream, xi, cx->used, cx->dims.n_particles, w.set, w.owner, w.sig, w.st, w.pid); break;
+        default: hipLaunchKernelGGL(k_init_beam<16>, grid, block, 0, cx->stream, xi, cx->used, cx->dims.n_particles, w.set, w.owner, w.sig, w.st, w.pid); break;
     }
     return hipGetLastError();
 }
@@ -297,16 +302,25 @@ __device__ __forceinline__ QD<K> qd_one_minus(const QD<K>& f) {
 // ---------------------------------------------------------------- fused step
 struct PartArgs {
     double* st;
-    int64_t n, cap;
-    const double* tau;  // dual step of the current element (NC doubles)
-    const double* map;  // map block (MB_N duals)
-    const double* E;
-    double* rho;
+    int64_t cap, used;
+    const SettingDev* set;  // per-setting arrays and charge
+    const int32_t* owner;
+    int tau_off;            // dual step of the current element in a setting's element table
+    int map_off;            // map block (MB_N duals) in it
     int nx, ny, nz;
     double lo0, lo1, lo2, ih0, ih1, ih2;
-    double kperp, kpar, q;
-    unsigned long long* cnt;
+    double kperp, kpar;
 };
+
+// the arrays and charge of one setting
+struct SetView {
+    const double* E;
+    double* rho;
+    unsigned long long* cnt;
+    double q;
+};
+
+__device__ __forceinline__ SetView set_view(const SettingDev& sd) { return SetView{sd.E, sd.rho, sd.cnt, sd.q}; }
 
 struct TiledArgs {
     const int4* chunks;
@@ -323,7 +337,7 @@ constexpr int TILE_CSTRIDE = ((TILE_NODES + 15) / 16) * 16 + 1;
 constexpr int PART_THREADS = 256;
 
 // wavefront max of the extents (all 64 lanes take part), one atomic per wave
-__device__ __forceinline__ void extent_flush(const PartArgs& a, double e0, double e1, double e2) {
+__device__ __forceinline__ void extent_flush(unsigned long long* cnt, double e0, double e1, double e2) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         e0 = fmax(e0, __shfl_xor(e0, off, 64));
@@ -331,9 +345,9 @@ __device__ __forceinline__ void extent_flush(const PartArgs& a, double e0, doubl
         e2 = fmax(e2, __shfl_xor(e2, off, 64));
     }
     if ((threadIdx.x & 63) == 0) {
-        atomicMax(a.cnt + CNT_EXT_X, (unsigned long long)__double_as_longlong(e0));
-        atomicMax(a.cnt + CNT_EXT_Y, (unsigned long long)__double_as_longlong(e1));
-        atomicMax(a.cnt + CNT_EXT_Z, (unsigned long long)__double_as_longlong(e2));
+        atomicMax(cnt + CNT_EXT_X, (unsigned long long)__double_as_longlong(e0));
+        atomicMax(cnt + CNT_EXT_Y, (unsigned long long)__double_as_longlong(e1));
+        atomicMax(cnt + CNT_EXT_Z, (unsigned long long)__double_as_longlong(e2));
     }
 }
 
@@ -406,7 +420,7 @@ __device__ __forceinline__ QD<K> raw_to_qd(const double* r, int q) {
 }
 
 template <int NC, int F, bool TILED>
-__device__ __forceinline__ void particle_body(const PartArgs& a, const double* __restrict__ smap,
+__device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& sv, const double* __restrict__ smap,
                                               const double* __restrict__ stau, int64_t p, int q,
                                               const RawState<Quad<NC>::K>& raw, double* lr, int ox, int oy,
                                               int oz, bool use_tile, double& e0, double& e1, double& e2) {
@@ -431,7 +445,7 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const double* _
 #pragma unroll
                     for (int kx = 0; kx < 2; ++kx) {
                         const QD<K> w = qd_mul(kx ? fx : qd_one_minus(fx), wyz);
-                        const double* ep = a.E + (n0 + kx + ky * a.nx + kz * sxy) * 3 * NC;
+                        const double* ep = sv.E + (n0 + kx + ky * a.nx + kz * sxy) * 3 * NC;
                         qd_fmad(w, qd_load<K, G>(ep, q), ex);
                         qd_fmad(w, qd_load<K, G>(ep + NC, q), ey);
                         qd_fmad(w, qd_load<K, G>(ep + 2 * NC, q), ez);
@@ -485,18 +499,18 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const double* _
                             if (TILED && local) {
                                 double* l = lr + (q * K) * TILE_CSTRIDE + l0 + kx + ky * TILE_R + kz * TILE_R * TILE_R;
 #pragma unroll
-                                for (int k = 0; k < K; ++k) unsafeAtomicAdd(l + k * TILE_CSTRIDE, qd_chan(w, q, k) * a.q);
+                                for (int k = 0; k < K; ++k) unsafeAtomicAdd(l + k * TILE_CSTRIDE, qd_chan(w, q, k) * sv.q);
                             } else {
-                                double* r = a.rho + (n0 + kx + ky * a.nx + kz * sxy) * NC + q * K;
+                                double* r = sv.rho + (n0 + kx + ky * a.nx + kz * sxy) * NC + q * K;
 #pragma unroll
-                                for (int k = 0; k < K; ++k) unsafeAtomicAdd(r + k, qd_chan(w, q, k) * a.q);
+                                for (int k = 0; k < K; ++k) unsafeAtomicAdd(r + k, qd_chan(w, q, k) * sv.q);
                             }
                         }
                     }
                 }
             }
         } else if (q == 0) {
-            atomicAdd(a.cnt + CNT_OUTSIDE, 1ull);
+            atomicAdd(sv.cnt + CNT_OUTSIDE, 1ull);
         }
         e0 = fmax(e0, fabs(x.v));
         e1 = fmax(e1, fabs(y.v));
@@ -510,36 +524,42 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const double* _
     qd_store(sp + 5 * cs, d, q);
 }
 
-// Copy the step's constants (tau and one map block) into LDS.
+// Copy a setting's step constants (tau and one map block) into LDS.
 template <int NC>
-__device__ __forceinline__ void stage_consts(const PartArgs& a, double* smap, double* stau) {
-    for (int j = threadIdx.x; j < MB_N * NC; j += PART_THREADS) smap[j] = a.map[j];
-    for (int j = threadIdx.x; j < NC; j += PART_THREADS) stau[j] = a.tau[j];
+__device__ __forceinline__ void stage_consts(const PartArgs& a, const double* __restrict__ ec, double* smap,
+                                             double* stau) {
+    for (int j = threadIdx.x; j < MB_N * NC; j += PART_THREADS) smap[j] = ec[a.map_off + j];
+    for (int j = threadIdx.x; j < NC; j += PART_THREADS) stau[j] = ec[a.tau_off + j];
 }
 
-// Storage-order kernel: deposit by global atomics.
+// Storage-order kernel: deposit by global atomics. A workgroup covers
+// PART_THREADS / G consecutive slots, which never straddle a storage segment,
+// so its setting is that of its first slot.
 template <int NC, int F>
 __global__ __launch_bounds__(PART_THREADS) void k_particles(PartArgs a) {
     constexpr int G = Quad<NC>::G;
     __shared__ __align__(16) double smap[MB_N * NC];
     __shared__ __align__(16) double stau[NC];
-    stage_consts<NC>(a, smap, stau);
+    const int64_t p0 = (int64_t)blockIdx.x * (PART_THREADS / G);
+    const SettingDev sd = a.set[a.owner[p0 / SEG]];
+    stage_consts<NC>(a, sd.ec, smap, stau);
     __syncthreads();
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t p = gid / G;
-    const int q = (int)(gid % G);
+    const SetView sv = set_view(sd);
+    const int64_t p = p0 + threadIdx.x / G;
+    const int q = (int)(threadIdx.x % G);
     double e0 = 0.0, e1 = 0.0, e2 = 0.0;
-    if (p < a.n) {
+    if (p - sd.off < sd.n) {
         const RawState<Quad<NC>::K> raw = load_raw<NC>(a, p, q);
-        particle_body<NC, F, false>(a, smap, stau, p, q, raw, nullptr, 0, 0, 0, false, e0, e1, e2);
+        particle_body<NC, F, false>(a, sv, smap, stau, p, q, raw, nullptr, 0, 0, 0, false, e0, e1, e2);
     }
-    if (F & (PF_DEPOSIT | PF_COUNT)) extent_flush(a, e0, e1, e2);
+    if (F & (PF_DEPOSIT | PF_COUNT)) extent_flush(sv.cnt, e0, e1, e2);
 }
 
-// Tiled kernel: workgroup = one chunk of particles sorted into one grid tile.
-// The deposit accumulates in LDS over the tile's nodes plus a TILE_HALO-cell
-// halo (particles drift between re-sorts) and is flushed once: only nodes
-// that received charge issue global atomics.
+// Tiled kernel, persistent: each workgroup walks the work list with a grid
+// stride. A work item is one chunk of particles of one setting sorted into
+// one grid tile; the deposit accumulates in LDS over the tile's nodes plus a
+// TILE_HALO-cell halo (particles drift between re-sorts) and is flushed once:
+// only nodes that received charge issue global atomics.
 template <int NC, int F>
 __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, TiledArgs t) {
     constexpr int G = Quad<NC>::G;
@@ -547,88 +567,148 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
     __shared__ __align__(16) double lr[LDSN];
     __shared__ __align__(16) double smap[MB_N * NC];
     __shared__ __align__(16) double stau[NC];
-    if (blockIdx.x >= *t.nchunks) return;  // uniform per workgroup
-    const int4 ck = t.chunks[blockIdx.x];
-    const bool use_tile = ck.x < t.nbins - 1;
-    const int tx = ck.x % t.tx, ty = (ck.x / t.tx) % t.ty, tz = ck.x / (t.tx * t.ty);
-    const int ox = tx * TILE_EDGE - TILE_HALO, oy = ty * TILE_EDGE - TILE_HALO, oz = tz * TILE_EDGE - TILE_HALO;
-    stage_consts<NC>(a, smap, stau);
-    if (F & PF_DEPOSIT)
-        for (int j = threadIdx.x; j < LDSN; j += PART_THREADS) lr[j] = 0.0;
-    __syncthreads();
+    const uint32_t nck = *t.nchunks;
     const int q = threadIdx.x % G;
-    double e0 = 0.0, e1 = 0.0, e2 = 0.0;
-    // software pipeline: the next particle's state is loaded while the
-    // current one is gathered, pushed and deposited
     constexpr int STRIDE = PART_THREADS / G;
-    int i = threadIdx.x / G;
-    RawState<Quad<NC>::K> next;
-    if (i < ck.z) next = load_raw<NC>(a, (int64_t)ck.y + i, q);
+    int cur = -1;
+    SetView sv{nullptr, nullptr, nullptr, 0.0};
 #pragma unroll 1
-    for (; i < ck.z; i += STRIDE) {
-        const RawState<Quad<NC>::K> cur = next;
-        if (i + STRIDE < ck.z) next = load_raw<NC>(a, (int64_t)ck.y + i + STRIDE, q);
-        particle_body<NC, F, true>(a, smap, stau, (int64_t)ck.y + i, q, cur, lr, ox, oy, oz, use_tile, e0, e1, e2);
-    }
-    if (F & PF_DEPOSIT) {
+    for (uint32_t ci = blockIdx.x; ci < nck; ci += gridDim.x) {
+        const int4 ck = t.chunks[ci];
+        if (ci != blockIdx.x) __syncthreads();  // the previous item's flush is done with lr and smap
+        if (ck.w != cur) {
+            cur = ck.w;
+            const SettingDev sd = a.set[cur];
+            sv = set_view(sd);
+            stage_consts<NC>(a, sd.ec, smap, stau);
+        }
+        if (F & PF_DEPOSIT)
+            for (int j = threadIdx.x; j < LDSN; j += PART_THREADS) lr[j] = 0.0;
         __syncthreads();
-        // node-major walk (NC consecutive lanes write one node's channels),
-        // started at a chunk-dependent node so that chunks of the same tile
-        // flushing at the same time hit different addresses
-        const int rot = (int)((blockIdx.x * 61u) % TILE_NODES);
-        for (int j = threadIdx.x; j < TILE_NODES * NC; j += PART_THREADS) {
-            const int ch = j % NC;
-            int node = j / NC + rot;
-            node -= node >= TILE_NODES ? TILE_NODES : 0;
-            const double v = lr[ch * TILE_CSTRIDE + node];
-            if (v != 0.0) {
-                const int lx = node % TILE_R, ly = (node / TILE_R) % TILE_R, lz = node / (TILE_R * TILE_R);
-                const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
-                if (gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz)
-                    unsafeAtomicAdd(a.rho + (((int64_t)gz * a.ny + gy) * a.nx + gx) * NC + ch, v);
+        const bool use_tile = ck.x < t.nbins - 1;
+        const int tx = ck.x % t.tx, ty = (ck.x / t.tx) % t.ty, tz = ck.x / (t.tx * t.ty);
+        const int ox = tx * TILE_EDGE - TILE_HALO, oy = ty * TILE_EDGE - TILE_HALO, oz = tz * TILE_EDGE - TILE_HALO;
+        double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+        // software pipeline: the next particle's state is loaded while the
+        // current one is gathered, pushed and deposited
+        int i = threadIdx.x / G;
+        RawState<Quad<NC>::K> next;
+        if (i < ck.z) next = load_raw<NC>(a, (int64_t)ck.y + i, q);
+#pragma unroll 1
+        for (; i < ck.z; i += STRIDE) {
+            const RawState<Quad<NC>::K> curst = next;
+            if (i + STRIDE < ck.z) next = load_raw<NC>(a, (int64_t)ck.y + i + STRIDE, q);
+            particle_body<NC, F, true>(a, sv, smap, stau, (int64_t)ck.y + i, q, curst, lr, ox, oy, oz, use_tile, e0,
+                                       e1, e2);
+        }
+        if (F & PF_DEPOSIT) {
+            __syncthreads();
+            // node-major walk (NC consecutive lanes write one node's channels),
+            // started at an item-dependent node so that items of the same tile
+            // flushing at the same time hit different addresses
+            const int rot = (int)((ci * 61u) % TILE_NODES);
+            for (int j = threadIdx.x; j < TILE_NODES * NC; j += PART_THREADS) {
+                const int ch = j % NC;
+                int node = j / NC + rot;
+                node -= node >= TILE_NODES ? TILE_NODES : 0;
+                const double v = lr[ch * TILE_CSTRIDE + node];
+                if (v != 0.0) {
+                    const int lx = node % TILE_R, ly = (node / TILE_R) % TILE_R, lz = node / (TILE_R * TILE_R);
+                    const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+                    if (gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz)
+                        unsafeAtomicAdd(sv.rho + (((int64_t)gz * a.ny + gy) * a.nx + gx) * NC + ch, v);
+                }
             }
         }
+        if (F & (PF_DEPOSIT | PF_COUNT)) extent_flush(sv.cnt, e0, e1, e2);
     }
-    if (F & (PF_DEPOSIT | PF_COUNT)) extent_flush(a, e0, e1, e2);
+}
+
+// Resident workgroups per CU of one tiled-kernel instance (queried once).
+template <int NC, int FL>
+static int tiled_occupancy() {
+    static int occ = 0;
+    if (occ == 0) {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_particles_tiled<NC, FL>, PART_THREADS, 0) !=
+                hipSuccess ||
+            v < 1)
+            v = 1;
+        occ = v;
+    }
+    return occ;
+}
+
+template <int NC>
+static int resident_nc(int flags) {
+    switch (flags) {
+        case PF_MAP | PF_DEPOSIT: return tiled_occupancy<NC, PF_MAP | PF_DEPOSIT>();
+        case PF_KICK | PF_MAP | PF_DEPOSIT: return tiled_occupancy<NC, PF_KICK | PF_MAP | PF_DEPOSIT>();
+        case PF_KICK | PF_MAP: return tiled_occupancy<NC, PF_KICK | PF_MAP>();
+        case PF_MAP | PF_COUNT: return tiled_occupancy<NC, PF_MAP | PF_COUNT>();
+        case PF_MAP: return tiled_occupancy<NC, PF_MAP>();
+        default: return tiled_occupancy<NC, PF_DEPOSIT>();
+    }
+}
+
+// Resident workgroups of the tiled kernel on the whole device for the
+// step's main flag set; also fills the per-instance cache of every instance
+// of this channel count (so that no query happens during graph capture).
+int particle_resident_blocks(dpic_ctx* cx) {
+    int r = 0;
+    const int all[6] = {PF_MAP | PF_DEPOSIT, PF_KICK | PF_MAP | PF_DEPOSIT, PF_KICK | PF_MAP, PF_MAP | PF_COUNT,
+                        PF_MAP, PF_DEPOSIT};
+    for (int f : all) {
+        const int v = cx->NC == 1 ? resident_nc<1>(f) : (cx->NC == 8 ? resident_nc<8>(f) : resident_nc<16>(f));
+        if (f == (PF_KICK | PF_MAP | PF_DEPOSIT)) r = v;
+    }
+    return r * (cx->cu_count > 0 ? cx->cu_count : 256);
+}
+
+template <int NC, int FL, bool TL>
+static void launch_one(dpic_ctx* cx, const PartArgs& a, const TiledArgs& t, size_t max_items) {
+    constexpr int G = Quad<NC>::G;
+    dim3 block(PART_THREADS);
+    if (TL) {
+        // default: twice the resident workgroups, so that the hardware
+        // dispatcher refills CUs whose items finish early
+        size_t g = cx->part_blocks > 0
+                       ? (size_t)cx->part_blocks
+                       : 2 * (size_t)tiled_occupancy<NC, FL>() * (size_t)(cx->cu_count > 0 ? cx->cu_count : 256);
+        if (g > max_items) g = max_items;
+        if (g < 1) g = 1;
+        hipLaunchKernelGGL((k_particles_tiled<NC, FL>), dim3((unsigned)g), block, 0, cx->stream, a, t);
+    } else {
+        const int64_t blocks = (a.used * G + PART_THREADS - 1) / PART_THREADS;
+        hipLaunchKernelGGL((k_particles<NC, FL>), dim3((unsigned)blocks), block, 0, cx->stream, a);
+    }
 }
 
 template <int NC, bool TL>
 static hipError_t launch_particles_nc(dpic_ctx* cx, int flags, const PartArgs& a, const TiledArgs& t,
-                                      unsigned tgrid) {
-    const int64_t threads = a.n * Quad<NC>::G;
-    if (threads == 0) return hipSuccess;
-    dim3 block(PART_THREADS), grid(TL ? tgrid : (unsigned)((threads + PART_THREADS - 1) / PART_THREADS));
-    hipStream_t s = cx->stream;
-#define DPIC_PART_CASE(FL)                                                              \
-    case FL:                                                                            \
-        if (TL)                                                                         \
-            hipLaunchKernelGGL((k_particles_tiled<NC, FL>), grid, block, 0, s, a, t);   \
-        else                                                                            \
-            hipLaunchKernelGGL((k_particles<NC, FL>), grid, block, 0, s, a);            \
-        break;
+                                      size_t max_items) {
+    if (a.used == 0) return hipSuccess;
     switch (flags) {
-        DPIC_PART_CASE(PF_MAP | PF_DEPOSIT)
-        DPIC_PART_CASE(PF_KICK | PF_MAP | PF_DEPOSIT)
-        DPIC_PART_CASE(PF_KICK | PF_MAP)
-        DPIC_PART_CASE(PF_MAP | PF_COUNT)
-        DPIC_PART_CASE(PF_MAP)
-        DPIC_PART_CASE(PF_DEPOSIT)
-        default:
-            return hipErrorInvalidValue;
+        case PF_MAP | PF_DEPOSIT: launch_one<NC, PF_MAP | PF_DEPOSIT, TL>(cx, a, t, max_items); break;
+        case PF_KICK | PF_MAP | PF_DEPOSIT: launch_one<NC, PF_KICK | PF_MAP | PF_DEPOSIT, TL>(cx, a, t, max_items); break;
+        case PF_KICK | PF_MAP: launch_one<NC, PF_KICK | PF_MAP, TL>(cx, a, t, max_items); break;
+        case PF_MAP | PF_COUNT: launch_one<NC, PF_MAP | PF_COUNT, TL>(cx, a, t, max_items); break;
+        case PF_MAP: launch_one<NC, PF_MAP, TL>(cx, a, t, max_items); break;
+        case PF_DEPOSIT: launch_one<NC, PF_DEPOSIT, TL>(cx, a, t, max_items); break;
+        default: return hipErrorInvalidValue;
     }
-#undef DPIC_PART_CASE
     return hipGetLastError();
 }
 
-hipError_t launch_particles(dpic_ctx* cx, int flags, int e_tau, const double* map, bool tiled) {
+hipError_t launch_particles(dpic_ctx* cx, int flags, int e_tau, int map_off, bool tiled) {
     PartArgs a;
     a.st = cx->ws.st;
-    a.n = cx->n;
     a.cap = cx->dims.n_particles;
-    a.tau = cx->ws.ec + (size_t)e_tau * EC_N * cx->NC + EC_TAU * cx->NC;
-    a.map = map ? map : cx->ws.ec;
-    a.E = cx->ws.E;
-    a.rho = cx->ws.rho;
+    a.used = cx->used;
+    a.set = cx->ws.set;
+    a.owner = cx->ws.owner;
+    a.tau_off = ec_offset(cx, e_tau, EC_TAU);
+    a.map_off = map_off;
     a.nx = cx->dims.nx;
     a.ny = cx->dims.ny;
     a.nz = cx->dims.nz;
@@ -640,10 +720,8 @@ hipError_t launch_particles(dpic_ctx* cx, int flags, int e_tau, const double* ma
     a.ih2 = 1.0 / cx->h[2];
     a.kperp = cx->kperp;
     a.kpar = cx->kpar;
-    a.q = cx->n > 0 ? cx->bunch_charge / (double)cx->n : 0.0;
-    a.cnt = cx->ws.counters;
     TiledArgs t{};
-    unsigned tgrid = 0;
+    size_t items = 0;
     if (tiled) {
         int tiles[3], nbins;
         if (!cx->chunks_valid || !sort_geometry(cx, tiles, &nbins)) return hipErrorInvalidValue;
@@ -652,41 +730,42 @@ hipError_t launch_particles(dpic_ctx* cx, int flags, int e_tau, const double* ma
         t.tx = tiles[0];
         t.ty = tiles[1];
         t.nbins = nbins;
-        tgrid = (unsigned)(nbins + (cx->n + TILE_CHUNK - 1) / TILE_CHUNK);
+        items = max_chunks(cx);
     }
     switch (cx->NC) {
-        case 1: return tiled ? launch_particles_nc<1, true>(cx, flags, a, t, tgrid) : launch_particles_nc<1, false>(cx, flags, a, t, tgrid);
-        case 8: return tiled ? launch_particles_nc<8, true>(cx, flags, a, t, tgrid) : launch_particles_nc<8, false>(cx, flags, a, t, tgrid);
-        default: return tiled ? launch_particles_nc<16, true>(cx, flags, a, t, tgrid) : launch_particles_nc<16, false>(cx, flags, a, t, tgrid);
+        case 1: return tiled ? launch_particles_nc<1, true>(cx, flags, a, t, items) : launch_particles_nc<1, false>(cx, flags, a, t, items);
+        case 8: return tiled ? launch_particles_nc<8, true>(cx, flags, a, t, items) : launch_particles_nc<8, false>(cx, flags, a, t, items);
+        default: return tiled ? launch_particles_nc<16, true>(cx, flags, a, t, items) : launch_particles_nc<16, false>(cx, flags, a, t, items);
     }
-}
-
-const double* element_map_block(const dpic_ctx* cx, int e, int slot) {
-    return cx->ws.ec + (size_t)e * EC_N * cx->NC + (size_t)slot * cx->NC;
 }
 
 // ---------------------------------------------------------------- read-back
-// st [6][cap][NC] in storage order -> st2 [n][6][NC] in original particle order
+// st [6][cap][NC] in storage order -> st2 [n][6][NC] in packed original order
 template <int NC>
-__global__ void k_canonical(const double* __restrict__ st, const int32_t* __restrict__ pid, int64_t n,
-                            int64_t cap, double* __restrict__ out) {
+__global__ void k_canonical(const double* __restrict__ st, const int32_t* __restrict__ pid, int64_t used, int64_t cap,
+                            const SettingDev* __restrict__ set, const int32_t* __restrict__ owner,
+                            double* __restrict__ out) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t p = gid / NC;
     const int c = (int)(gid % NC);
-    if (p >= n) return;
+    if (p >= used) return;
+    const SettingDev sd = set[owner[p / SEG]];
+    if (p - sd.off >= sd.n) return;
     const int64_t q = pid[p];
 #pragma unroll
     for (int j = 0; j < 6; ++j) out[(q * 6 + j) * NC + c] = st[((int64_t)j * cap + p) * NC + c];
 }
 
 hipError_t launch_canonical_state(dpic_ctx* cx) {
-    const int64_t threads = cx->n * cx->NC;
+    const int64_t threads = cx->used * cx->NC;
     if (threads == 0) return hipSuccess;
     dim3 block(256), grid((unsigned)((threads + 255) / 256));
+    const Workspace& w = cx->ws;
+    const int64_t cap = cx->dims.n_particles;
     switch (cx->NC) {
-        case 1: hipLaunchKernelGGL(k_canonical<1>, grid, block, 0, cx->stream, cx->ws.st, cx->ws.pid, cx->n, cx->dims.n_particles, cx->ws.st2); break;
-        case 8: hipLaunchKernelGGL(k_canonical<8>, grid, block, 0, cx->stream, cx->ws.st, cx->ws.pid, cx->n, cx->dims.n_particles, cx->ws.st2); break;
-        default: hipLaunchKernelGGL(k_canonical<16>, grid, block, 0, cx->stream, cx->ws.st, cx->ws.pid, cx->n, cx->dims.n_particles, cx->ws.st2); break;
+        case 1: hipLaunchKernelGGL(k_canonical<1>, grid, block, 0, cx->stream, w.st, w.pid, cx->used, cap, w.set, w.owner, w.st2); break;
+        case 8: hipLaunchKernelGGL(k_canonical<8>, grid, block, 0, cx->stream, w.st, w.pid, cx->used, cap, w.set, w.owner, w.st2); break;
+        default: hipLaunchKernelGGL(k_canonical<16>, grid, block, 0, cx->stream, w.st, w.pid, cx->used, cap, w.set, w.owner, w.st2); break;
     }
     return hipGetLastError();
 }

@@ -249,6 +249,7 @@ struct ColArgs {
     int64_t out_outer, out_stride;
     int n_out;        // output rows; row t holds transform row (t - out_shift) mod M
     int out_shift;
+    int64_t in_batch, out_batch;  // strides between settings (grid dimension y)
     // Ghat multiply (mode 1): column w is (kx = w / ncc), outer index is ky
     const double* ghat;
     int ncc, gnx1, gny1, Mx, My;
@@ -347,8 +348,8 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_cols(const double2* __res
     const int outer = blockIdx.x / tiles;
     const int col = (blockIdx.x - outer * tiles) * BC + b;
     const bool valid = col < a.W;
-    const double2* src = in + (int64_t)outer * a.in_outer + (int64_t)col * a.bstride;
-    double2* dst = out + (int64_t)outer * a.out_outer + (int64_t)col * a.bstride;
+    const double2* src = in + (int64_t)blockIdx.y * a.in_batch + (int64_t)outer * a.in_outer + (int64_t)col * a.bstride;
+    double2* dst = out + (int64_t)blockIdx.y * a.out_batch + (int64_t)outer * a.out_outer + (int64_t)col * a.bstride;
     double hr[NG][R2], hi[NG][R2];  // groups k1 = r + R2 g, values over k2
     if (MODE != 2) {
         double xr[R1], xi[R1];
@@ -452,14 +453,14 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_cols(const double2* __res
 }
 
 template <int MODE>
-static hipError_t launch_cols(int M, int n_outer, const ColArgs& a, const double2* in, double2* out,
+static hipError_t launch_cols(int M, int n_outer, int nb, const ColArgs& a, const double2* in, double2* out,
                               const double2* tw, hipStream_t s) {
     switch (M) {
 #define DPIC_COLS(MM)                                                                                 \
     case MM: {                                                                                        \
         using C = ColCfg<MM>;                                                                         \
         const unsigned blocks = (unsigned)n_outer * (unsigned)((a.W + C::BC - 1) / C::BC);            \
-        hipLaunchKernelGGL((k_fft_cols<MM, MODE>), dim3(blocks), dim3(C::NT), 0, s, in, out, a, tw);  \
+        hipLaunchKernelGGL((k_fft_cols<MM, MODE>), dim3(blocks, nb), dim3(C::NT), 0, s, in, out, a, tw); \
         break;                                                                                        \
     }
         DPIC_COLS(16) DPIC_COLS(32) DPIC_COLS(64) DPIC_COLS(128)
@@ -512,7 +513,8 @@ static hipError_t launch_rows_inv_nc(int M, const double2* in, double* phi, int 
 // The forward solve uses nin = n (rho) and nout = n + 2 with shift 1 (the
 // ghost ring at position -1 = M - 1); the adjoint solve uses nin = n + 2 (its
 // source already shifted by one) and nout = n with shift -1.
-hipError_t launch_conv(dpic_ctx* cx, double* in, const int nin[3], double* out, const int nout[3], int shift, int NC) {
+hipError_t launch_conv(dpic_ctx* cx, double* in, const int nin[3], double* out, const int nout[3], int shift, int NC,
+                       int nb) {
     const int nx = cx->dims.nx, ny = cx->dims.ny, nz = cx->dims.nz;
     const int Mx = 2 * nx, My = 2 * ny, Mz = 2 * nz;
     const int NCC = NC == 1 ? 1 : NC / 2;
@@ -523,9 +525,9 @@ hipError_t launch_conv(dpic_ctx* cx, double* in, const int nin[3], double* out, 
     hipError_t e;
     // 1: x forward, in -> A[nin_z][nin_y][Mx]
     switch (NC) {
-        case 1: e = launch_rows_fwd_nc<1>(Mx, in, cx->ws.buf0, nin[0], nin[1] * nin[2], twx, s); break;
-        case 8: e = launch_rows_fwd_nc<8>(Mx, in, cx->ws.buf0, nin[0], nin[1] * nin[2], twx, s); break;
-        default: e = launch_rows_fwd_nc<16>(Mx, in, cx->ws.buf0, nin[0], nin[1] * nin[2], twx, s); break;
+        case 1: e = launch_rows_fwd_nc<1>(Mx, in, cx->ws.buf0, nin[0], nin[1] * nin[2] * nb, twx, s); break;
+        case 8: e = launch_rows_fwd_nc<8>(Mx, in, cx->ws.buf0, nin[0], nin[1] * nin[2] * nb, twx, s); break;
+        default: e = launch_rows_fwd_nc<16>(Mx, in, cx->ws.buf0, nin[0], nin[1] * nin[2] * nb, twx, s); break;
     }
     if (e != hipSuccess) return e;
     const int64_t W = (int64_t)Mx * NCC;
@@ -538,6 +540,7 @@ hipError_t launch_conv(dpic_ctx* cx, double* in, const int nin[3], double* out, 
     a.gny1 = ny + 1;
     a.Mx = Mx;
     a.My = My;
+    // settings are back to back in every array
     // 2: y forward, A -> B[nin_z][My][Mx]
     a.in_outer = (int64_t)nin[1] * W;
     a.in_stride = W;
@@ -546,7 +549,9 @@ hipError_t launch_conv(dpic_ctx* cx, double* in, const int nin[3], double* out, 
     a.out_stride = W;
     a.n_out = My;
     a.out_shift = 0;
-    if ((e = launch_cols<0>(My, nin[2], a, cx->ws.buf0, cx->ws.buf1, twy, s)) != hipSuccess) return e;
+    a.in_batch = (int64_t)nin[2] * a.in_outer;
+    a.out_batch = (int64_t)nin[2] * a.out_outer;
+    if ((e = launch_cols<0>(My, nin[2], nb, a, cx->ws.buf0, cx->ws.buf1, twy, s)) != hipSuccess) return e;
     // 3: z forward, Ghat, z inverse, B -> C[nout_z][My][Mx]
     a.in_outer = W;
     a.in_stride = (int64_t)My * W;
@@ -555,7 +560,9 @@ hipError_t launch_conv(dpic_ctx* cx, double* in, const int nin[3], double* out, 
     a.out_stride = (int64_t)My * W;
     a.n_out = nout[2];
     a.out_shift = shift;
-    if ((e = launch_cols<1>(Mz, My, a, cx->ws.buf1, cx->ws.buf0, twz, s)) != hipSuccess) return e;
+    a.in_batch = (int64_t)nin[2] * My * W;
+    a.out_batch = (int64_t)nout[2] * My * W;
+    if ((e = launch_cols<1>(Mz, My, nb, a, cx->ws.buf1, cx->ws.buf0, twz, s)) != hipSuccess) return e;
     // 4: y inverse, C -> D[nout_z][nout_y][Mx]
     a.in_outer = (int64_t)My * W;
     a.in_stride = W;
@@ -564,9 +571,11 @@ hipError_t launch_conv(dpic_ctx* cx, double* in, const int nin[3], double* out, 
     a.out_stride = W;
     a.n_out = nout[1];
     a.out_shift = shift;
-    if ((e = launch_cols<2>(My, nout[2], a, cx->ws.buf0, cx->ws.buf1, twy, s)) != hipSuccess) return e;
+    a.in_batch = (int64_t)nout[2] * a.in_outer;
+    a.out_batch = (int64_t)nout[2] * a.out_outer;
+    if ((e = launch_cols<2>(My, nout[2], nb, a, cx->ws.buf0, cx->ws.buf1, twy, s)) != hipSuccess) return e;
     // 5: x inverse, D -> out
-    const int rows = nout[1] * nout[2];
+    const int rows = nout[1] * nout[2] * nb;
     switch (NC) {
         case 1: return launch_rows_inv_nc<1>(Mx, cx->ws.buf1, out, nout[0], shift, rows, twx, s);
         case 8: return launch_rows_inv_nc<8>(Mx, cx->ws.buf1, out, nout[0], shift, rows, twx, s);
@@ -577,7 +586,7 @@ hipError_t launch_conv(dpic_ctx* cx, double* in, const int nin[3], double* out, 
 hipError_t launch_solve(dpic_ctx* cx) {
     const int n[3] = {cx->dims.nx, cx->dims.ny, cx->dims.nz};
     const int g[3] = {n[0] + 2, n[1] + 2, n[2] + 2};
-    return launch_conv(cx, cx->ws.rho, n, cx->ws.phi, g, 1, cx->NC);
+    return launch_conv(cx, cx->ws.rho, n, cx->ws.phi, g, 1, cx->NC, cx->B);
 }
 
 // ---------------------------------------------------------------- Green's function
@@ -696,7 +705,7 @@ hipError_t launch_green(dpic_ctx* cx) {
     a.out_stride = 1;
     a.n_out = Mx;
     a.out_shift = 0;
-    if ((e = launch_cols<0>(Mx, Mz, a, cx->ws.buf0, cx->ws.buf1, twx, s)) != hipSuccess) return e;
+    if ((e = launch_cols<0>(Mx, Mz, 1, a, cx->ws.buf0, cx->ws.buf1, twx, s)) != hipSuccess) return e;
     // y: outer z, columns x (stride 1), rows y (stride Mx)
     a.W = Mx;
     a.bstride = 1;
@@ -704,7 +713,7 @@ hipError_t launch_green(dpic_ctx* cx) {
     a.n_in = My;
     a.out_stride = Mx;
     a.n_out = My;
-    if ((e = launch_cols<0>(My, Mz, a, cx->ws.buf1, cx->ws.buf0, twy, s)) != hipSuccess) return e;
+    if ((e = launch_cols<0>(My, Mz, 1, a, cx->ws.buf1, cx->ws.buf0, twy, s)) != hipSuccess) return e;
     // z: outer y, columns x, rows z (stride Mx My)
     a.in_outer = Mx;
     a.in_stride = (int64_t)Mx * My;
@@ -712,7 +721,7 @@ hipError_t launch_green(dpic_ctx* cx) {
     a.out_outer = Mx;
     a.out_stride = (int64_t)Mx * My;
     a.n_out = Mz;
-    if ((e = launch_cols<0>(Mz, My, a, cx->ws.buf0, cx->ws.buf1, twz, s)) != hipSuccess) return e;
+    if ((e = launch_cols<0>(Mz, My, 1, a, cx->ws.buf0, cx->ws.buf1, twz, s)) != hipSuccess) return e;
     const int64_t oct = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
     hipLaunchKernelGGL(k_green_extract, dim3((unsigned)((oct + 255) / 256)), dim3(256), 0, s, cx->ws.buf1, cx->ws.ghat,
                        nx, ny, nz, 1.0 / (double)total);
@@ -723,19 +732,21 @@ hipError_t launch_green(dpic_ctx* cx) {
 // E = -grad phi by central differences on every node; phi carries one ghost
 // ring. cz includes 1/gamma0 (rest-frame longitudinal field).
 template <int NC>
-__global__ void k_field(const double* __restrict__ phi, double* __restrict__ E, int nx, int ny, int nz, double cx,
-                        double cy, double cz) {
+__global__ void k_field(const double* __restrict__ phi, double* __restrict__ E, int nx, int ny, int nz, int nb,
+                        double cx, double cy, double cz) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)nx * ny * nz * NC;
-    if (gid >= total) return;
+    const int64_t nodes = (int64_t)nx * ny * nz;
+    if (gid >= nodes * NC * nb) return;
     const int c = (int)(gid % NC);
-    const int64_t node = gid / NC;
+    const int64_t gnode = gid / NC;  // node over all settings
+    const int64_t b = gnode / nodes;
+    const int64_t node = gnode - b * nodes;
     const int ix = (int)(node % nx);
     const int iy = (int)((node / nx) % ny);
     const int iz = (int)(node / ((int64_t)nx * ny));
     const int64_t sx = NC, sy = (int64_t)(nx + 2) * NC, sz = (int64_t)(nx + 2) * (ny + 2) * NC;
-    const double* p = phi + (iz + 1) * sz + (iy + 1) * sy + (ix + 1) * sx + c;
-    double* o = E + node * 3 * NC + c;
+    const double* p = phi + b * (nz + 2) * sz + (iz + 1) * sz + (iy + 1) * sy + (ix + 1) * sx + c;
+    double* o = E + gnode * 3 * NC + c;
     o[0] = cx * (p[sx] - p[-sx]);
     o[NC] = cy * (p[sy] - p[-sy]);
     o[2 * NC] = cz * (p[sz] - p[-sz]);
@@ -744,12 +755,13 @@ __global__ void k_field(const double* __restrict__ phi, double* __restrict__ E, 
 hipError_t launch_field(dpic_ctx* cx) {
     const int nx = cx->dims.nx, ny = cx->dims.ny, nz = cx->dims.nz;
     const double fx = -0.5 / cx->h[0], fy = -0.5 / cx->h[1], fz = -0.5 / (cx->h[2] * cx->gamma0);
-    const int64_t total = (int64_t)nx * ny * nz * cx->NC;
+    const int nb = cx->B;
+    const int64_t total = (int64_t)nx * ny * nz * cx->NC * nb;
     dim3 grid((unsigned)((total + 255) / 256)), block(256);
     switch (cx->NC) {
-        case 1: hipLaunchKernelGGL(k_field<1>, grid, block, 0, cx->stream, cx->ws.phi, cx->ws.E, nx, ny, nz, fx, fy, fz); break;
-        case 8: hipLaunchKernelGGL(k_field<8>, grid, block, 0, cx->stream, cx->ws.phi, cx->ws.E, nx, ny, nz, fx, fy, fz); break;
-        default: hipLaunchKernelGGL(k_field<16>, grid, block, 0, cx->stream, cx->ws.phi, cx->ws.E, nx, ny, nz, fx, fy, fz); break;
+        case 1: hipLaunchKernelGGL(k_field<1>, grid, block, 0, cx->stream, cx->ws.phi, cx->ws.E, nx, ny, nz, nb, fx, fy, fz); break;
+        case 8: hipLaunchKernelGGL(k_field<8>, grid, block, 0, cx->stream, cx->ws.phi, cx->ws.E, nx, ny, nz, nb, fx, fy, fz); break;
+        default: hipLaunchKernelGGL(k_field<16>, grid, block, 0, cx->stream, cx->ws.phi, cx->ws.E, nx, ny, nz, nb, fx, fy, fz); break;
     }
     return hipGetLastError();
 }

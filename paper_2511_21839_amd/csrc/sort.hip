@@ -15,8 +15,13 @@
 // The order inside one bin of one block is not fixed. The original particle
 // index travels with the state so read-back stays in the original order.
 //
+// Batches: each setting is sorted within its own storage range (see
+// k_sort_count); bins are per setting.
+//
 // Work list: every bin's particle range is cut into chunks of at most
-// TILE_CHUNK particles; chunk = (tile, first particle, count).
+// `chunk` particles; chunk = (tile, first slot, count, setting).
+#include <algorithm>
+
 #include "context.hpp"
 
 namespace dpic {
@@ -39,25 +44,52 @@ __device__ __forceinline__ uint32_t tile_key(double x, double y, double z, const
 
 constexpr int SORT_THREADS = 1024;
 
+// Sort block k covers storage segment k, which belongs to setting
+// b = owner[k]. Its column of counts sits at
+// nbins * seg0_b + bin * nseg_b + (k - seg0_b) (seg0_b = off_b / SEG, nseg_b
+// the setting's segments): the array is ordered [setting][bin][segment], so
+// one exclusive scan over it gives every particle's packed destination.
+struct SegInfo {
+    int b;
+    int64_t lo, hi;       // slots of this segment holding particles
+    int64_t col, nseg;    // counts index of (bin 0, this segment), segments of the setting
+    int64_t delta;
+};
+
+__device__ __forceinline__ SegInfo seg_info(const SettingDev* set, const int32_t* owner, int nbins, int64_t k) {
+    SegInfo r;
+    r.b = owner[k];
+    const SettingDev sd = set[r.b];
+    const int64_t seg0 = sd.off / SEG;
+    r.nseg = (sd.n + SEG - 1) / SEG;
+    r.lo = k * SEG;
+    const int64_t end = sd.off + sd.n;
+    r.hi = (k + 1) * SEG < end ? (k + 1) * SEG : end;
+    r.col = (int64_t)nbins * seg0 + (k - seg0);
+    r.delta = sd.delta;
+    return r;
+}
+
 template <int NC>
-__global__ __launch_bounds__(SORT_THREADS) void k_sort_count(const double* __restrict__ st, int64_t n, int64_t cap,
-                                                             SortGeom g, uint32_t* __restrict__ key,
-                                                             uint32_t* __restrict__ counts, int nblocks) {
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_count(const double* __restrict__ st, int64_t cap,
+                                                             const SettingDev* __restrict__ set,
+                                                             const int32_t* __restrict__ owner, SortGeom g,
+                                                             uint32_t* __restrict__ key, uint32_t* __restrict__ counts) {
     __shared__ uint32_t h[NUM_TILE_BINS_MAX + 1];
     for (int b = threadIdx.x; b < g.nbins; b += SORT_THREADS) h[b] = 0u;
     __syncthreads();
+    const SegInfo si = seg_info(set, owner, g.nbins, blockIdx.x);
     const int64_t cs = cap * NC;
-    const int64_t p0 = (int64_t)blockIdx.x * SORT_PB;
     for (int i = threadIdx.x; i < SORT_PB; i += SORT_THREADS) {
-        const int64_t p = p0 + i;
-        if (p < n) {
+        const int64_t p = si.lo + i;
+        if (p < si.hi) {
             const uint32_t k = tile_key(st[p * NC], st[2 * cs + p * NC], st[4 * cs + p * NC], g);
             key[p] = k;
             atomicAdd(&h[k], 1u);
         }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < g.nbins; b += SORT_THREADS) counts[(int64_t)b * nblocks + blockIdx.x] = h[b];
+    for (int b = threadIdx.x; b < g.nbins; b += SORT_THREADS) counts[si.col + (int64_t)b * si.nseg] = h[b];
 }
 
 // Exclusive scan of m values in place: per-segment sums, scan of the sums in
@@ -122,59 +154,80 @@ __global__ __launch_bounds__(1024) void k_scan_apply(uint32_t* __restrict__ v, i
 
 template <int NC>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(const double* __restrict__ st,
-                                                               const int32_t* __restrict__ pid, int64_t n,
-                                                               int64_t cap, const uint32_t* __restrict__ key,
+                                                               const int32_t* __restrict__ pid, int64_t cap,
+                                                               const SettingDev* __restrict__ set,
+                                                               const int32_t* __restrict__ owner,
+                                                               const uint32_t* __restrict__ key,
                                                                const uint32_t* __restrict__ offs, int nbins,
-                                                               int nblocks, double* __restrict__ st2,
-                                                               int32_t* __restrict__ pid2) {
+                                                               double* __restrict__ st2, int32_t* __restrict__ pid2) {
     __shared__ uint32_t cur[NUM_TILE_BINS_MAX + 1];
-    for (int b = threadIdx.x; b < nbins; b += SORT_THREADS) cur[b] = offs[(int64_t)b * nblocks + blockIdx.x];
+    const SegInfo si = seg_info(set, owner, nbins, blockIdx.x);
+    for (int b = threadIdx.x; b < nbins; b += SORT_THREADS) cur[b] = offs[si.col + (int64_t)b * si.nseg];
     __syncthreads();
     const int64_t cs = cap * NC;
-    const int64_t p0 = (int64_t)blockIdx.x * SORT_PB;
     // lanes in groups of NC: the group leader claims the slot, every lane copies its channel
     for (int i = threadIdx.x; i < SORT_PB * NC; i += SORT_THREADS) {
-        const int64_t p = p0 + i / NC;
+        const int64_t p = si.lo + i / NC;
         const int c = i % NC;
-        const bool valid = p < n;
+        const bool valid = p < si.hi;
         uint32_t dst = 0;
         if (valid && c == 0) dst = atomicAdd(&cur[key[p]], 1u);
         dst = __shfl(dst, (int)(threadIdx.x & 63) & ~(NC - 1), 64);
         if (valid) {
+            const int64_t d = (int64_t)dst + si.delta;  // packed position -> storage slot
 #pragma unroll
-            for (int j = 0; j < 6; ++j) st2[j * cs + (int64_t)dst * NC + c] = st[j * cs + p * NC + c];
-            if (c == 0) pid2[dst] = pid[p];
+            for (int j = 0; j < 6; ++j) st2[j * cs + d * NC + c] = st[j * cs + p * NC + c];
+            if (c == 0) pid2[d] = pid[p];
         }
     }
 }
 
-// One block: chunk list from the bin ranges. Bin b holds particles
-// [offs[b*nblocks], offs[(b+1)*nblocks]) (n for the last bin).
-__global__ __launch_bounds__(1024) void k_build_chunks(const uint32_t* __restrict__ offs, int nbins, int nblocks,
-                                                       int64_t n, int4* __restrict__ chunks,
+// One block: work list from the bin ranges of every setting. Flattened bin
+// f = b * nbins + bin holds slots [start(b, bin), start(b, bin + 1)), the
+// last bin ending at off_b + n_b; each range is cut into items of at most
+// `chunk` particles: (tile, first slot, count, setting).
+__device__ __forceinline__ void bin_range(const SettingDev* set, const uint32_t* offs, int nbins, int f, int64_t* a,
+                                          int64_t* e) {
+    const int b = f / nbins, bin = f - b * nbins;
+    const SettingDev sd = set[b];
+    const int64_t nseg = (sd.n + SEG - 1) / SEG;
+    if (nseg == 0) {
+        *a = *e = 0;
+        return;
+    }
+    const int64_t base = (int64_t)nbins * (sd.off / SEG);
+    *a = (int64_t)offs[base + (int64_t)bin * nseg] + sd.delta;
+    *e = bin + 1 < nbins ? (int64_t)offs[base + (int64_t)(bin + 1) * nseg] + sd.delta : sd.off + sd.n;
+}
+
+__global__ __launch_bounds__(1024) void k_build_chunks(const SettingDev* __restrict__ set,
+                                                       const uint32_t* __restrict__ offs, int nbins, int nb,
+                                                       int chunk, int4* __restrict__ chunks,
                                                        uint32_t* __restrict__ nchunks) {
     __shared__ uint32_t sh[1024];
-    const int per = (nbins + 1023) / 1024;
-    const int b0 = threadIdx.x * per;
+    const int nf = nbins * nb;
+    const int per = (nf + 1023) / 1024;
+    const int f0 = threadIdx.x * per;
     uint32_t s = 0;
     for (int i = 0; i < per; ++i) {
-        const int b = b0 + i;
-        if (b < nbins) {
-            const uint32_t a = offs[(int64_t)b * nblocks];
-            const uint32_t e = (b + 1 < nbins) ? offs[(int64_t)(b + 1) * nblocks] : (uint32_t)n;
-            s += (e - a + TILE_CHUNK - 1) / TILE_CHUNK;
+        const int f = f0 + i;
+        if (f < nf) {
+            int64_t a, e;
+            bin_range(set, offs, nbins, f, &a, &e);
+            s += (uint32_t)((e - a + chunk - 1) / chunk);
         }
     }
     uint32_t total = 0;
     uint32_t run = block_excl_scan_1024(s, sh, &total);
     for (int i = 0; i < per; ++i) {
-        const int b = b0 + i;
-        if (b < nbins) {
-            const uint32_t a = offs[(int64_t)b * nblocks];
-            const uint32_t e = (b + 1 < nbins) ? offs[(int64_t)(b + 1) * nblocks] : (uint32_t)n;
-            for (uint32_t q = a; q < e; q += TILE_CHUNK) {
-                const uint32_t cnt = (e - q) < (uint32_t)TILE_CHUNK ? (e - q) : (uint32_t)TILE_CHUNK;
-                chunks[run++] = make_int4(b, (int)q, (int)cnt, 0);
+        const int f = f0 + i;
+        if (f < nf) {
+            int64_t a, e;
+            bin_range(set, offs, nbins, f, &a, &e);
+            const int b = f / nbins;
+            for (int64_t q = a; q < e; q += chunk) {
+                const int64_t cnt = (e - q) < chunk ? (e - q) : chunk;
+                chunks[run++] = make_int4(f - b * nbins, (int)q, (int)cnt, b);
             }
         }
     }
@@ -189,6 +242,16 @@ bool sort_geometry(const dpic_ctx* cx, int* tiles, int* nbins) {
         for (int d = 0; d < 3; ++d) tiles[d] = t[d];
     *nbins = t[0] * t[1] * t[2] + 1;
     return *nbins <= NUM_TILE_BINS_MAX + 1;
+}
+
+// Upper bound of the work items: every non-empty (setting, bin) range gives
+// at most one item more than its particles / chunk.
+size_t max_chunks(const dpic_ctx* cx) {
+    int nbins = 0;
+    sort_geometry(cx, nullptr, &nbins);
+    size_t bins = 0;
+    for (int b = 0; b < cx->B; ++b) bins += (size_t)std::min<int64_t>(cx->nb[b], nbins);
+    return bins + (size_t)(cx->n / cx->chunk) + 1;
 }
 
 hipError_t launch_sort(dpic_ctx* cx) {
@@ -209,36 +272,33 @@ hipError_t launch_sort(dpic_ctx* cx) {
     g.tz = t[2];
     hipStream_t s = cx->stream;
     const int64_t cap = cx->dims.n_particles;
-    const int64_t n = cx->n;
-    const int nblocks = (int)((n + SORT_PB - 1) / SORT_PB) > 0 ? (int)((n + SORT_PB - 1) / SORT_PB) : 1;
-    const int64_t m = (int64_t)g.nbins * nblocks;
-    const int nseg = (int)((m + SCAN_SEG - 1) / SCAN_SEG);
-    switch (cx->NC) {
-        case 1: hipLaunchKernelGGL(k_sort_count<1>, dim3(nblocks), dim3(SORT_THREADS), 0, s, cx->ws.st, n, cap, g, cx->ws.key, cx->ws.counts, nblocks); break;
-        case 8: hipLaunchKernelGGL(k_sort_count<8>, dim3(nblocks), dim3(SORT_THREADS), 0, s, cx->ws.st, n, cap, g, cx->ws.key, cx->ws.counts, nblocks); break;
-        default: hipLaunchKernelGGL(k_sort_count<16>, dim3(nblocks), dim3(SORT_THREADS), 0, s, cx->ws.st, n, cap, g, cx->ws.key, cx->ws.counts, nblocks); break;
-    }
-    hipLaunchKernelGGL(k_scan_seg_sums, dim3(nseg), dim3(1024), 0, s, cx->ws.counts, m, cx->ws.seg);
-    hipLaunchKernelGGL(k_scan_seg_offsets, dim3(1), dim3(1024), 0, s, cx->ws.seg, nseg);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nseg), dim3(1024), 0, s, cx->ws.counts, m, cx->ws.seg);
-    if (n > 0) {
+    const Workspace& w = cx->ws;
+    const int nsegs = (int)((cx->used + SEG - 1) / SEG);
+    const int64_t m = (int64_t)g.nbins * nsegs;
+    const int nscan = (int)((m + SCAN_SEG - 1) / SCAN_SEG);
+    if (nsegs > 0) {
         switch (cx->NC) {
-            case 1: hipLaunchKernelGGL(k_sort_scatter<1>, dim3(nblocks), dim3(SORT_THREADS), 0, s, cx->ws.st, cx->ws.pid, n, cap, cx->ws.key, cx->ws.counts, g.nbins, nblocks, cx->ws.st2, cx->ws.pid2); break;
-            case 8: hipLaunchKernelGGL(k_sort_scatter<8>, dim3(nblocks), dim3(SORT_THREADS), 0, s, cx->ws.st, cx->ws.pid, n, cap, cx->ws.key, cx->ws.counts, g.nbins, nblocks, cx->ws.st2, cx->ws.pid2); break;
-            default: hipLaunchKernelGGL(k_sort_scatter<16>, dim3(nblocks), dim3(SORT_THREADS), 0, s, cx->ws.st, cx->ws.pid, n, cap, cx->ws.key, cx->ws.counts, g.nbins, nblocks, cx->ws.st2, cx->ws.pid2); break;
+            case 1: hipLaunchKernelGGL(k_sort_count<1>, dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, w.counts); break;
+            case 8: hipLaunchKernelGGL(k_sort_count<8>, dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, w.counts); break;
+            default: hipLaunchKernelGGL(k_sort_count<16>, dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, w.counts); break;
+        }
+        hipLaunchKernelGGL(k_scan_seg_sums, dim3(nscan), dim3(1024), 0, s, w.counts, m, w.seg);
+        hipLaunchKernelGGL(k_scan_seg_offsets, dim3(1), dim3(1024), 0, s, w.seg, nscan);
+        hipLaunchKernelGGL(k_scan_apply, dim3(nscan), dim3(1024), 0, s, w.counts, m, w.seg);
+        switch (cx->NC) {
+            case 1: hipLaunchKernelGGL(k_sort_scatter<1>, dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, w.pid, cap, w.set, w.owner, w.key, w.counts, g.nbins, w.st2, w.pid2); break;
+            case 8: hipLaunchKernelGGL(k_sort_scatter<8>, dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, w.pid, cap, w.set, w.owner, w.key, w.counts, g.nbins, w.st2, w.pid2); break;
+            default: hipLaunchKernelGGL(k_sort_scatter<16>, dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, w.pid, cap, w.set, w.owner, w.key, w.counts, g.nbins, w.st2, w.pid2); break;
         }
     }
-    hipLaunchKernelGGL(k_build_chunks, dim3(1), dim3(1024), 0, s, cx->ws.counts, g.nbins, nblocks, n, cx->ws.chunks,
-                       cx->ws.nchunks);
+    hipLaunchKernelGGL(k_build_chunks, dim3(1), dim3(1024), 0, s, w.set, w.counts, g.nbins, cx->B, (int)cx->chunk,
+                       w.chunks, w.nchunks);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (n > 0) {
-        double* tmp = cx->ws.st;
-        cx->ws.st = cx->ws.st2;
-        cx->ws.st2 = tmp;
-        int32_t* q = cx->ws.pid;
-        cx->ws.pid = cx->ws.pid2;
-        cx->ws.pid2 = q;
+    if (nsegs > 0) {
+        std::swap(cx->ws.st, cx->ws.st2);
+        std::swap(cx->ws.pid, cx->ws.pid2);
+        cx->swapped = !cx->swapped;
     }
     cx->chunks_valid = true;
     return hipSuccess;

@@ -25,7 +25,8 @@ DPIC_EUNSUPPORTED = -5
 
 GRID_RHO, GRID_PHI, GRID_E = 0, 1, 2
 STAGE_DEPOSIT, STAGE_SOLVE, STAGE_FIELD = 0, 1, 2
-OPT_SORT_EVERY, OPT_STAGE_TIMING = 1, 2
+OPT_SORT_EVERY, OPT_STAGE_TIMING, OPT_CHUNK, OPT_PART_BLOCKS, OPT_GRAPH = 1, 2, 3, 4, 5
+SEG = 1024  # each setting of a batch starts on a multiple of this many storage slots
 N_STAGE_TIMERS = 4
 STAGE_TIMER_NAMES = ("particles", "solve", "field", "sort")
 
@@ -37,10 +38,11 @@ _ERRNAMES = {
 # exported symbols, in header order (the CPU tests check that each is present)
 SYMBOLS = (
     "dpic_version", "dpic_query_workspace", "dpic_create", "dpic_destroy", "dpic_last_error",
-    "dpic_set_beam", "dpic_set_grid", "dpic_set_lattice", "dpic_set_params", "dpic_init_beam",
-    "dpic_step", "dpic_read_moments", "dpic_read_emittance", "dpic_read_particles",
-    "dpic_counters", "dpic_stage", "dpic_read_grid", "dpic_write_grid", "dpic_state_bytes",
-    "dpic_save_state", "dpic_load_state", "dpic_set_option", "dpic_stage_times",
+    "dpic_set_beam", "dpic_set_grid", "dpic_set_lattice", "dpic_set_params", "dpic_set_params_batch",
+    "dpic_init_beam", "dpic_init_beam_batch", "dpic_step", "dpic_read_moments", "dpic_read_emittance",
+    "dpic_read_particles", "dpic_counters", "dpic_batch_counters", "dpic_stage", "dpic_read_grid",
+    "dpic_write_grid", "dpic_state_bytes", "dpic_save_state", "dpic_load_state", "dpic_set_option",
+    "dpic_get_option", "dpic_autotune", "dpic_stage_times",
     "dpic_adjoint_query", "dpic_adjoint_bind", "dpic_adjoint_backward",
 )
 
@@ -53,7 +55,8 @@ class DpicError(RuntimeError):
 
 class dpic_dims(ctypes.Structure):
     _fields_ = [("n_particles", ctypes.c_int64), ("ntan", ctypes.c_int32), ("nx", ctypes.c_int32),
-                ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("nbatch", ctypes.c_int32)]
 
 
 _lib = None
@@ -73,12 +76,15 @@ _SIGS = {
     "dpic_set_grid": ([_P, _D, _D], ctypes.c_int),
     "dpic_set_lattice": ([_P, ctypes.c_int, _I, _I, _D, _D, _I, _I, ctypes.c_int], ctypes.c_int),
     "dpic_set_params": ([_P, ctypes.c_int, _D, _D], ctypes.c_int),
+    "dpic_set_params_batch": ([_P, ctypes.c_int, ctypes.c_int, _D, _D], ctypes.c_int),
     "dpic_init_beam": ([_P, ctypes.c_int64, _P, _D, _D], ctypes.c_int),
+    "dpic_init_beam_batch": ([_P, ctypes.c_int, _I64, _P, _D, _D], ctypes.c_int),
     "dpic_step": ([_P, ctypes.c_int], ctypes.c_int),
     "dpic_read_moments": ([_P, _D], ctypes.c_int),
     "dpic_read_emittance": ([_P, ctypes.c_int, _D], ctypes.c_int),
     "dpic_read_particles": ([_P, _D], ctypes.c_int),
     "dpic_counters": ([_P, _I64, _I64, _D], ctypes.c_int),
+    "dpic_batch_counters": ([_P, _I64], ctypes.c_int),
     "dpic_stage": ([_P, ctypes.c_int], ctypes.c_int),
     "dpic_read_grid": ([_P, ctypes.c_int, _D], ctypes.c_int),
     "dpic_write_grid": ([_P, ctypes.c_int, _D], ctypes.c_int),
@@ -86,6 +92,8 @@ _SIGS = {
     "dpic_save_state": ([_P, _P], ctypes.c_int),
     "dpic_load_state": ([_P, _P], ctypes.c_int),
     "dpic_set_option": ([_P, ctypes.c_int, ctypes.c_int64], ctypes.c_int),
+    "dpic_get_option": ([_P, ctypes.c_int, _I64], ctypes.c_int),
+    "dpic_autotune": ([_P, _P, ctypes.c_size_t, ctypes.c_int, _I64, _D], ctypes.c_int),
     "dpic_stage_times": ([_P, _D, _I64], ctypes.c_int),
     "dpic_adjoint_query": ([ctypes.POINTER(dpic_dims), ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
                            ctypes.c_int),
@@ -142,8 +150,14 @@ def dpic_version() -> int:
     return lib().dpic_version()
 
 
-def make_dims(n_particles: int, ntan: int, grid: Sequence[int]) -> dpic_dims:
-    return dpic_dims(int(n_particles), int(ntan), int(grid[0]), int(grid[1]), int(grid[2]), 0)
+def make_dims(n_particles: int, ntan: int, grid: Sequence[int], nbatch: int = 1) -> dpic_dims:
+    return dpic_dims(int(n_particles), int(ntan), int(grid[0]), int(grid[1]), int(grid[2]), 0, int(nbatch))
+
+
+def batch_capacity(ns: Sequence[int]) -> int:
+    """Storage slots that settings with these particle counts need."""
+    ns = [int(v) for v in ns]
+    return sum((v + SEG - 1) // SEG * SEG for v in ns[:-1]) + (ns[-1] if ns else 0)
 
 
 def dpic_query_workspace(dims: dpic_dims) -> int:
@@ -195,6 +209,26 @@ def dpic_set_params(ctx, p, seed=None, ntan: Optional[int] = None):
     _check(ctx, lib().dpic_set_params(ctx, len(p), _dp(p), _dp(s)))
 
 
+def dpic_set_params_batch(ctx, p, seed=None):
+    p = _f64(p)
+    if p.ndim != 2:
+        raise ValueError("p must be [nbatch][np]")
+    s = None
+    if seed is not None:
+        s = _f64(seed)
+        if s.size == 0:
+            s = None
+    _check(ctx, lib().dpic_set_params_batch(ctx, p.shape[0], p.shape[1], _dp(p), _dp(s)))
+
+
+def dpic_init_beam_batch(ctx, ns, xi_dev_ptr: int, sigma, sigma_seed=None):
+    n = np.ascontiguousarray(np.asarray(ns, dtype=np.int64))
+    sigma = _f64(sigma, (len(n), 6))
+    ss = None if sigma_seed is None else _f64(sigma_seed)
+    _check(ctx, lib().dpic_init_beam_batch(ctx, len(n), n.ctypes.data_as(_I64), _P(xi_dev_ptr) if xi_dev_ptr else None,
+                                           _dp(sigma), _dp(ss)))
+
+
 def dpic_init_beam(ctx, n: int, xi_dev_ptr: int, sigma, sigma_seed=None):
     sigma = _f64(sigma, (6,))
     ss = None if sigma_seed is None else _f64(sigma_seed)
@@ -205,14 +239,14 @@ def dpic_step(ctx, n: int):
     _check(ctx, lib().dpic_step(ctx, int(n)))
 
 
-def dpic_read_moments(ctx, ntan: int) -> np.ndarray:
-    out = np.empty((3, 5, ntan + 1))
+def dpic_read_moments(ctx, ntan: int, nbatch: int = 1) -> np.ndarray:
+    out = np.empty((nbatch, 3, 5, ntan + 1))
     _check(ctx, lib().dpic_read_moments(ctx, _dp(out)))
     return out
 
 
-def dpic_read_emittance(ctx, ntan: int, centred: bool = False) -> np.ndarray:
-    out = np.empty((3, ntan + 1))
+def dpic_read_emittance(ctx, ntan: int, centred: bool = False, nbatch: int = 1) -> np.ndarray:
+    out = np.empty((nbatch, 3, ntan + 1))
     _check(ctx, lib().dpic_read_emittance(ctx, int(bool(centred)), _dp(out)))
     return out
 
@@ -230,6 +264,12 @@ def dpic_counters(ctx):
     return oob.value, steps.value, ext
 
 
+def dpic_batch_counters(ctx, nbatch: int) -> np.ndarray:
+    out = np.zeros(nbatch, dtype=np.int64)
+    _check(ctx, lib().dpic_batch_counters(ctx, out.ctypes.data_as(_I64)))
+    return out
+
+
 def dpic_stage(ctx, stage: int):
     _check(ctx, lib().dpic_stage(ctx, int(stage)))
 
@@ -245,8 +285,8 @@ def grid_shape(which: int, grid: Sequence[int], ntan: int):
     raise ValueError(which)
 
 
-def dpic_read_grid(ctx, which: int, grid, ntan: int) -> np.ndarray:
-    out = np.empty(grid_shape(which, grid, ntan))
+def dpic_read_grid(ctx, which: int, grid, ntan: int, nbatch: int = 1) -> np.ndarray:
+    out = np.empty((nbatch,) + grid_shape(which, grid, ntan))
     _check(ctx, lib().dpic_read_grid(ctx, int(which), _dp(out)))
     return out
 
@@ -272,6 +312,20 @@ def dpic_load_state(ctx, dev_ptr: int):
 
 def dpic_set_option(ctx, option: int, value: int):
     _check(ctx, lib().dpic_set_option(ctx, int(option), int(value)))
+
+
+def dpic_get_option(ctx, option: int) -> int:
+    v = ctypes.c_int64(0)
+    _check(ctx, lib().dpic_get_option(ctx, int(option), ctypes.byref(v)))
+    return v.value
+
+
+def dpic_autotune(ctx, scratch_ptr: int, scratch_bytes: int, trial_steps: int):
+    best = np.zeros(3, dtype=np.int64)
+    ms = ctypes.c_double(0.0)
+    _check(ctx, lib().dpic_autotune(ctx, _P(scratch_ptr), scratch_bytes, int(trial_steps),
+                                    best.ctypes.data_as(_I64), ctypes.byref(ms)))
+    return {"sort_every": int(best[0]), "chunk": int(best[1]), "part_blocks": int(best[2]), "ms": ms.value}
 
 
 def dpic_stage_times(ctx):
@@ -301,9 +355,14 @@ def dpic_adjoint_backward(ctx, weights, n_params: int):
 
 # ---------------------------------------------------------------- convenience
 class Simulation:
-    """One context with its torch-owned workspace, on torch's current stream."""
+    """One context with its torch-owned workspace, on torch's current stream.
 
-    def __init__(self, n_particles: int, ntan: int, grid: Sequence[int], device: str = "cuda"):
+    With nbatch > 1 the context runs that many settings together: use
+    set_params_batch and init_beam_batch, and the readers return arrays with a
+    leading setting index. n_particles is the storage capacity (see
+    batch_capacity)."""
+
+    def __init__(self, n_particles: int, ntan: int, grid: Sequence[int], device: str = "cuda", nbatch: int = 1):
         import torch  # device memory and streams only
 
         if not torch.cuda.is_available():
@@ -312,7 +371,8 @@ class Simulation:
         self.ntan = int(ntan)
         self.grid = tuple(int(g) for g in grid)
         self.capacity = int(n_particles)
-        self.dims = make_dims(n_particles, ntan, grid)
+        self.nbatch = int(nbatch)
+        self.dims = make_dims(n_particles, ntan, grid, nbatch)
         nbytes = dpic_query_workspace(self.dims)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         base = self.workspace.data_ptr()
@@ -346,12 +406,26 @@ class Simulation:
     def set_params(self, p, seed=None):
         dpic_set_params(self.ctx, p, seed)
 
+    def set_params_batch(self, p, seed=None):
+        dpic_set_params_batch(self.ctx, p, seed)
+
     def init_beam(self, xi: np.ndarray, sigma, sigma_seed=None):
         torch = self.torch
         xi = np.ascontiguousarray(xi, dtype=np.float64)
         self._xi = torch.from_numpy(xi).to(device=self.workspace.device)
         self.n = xi.shape[0]
         dpic_init_beam(self.ctx, self.n, self._xi.data_ptr(), sigma, sigma_seed)
+
+    def init_beam_batch(self, ns, xi: np.ndarray, sigmas, sigma_seed=None):
+        """Setting b takes rows [sum(ns[:b]), + ns[b]) of xi [sum ns][6] and sizes sigmas[b]."""
+        torch = self.torch
+        xi = np.ascontiguousarray(xi, dtype=np.float64).reshape(-1, 6)
+        if xi.shape[0] != int(np.sum(ns)):
+            raise ValueError("xi must hold sum(ns) rows")
+        self._xi = torch.from_numpy(xi).to(device=self.workspace.device)
+        self.n = xi.shape[0]
+        self.ns = [int(v) for v in ns]
+        dpic_init_beam_batch(self.ctx, ns, self._xi.data_ptr(), sigmas, sigma_seed)
 
     # -- run --------------------------------------------------------------
     def step(self, n: int):
@@ -361,11 +435,14 @@ class Simulation:
         dpic_stage(self.ctx, stage)
 
     # -- read ---------------------------------------------------------------
+    def _unbatch(self, a):
+        return a[0] if self.nbatch == 1 else a
+
     def moments(self):
-        return dpic_read_moments(self.ctx, self.ntan)
+        return self._unbatch(dpic_read_moments(self.ctx, self.ntan, self.nbatch))
 
     def emittance(self, centred=False):
-        return dpic_read_emittance(self.ctx, self.ntan, centred)
+        return self._unbatch(dpic_read_emittance(self.ctx, self.ntan, centred, self.nbatch))
 
     def particles(self):
         return dpic_read_particles(self.ctx, self.n, self.ntan)
@@ -373,8 +450,11 @@ class Simulation:
     def counters(self):
         return dpic_counters(self.ctx)
 
+    def batch_counters(self):
+        return dpic_batch_counters(self.ctx, self.nbatch)
+
     def read_grid(self, which):
-        return dpic_read_grid(self.ctx, which, self.grid, self.ntan)
+        return self._unbatch(dpic_read_grid(self.ctx, which, self.grid, self.ntan, self.nbatch))
 
     def write_grid(self, which, data):
         dpic_write_grid(self.ctx, which, data)
@@ -382,8 +462,19 @@ class Simulation:
     def set_option(self, option, value):
         dpic_set_option(self.ctx, option, value)
 
+    def get_option(self, option):
+        return dpic_get_option(self.ctx, option)
+
     def stage_times(self):
         return dpic_stage_times(self.ctx)
+
+    def autotune(self, trial_steps: int):
+        """Time candidate work-item sizes, grid sizes and sort cadences from the
+        current state (which is restored) and keep the fastest."""
+        nbytes = dpic_state_bytes(self.ctx)
+        scratch = self.torch.empty(nbytes + 256, dtype=self.torch.uint8, device=self.workspace.device)
+        ptr = (scratch.data_ptr() + 255) // 256 * 256
+        return dpic_autotune(self.ctx, ptr, nbytes, trial_steps)
 
     def synchronize(self):
         self.stream.synchronize()

@@ -41,7 +41,11 @@ __all__ = [
     "PARAM_NAMES",
     "c1",
     "c2",
+    "c4",
+    "c5_inputs",
     "tiny",
+    "Batch",
+    "perturbed_batch",
 ]
 
 # Recipe constants (CODATA 2018); used only to turn a peak current into a
@@ -245,3 +249,76 @@ def tiny(n_particles: int = 3001, grid: int = 16, steps_per_element: int = 4,
         bunch_charge_C=bunch_charge_from_peak_current(100.0, SIGMA_NOMINAL[4]),
     )
     return w.with_(**kw) if kw else w
+
+
+# ---------------------------------------------------------------- batches
+@dataclasses.dataclass
+class Batch:
+    """Settings that share grid, beam energy, bunch charge and lattice
+    structure, each with its own parameters, beam sizes, particle count and
+    normals (drawn with its own seed)."""
+
+    base: Workload
+    params: np.ndarray   # [B][7]
+    sigma: np.ndarray    # [B][6]
+    ns: np.ndarray       # [B] particles per setting
+    seeds: np.ndarray    # [B] normal-draw seeds
+
+    @property
+    def nbatch(self) -> int:
+        return len(self.ns)
+
+    def setting(self, b: int) -> Workload:
+        """Setting b as a single-run workload (same inputs)."""
+        return self.base.with_(params=tuple(float(v) for v in self.params[b]),
+                               sigma=tuple(float(v) for v in self.sigma[b]),
+                               n_particles=int(self.ns[b]), seed=int(self.seeds[b]))
+
+    def xi(self) -> np.ndarray:
+        """Packed normals [sum ns][6]: setting b's rows follow those of 0..b-1."""
+        parts = [truncated_normals(int(n), int(s)) for n, s in zip(self.ns, self.seeds)]
+        return np.concatenate(parts, axis=0) if parts else np.zeros((0, 6))
+
+
+def perturbed_batch(base: Workload, ns: Sequence[int], seed: int, rel: float = 0.05,
+                    perturb_sigma: bool = False) -> Batch:
+    """Parameters (and optionally beam sizes) uniform within +-rel of the
+    base workload's, one seeded draw per setting."""
+    rng = np.random.default_rng(seed)
+    B = len(ns)
+    p = np.asarray(base.params, dtype=np.float64)[None, :] * (1.0 + rng.uniform(-rel, rel, size=(B, len(base.params))))
+    s = np.tile(np.asarray(base.sigma, dtype=np.float64), (B, 1))
+    if perturb_sigma:
+        s = s * (1.0 + rng.uniform(-rel, rel, size=(B, 6)))
+    seeds = base.seed + 1000 + np.arange(B)
+    return Batch(base=base, params=p, sigma=s, ns=np.asarray(ns, dtype=np.int64), seeds=seeds)
+
+
+def c4(nbatch: int = 64, seed: int = 20251124, **kw) -> Batch:
+    """64 settings of the 64^3-grid beam (tune ratio 0.3 bunch charge) over 5
+    FODO cells (500 steps), parameters uniform within +-5% of nominal,
+    particle counts log-uniform in [1e5, 1e6]."""
+    rng = np.random.default_rng(seed)
+    ns = np.rint(10.0 ** rng.uniform(5.0, 6.0, size=nbatch)).astype(np.int64)
+    I = peak_current_for_tune_depression(0.3, 1e-3, 1e-6)
+    base = Workload(
+        name=f"c4: {nbatch} settings, 1e5-1e6 protons each, 64^3 grid, 5 FODO cells, 500 steps, eta=0.3",
+        n_particles=int(ns.max()),
+        seed=seed,
+        grid=(64, 64, 64),
+        lo=tuple(-h for h in C2_HALF),
+        hi=C2_HALF,
+        lattice=fodo_lattice(20, 5),
+        ntan=7,
+        bunch_charge_C=bunch_charge_from_peak_current(I, SIGMA_NOMINAL[4]),
+    )
+    base = base.with_(**kw) if kw else base
+    return perturbed_batch(base, ns, seed + 1)
+
+
+def c5_inputs(n_runs: int, seed: int = 20251125, rel: float = 0.05) -> np.ndarray:
+    """[n_runs][13]: the 7 lattice parameters and 6 beam sizes, each uniform
+    within +-rel of nominal (the surrogate's training and test inputs)."""
+    rng = np.random.default_rng(seed)
+    nominal = np.concatenate([NOMINAL_PARAMS, SIGMA_NOMINAL])
+    return nominal[None, :] * (1.0 + rng.uniform(-rel, rel, size=(n_runs, 13)))

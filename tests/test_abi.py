@@ -30,7 +30,13 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version():
-    assert dpic.dpic_version() == 10000
+    assert dpic.dpic_version() == 10100
+
+
+def test_dims_struct_matches_header():
+    # int64 capacity, then ntan, nx, ny, nz, flags, nbatch (int32)
+    assert ctypes.sizeof(dpic.dpic_dims) == 32
+    assert dpic.dpic_dims.nbatch.offset == 28
 
 
 def test_workspace_query_and_dimension_checks():
@@ -92,6 +98,50 @@ def test_call_order_and_argument_errors():
         dpic.dpic_set_option(ctx, dpic.OPT_SORT_EVERY, 10)
     finally:
         dpic.dpic_destroy(ctx)
+
+
+def test_batch_capacity_rule():
+    # every setting but the last starts on a multiple of 1024 slots
+    assert dpic.batch_capacity([1000]) == 1000
+    assert dpic.batch_capacity([1000, 1]) == 1025
+    assert dpic.batch_capacity([0, 2048, 5]) == 2053
+    assert dpic.batch_capacity([1024, 1025, 7]) == 1024 + 2048 + 7
+
+
+def test_batch_host_checks():
+    d = dpic.make_dims(3000, 7, (16, 16, 16), nbatch=3)
+    need = dpic.dpic_query_workspace(d)
+    assert need > dpic.dpic_query_workspace(dpic.make_dims(3000, 7, (16, 16, 16)))
+    ctx = dpic.dpic_create(d, 0x100000, need, 0)
+    try:
+        with pytest.raises(dpic.DpicError) as ei:
+            dpic.dpic_set_params_batch(ctx, np.ones((2, 7)))  # wrong number of settings
+        assert ei.value.code == dpic.DPIC_EINVAL
+        with pytest.raises(dpic.DpicError) as ei:  # the single-setting call needs B = 1
+            dpic.dpic_init_beam(ctx, 10, 0x200000, np.ones(6))
+        assert ei.value.code == dpic.DPIC_ESTATE
+        with pytest.raises(dpic.DpicError) as ei:  # 1024 + 1024 + 1000 > 3000 slots
+            dpic.dpic_init_beam_batch(ctx, [1000, 1000, 1000], 0x200000, np.ones((3, 6)))
+        assert ei.value.code == dpic.DPIC_EINVAL and "capacity" in str(ei.value)
+        with pytest.raises(dpic.DpicError):
+            dpic.dpic_init_beam_batch(ctx, [10, -1, 10], 0x200000, np.ones((3, 6)))
+        for bad in (100, 130, 16384):
+            with pytest.raises(dpic.DpicError):
+                dpic.dpic_set_option(ctx, dpic.OPT_CHUNK, bad)
+        dpic.dpic_set_option(ctx, dpic.OPT_CHUNK, 512)
+        assert dpic.dpic_get_option(ctx, dpic.OPT_CHUNK) == 512
+        dpic.dpic_set_option(ctx, dpic.OPT_GRAPH, 1)
+        assert dpic.dpic_get_option(ctx, dpic.OPT_GRAPH) == 1
+        with pytest.raises(dpic.DpicError) as ei:  # reverse mode runs one setting per context
+            dpic.dpic_adjoint_bind(ctx, 0x100000, 1 << 30, 10, 5)
+        assert ei.value.code == dpic.DPIC_EUNSUPPORTED
+    finally:
+        dpic.dpic_destroy(ctx)
+    with pytest.raises(dpic.DpicError):
+        dpic.dpic_query_workspace(dpic.make_dims(3000, 7, (16, 16, 16), nbatch=5000))
+    with pytest.raises(dpic.DpicError) as ei:
+        dpic.dpic_adjoint_query(dpic.make_dims(3000, 0, (16, 16, 16), nbatch=2), 10, 5)
+    assert ei.value.code == dpic.DPIC_EUNSUPPORTED
 
 
 def test_binding_has_no_compute_fallback():
