@@ -219,13 +219,8 @@ def _batched_timing():
     c4 = synth.c4()
     r4 = _batch_vs_singles(c4, c4.base.total_steps(), autotune_steps=20)
     r4["workload"] = c4.base.name
-    base5 = synth.c1(ntan=13, sigma_tangents=True)
-    x = synth.c5_inputs(256, seed=7)
-    import numpy as np
-
-    b5 = synth.Batch(base=base5, params=x[:, :7], sigma=x[:, 7:], ns=np.full(256, base5.n_particles),
-                     seeds=base5.seed + np.arange(256))
-    r5 = _batch_vs_singles(b5, base5.total_steps(), graph=True)
+    b5 = synth.c5_batch(256, seed=7)
+    r5 = _batch_vs_singles(b5, b5.base.total_steps(), graph=True)
     r5["workload"] = "256 settings of 1e4 protons, 32^3 grid, 100 steps, 13 tangents (inputs +-5%), graph replay"
     return {"c4": r4, "c1x256": r5}
 

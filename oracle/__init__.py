@@ -17,9 +17,12 @@ Modules
               self term
   pic      -- deposit, solve, field, gather, kick, split-operator step,
               moments and emittances (Sec. 4)
+  mlp      -- the emittance surrogate: MLP with its input Jacobian, the
+              Sobolev loss and its weight gradient (exact, and with the
+              rounding points of a BF16 matrix-core implementation)
 
 Every function is pinned by the tests in tests/test_oracle_*.py against
 closed forms, brute force, invariants or finite differences; the pins are
 listed per function in the module docstrings.
 """
-from . import dual, physics, lattice, green, pic  # noqa: F401
+from . import dual, physics, lattice, green, pic, mlp  # noqa: F401

@@ -43,6 +43,8 @@ __all__ = [
     "c2",
     "c4",
     "c5_inputs",
+    "c5_base",
+    "c5_batch",
     "tiny",
     "Batch",
     "perturbed_batch",
@@ -199,6 +201,12 @@ class Workload:
 # lengthens the bunch) settles at half-widths (13.87, 15.86, 29.62) mm.
 C1_HALF = (4.6e-3, 8.0e-3, 9.2e-3)
 C2_HALF = (14.0e-3, 16.0e-3, 30.0e-3)
+# Batched workloads, from the batched pre-pass over all their settings:
+# c4's 64 settings settle at half-widths (18.48, 21.91, 14.72) mm; 1024
+# settings spanning the surrogate's +-5% input box at (4.79, 8.96, 9.48) mm,
+# recorded with 5% more so that other draws from that box stay inside.
+C4_HALF = (18.5e-3, 22.0e-3, 14.8e-3)
+C5_HALF = (5.0e-3, 9.4e-3, 10.0e-3)
 
 
 def c1(ntan: int = 7, **kw) -> Workload:
@@ -306,14 +314,30 @@ def c4(nbatch: int = 64, seed: int = 20251124, **kw) -> Batch:
         n_particles=int(ns.max()),
         seed=seed,
         grid=(64, 64, 64),
-        lo=tuple(-h for h in C2_HALF),
-        hi=C2_HALF,
+        lo=tuple(-h for h in C4_HALF),
+        hi=C4_HALF,
         lattice=fodo_lattice(20, 5),
         ntan=7,
         bunch_charge_C=bunch_charge_from_peak_current(I, SIGMA_NOMINAL[4]),
     )
     base = base.with_(**kw) if kw else base
     return perturbed_batch(base, ns, seed + 1)
+
+
+def c5_base(ntan: int = 13) -> Workload:
+    """The surrogate's training run: the 1e4-particle, 32^3, 100-step
+    workload on a box that holds every input of the +-5% box, with the 13
+    inputs (7 lattice parameters, 6 beam sizes) as tangents."""
+    return c1(ntan=ntan, sigma_tangents=ntan == 13, lo=tuple(-h for h in C5_HALF), hi=C5_HALF,
+              name="c5: 1e4 protons, 32^3 grid, 1 FODO cell, 100 steps, 100 A, inputs +-5%")
+
+
+def c5_batch(n_runs: int, seed: int = 20251125, ntan: int = 13) -> Batch:
+    """n_runs settings of c5_base at inputs c5_inputs(n_runs, seed)."""
+    base = c5_base(ntan)
+    x = c5_inputs(n_runs, seed)
+    return Batch(base=base, params=x[:, :7], sigma=x[:, 7:], ns=np.full(n_runs, base.n_particles, dtype=np.int64),
+                 seeds=base.seed + 10_000 + (seed % 1000) * 100_000 + np.arange(n_runs))
 
 
 def c5_inputs(n_runs: int, seed: int = 20251125, rel: float = 0.05) -> np.ndarray:
