@@ -416,14 +416,18 @@ class Simulation:
         self.n = xi.shape[0]
         dpic_init_beam(self.ctx, self.n, self._xi.data_ptr(), sigma, sigma_seed)
 
-    def init_beam_batch(self, ns, xi: np.ndarray, sigmas, sigma_seed=None):
-        """Setting b takes rows [sum(ns[:b]), + ns[b]) of xi [sum ns][6] and sizes sigmas[b]."""
+    def init_beam_batch(self, ns, xi, sigmas, sigma_seed=None):
+        """Setting b takes rows [sum(ns[:b]), + ns[b]) of xi [sum ns][6] (numpy,
+        or a float64 tensor on the device) and sizes sigmas[b]."""
         torch = self.torch
-        xi = np.ascontiguousarray(xi, dtype=np.float64).reshape(-1, 6)
-        if xi.shape[0] != int(np.sum(ns)):
+        if isinstance(xi, torch.Tensor):
+            self._xi = xi.to(device=self.workspace.device, dtype=torch.float64).reshape(-1, 6).contiguous()
+        else:
+            xi = np.ascontiguousarray(xi, dtype=np.float64).reshape(-1, 6)
+            self._xi = torch.from_numpy(xi).to(device=self.workspace.device)
+        if self._xi.shape[0] != int(np.sum(ns)):
             raise ValueError("xi must hold sum(ns) rows")
-        self._xi = torch.from_numpy(xi).to(device=self.workspace.device)
-        self.n = xi.shape[0]
+        self.n = int(self._xi.shape[0])
         self.ns = [int(v) for v in ns]
         dpic_init_beam_batch(self.ctx, ns, self._xi.data_ptr(), sigmas, sigma_seed)
 

@@ -1,0 +1,215 @@
+"""The surrogate's kernels (BF16 MFMA, FP32 accumulation) through the C ABI
+against the CPU oracle (oracle/mlp.py in its BF16-rounding mode), training
+on the GPU, and what the trained network gains as a screen in front of the
+PIC code.
+
+Tolerances: both sides round the same quantities to BF16 (inputs, hidden
+activations and tangents, backward products) and the weights are BF16-exact,
+so they differ by FP32 against FP64 accumulation (~1e-6 relative over 256
+terms) plus the few BF16 roundings that the two accumulations send to
+neighbouring values (one BF16 step, 2^-8 relative, in one element, diluted
+by the next layer). Outputs and Jacobians: 2e-3 normwise; loss: 1e-3
+relative; weight gradients: 1e-2 normwise per layer tensor (a flipped
+rounding in a backward product enters every term of a gradient sum).
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+NOM = np.array([0.1, 0.1, 22.0, 0.2, 0.1, -22.0, 0.1, 1e-3, 1e-3, 1e-3, 1e-3, 2e-3, 1e-3])
+OC, OS = np.array([1.1e-6, 1.3e-6]), np.array([4e-8, 6e-8])
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+
+
+def _bf16_params(seed, scale=1.0):
+    from paper_2511_21839_amd import surrogate as sg
+
+    p = sg.init_params(np.random.default_rng(seed)).astype(np.float64)
+    widths = sg.WIDTHS
+    layers = mlp.unflatten(p, widths)
+    layers = [(mlp.round_bf16(scale * W), b) for W, b in layers]
+    return mlp.flatten(layers).astype(np.float32), layers
+
+
+def _net(nmax, params):
+    from paper_2511_21839_amd import surrogate as sg
+
+    net = sg.Surrogate(nmax)
+    net.set_normalization(NOM, 0.05 * np.abs(NOM), OC, OS)
+    net.set_params(params)
+    return net
+
+
+def _inputs(n, seed):
+    rng = np.random.default_rng(seed)
+    return NOM * (1.0 + rng.uniform(-0.05, 0.05, size=(n, 13)))
+
+
+def _u(x):
+    return (x - NOM) / (0.05 * np.abs(NOM))
+
+
+@pytest.mark.parametrize("n", [1, 37, 300])
+def test_forward_values_and_jacobian_match_oracle(n):
+    flat, layers = _bf16_params(1, scale=2.0)
+    net = _net(512, flat)
+    x = _inputs(n, 2)
+    eps, jac = net.predict(x)
+    o, J, _ = mlp.forward(layers, _u(x), bf16=True)
+    o_gpu = (eps - OC) / OS
+    J_gpu = jac * (0.05 * np.abs(NOM))[None, None, :] / OS[None, :, None]
+    assert np.abs(o_gpu - o).max() <= 2e-3 * np.abs(o).max()
+    assert np.abs(J_gpu - J).max() <= 2e-3 * np.abs(J).max()
+    # the exact (unrounded) network is within BF16 accuracy of both
+    oe, Je, _ = mlp.forward(layers, _u(x))
+    assert np.abs(o_gpu - oe).max() <= 5e-2 * np.abs(oe).max()
+
+
+@pytest.mark.parametrize("n,wv,wj", [(64, 1.0, 1.0), (333, 0.3, 2.0)])
+def test_loss_gradient_matches_oracle(n, wv, wj):
+    from paper_2511_21839_amd import surrogate as sg
+
+    flat, layers = _bf16_params(3, scale=2.0)
+    net = _net(512, flat)
+    x = _inputs(n, 4)
+    rng = np.random.default_rng(5)
+    eps_t = OC + OS * rng.normal(size=(n, 2))
+    jac_t = (OS[None, :, None] / (0.05 * np.abs(NOM))[None, None, :]) * rng.normal(size=(n, 2, 13))
+    loss, g = net.loss_grad(x, eps_t, jac_t, wv, wj)
+    y = (eps_t - OC) / OS
+    G = jac_t * (0.05 * np.abs(NOM))[None, None, :] / OS[:, None]
+    want_loss, want = mlp.loss_and_grad(layers, _u(x), y, G, wv, wj, bf16=True)
+    assert loss == pytest.approx(want_loss, rel=1e-3)
+    got = mlp.unflatten(g.astype(np.float64), sg.WIDTHS)
+    for l, ((gW, gb), (wW, wb)) in enumerate(zip(got, want)):
+        eW = np.abs(gW - wW).max() / np.abs(wW).max()
+        eb = np.abs(gb - wb).max() / np.abs(wb).max()
+        assert eW <= 1e-2 and eb <= 1e-2, (l, eW, eb)
+
+
+def test_training_fits_an_analytic_map_with_its_gradient():
+    from paper_2511_21839_amd import surrogate as sg
+
+    rng = np.random.default_rng(7)
+    a = rng.normal(size=(2, 13)) * 0.3
+    n = 4096
+    x = _inputs(n, 8)
+    u = _u(x)
+    o = np.sin(u) @ a.T + 0.2 * u[:, [0]] * u[:, [1]]
+    J = np.cos(u)[:, None, :] * a[None, :, :]
+    J[:, :, 0] += 0.2 * u[:, [1]]
+    J[:, :, 1] += 0.2 * u[:, [0]]
+    eps = OC + OS * o
+    jac = J * OS[None, :, None] / (0.05 * np.abs(NOM))[None, None, :]
+    net = _net(1024, sg.init_params(np.random.default_rng(9)))
+    loss0, _ = net.loss_grad(x[:1024], eps[:1024], jac[:1024], 1.0, 1.0)
+    hist = net.fit(x, eps, jac, epochs=60, batch=512, lr=2e-3, seed=1)
+    loss1, _ = net.loss_grad(x[:1024], eps[:1024], jac[:1024], 1.0, 1.0)
+    assert loss1 < 0.03 * loss0, (loss0, loss1, hist)
+    xt = _inputs(512, 10)
+    ut = _u(xt)
+    ot = np.sin(ut) @ a.T + 0.2 * ut[:, [0]] * ut[:, [1]]
+    e, _ = net.predict(xt)
+    assert np.abs((e - OC) / OS - ot).max() < 0.05 * np.abs(ot).max()
+
+
+def _setup(w):
+    from paper_2511_21839_amd import surrogate as sg
+
+    L = w.lattice
+    return sg.PicSetup(grid=w.grid, lo=w.lo, hi=w.hi, beam=(w.kinetic_eV, w.rest_eV, w.charge_e, w.bunch_charge_C),
+                       lattice=(L.kind, L.n_steps, L.L, L.k, L.L_param, L.k_param, L.n_periods),
+                       n_steps=w.total_steps())
+
+
+def test_pic_targets_match_single_forward_runs():
+    """The batched 13-tangent training targets equal the oracle's run of the
+    same input point (values 1e-10, gradients 1e-9 normwise)."""
+    import synth
+    from oracle import pic
+    from paper_2511_21839_amd import surrogate as sg
+
+    base = synth.c5_base().with_(n_particles=1500, lattice=synth.fodo_lattice(3, 1))
+    x = synth.c5_inputs(3, seed=21)
+    eps, jac, oob = sg.pic_targets(_setup(base), x, base.xi(), batch=2)
+    assert oob.sum() == 0
+    for i in range(3):
+        w = base.with_(params=tuple(x[i, :7]), sigma=tuple(x[i, 7:]))
+        ref = pic.simulate_workload(w).emittance
+        np.testing.assert_allclose(eps[i], ref[:2, 0], rtol=1e-10)
+        for k in range(2):
+            assert np.abs(jac[i, k] - ref[k, 1:]).max() <= 1e-9 * np.abs(ref[k, 1:]).max()
+
+
+def test_trained_surrogate_screens_candidates_better_than_random_search():
+    """Sobolev-train the network on 2048 PIC runs (values + 13-gradients),
+    then let it screen 65536 candidates: the PIC evaluation of its top 64
+    finds a lower J = eps_x + eps_y than 64 PIC runs of random candidates
+    (the same PIC cost). At the best point the PIC adjoint judges the
+    predicted gradient (1e-3 relative) and replaces it when it disagrees; a
+    projected step along the gradient in use lowers J further."""
+    import synth
+    from paper_2511_21839_amd import surrogate as sg
+    from paper_2511_21839_amd.autograd import AdjointRun
+
+    base = synth.c5_base()
+    setup = _setup(base)
+    xi = base.xi()
+    xtr = synth.c5_inputs(2048, seed=11)
+    eps, jac, oob = sg.pic_targets(setup, xtr, xi)
+    assert oob.sum() == 0
+    net = sg.Surrogate(65536)
+    net.set_normalization(NOM, 0.05 * np.abs(NOM), eps.mean(axis=0), eps.std(axis=0))
+    net.set_params(sg.init_params(np.random.default_rng(12)))
+    net.fit(xtr, eps, jac, epochs=150, batch=256, lr=2e-3, seed=3)
+    # held-out accuracy of J and of its gradient
+    xte = synth.c5_inputs(256, seed=14)
+    ete, jte, _ = sg.pic_targets(setup, xte, xi)
+    ep, jp = net.predict(xte)
+    j_err = np.abs(sg.objective(ep) - sg.objective(ete)) / sg.objective(ete)
+    g_err = np.abs((jp[:, 0] + jp[:, 1]) - (jte[:, 0] + jte[:, 1])).max(axis=1) / \
+        np.abs(jte[:, 0] + jte[:, 1]).max(axis=1)
+    print(f"held-out J rel err: median {np.median(j_err):.2e} max {j_err.max():.2e}; "
+          f"grad rel err median {np.median(g_err):.2e}")
+    assert np.median(j_err) < 5e-3
+    # screening against random search at equal PIC cost
+    cand = synth.c5_inputs(65536, seed=15)
+    idx, j_pred, g_pred = sg.screen(net, cand, 64)
+    e_s, _, _ = sg.pic_targets(setup, cand[idx], xi)
+    e_r, _, _ = sg.pic_targets(setup, cand[:64], xi)
+    js, jr = sg.objective(e_s), sg.objective(e_r)
+    print(f"best J: screened {js.min():.6e}, random {jr.min():.6e}")
+    assert js.min() < jr.min()
+    # the PIC adjoint judges the predicted gradient at the best point
+    b = int(np.argmin(js))
+    xb = cand[idx[b]]
+    L = base.lattice
+    run = AdjointRun(base.n_particles, base.grid, base.lo, base.hi,
+                     (base.kinetic_eV, base.rest_eV, base.charge_e, base.bunch_charge_C),
+                     (L.kind, L.n_steps, L.L, L.k, L.L_param, L.k_param, L.n_periods), xi, base.total_steps(),
+                     checkpoint_every=50)
+    jb = run.forward(xb[:7], xb[7:])
+    assert jb[0] + jb[1] == pytest.approx(js[b], rel=1e-10)
+    gp, gs = run.backward([1.0, 1.0, 0.0])
+    g_pic = np.concatenate([gp, gs])
+    ok, err = sg.judge(g_pred[b], g_pic)
+    g_use = g_pred[b] if ok else g_pic
+    print(f"surrogate gradient rel err at the best point {err:.2e} -> {'surrogate' if ok else 'PIC fallback'}")
+    # a projected step in the normalised inputs lowers J
+    s = 0.05 * np.abs(NOM)
+    d = -g_use * s
+    x1 = np.clip(xb + 0.2 * s * d / np.abs(d).max(), NOM - s * np.sign(NOM), NOM + s * np.sign(NOM))
+    x1 = np.clip(x1, np.minimum(NOM - s, NOM + s), np.maximum(NOM - s, NOM + s))
+    e1, _, _ = sg.pic_targets(setup, x1[None, :], xi)
+    assert sg.objective(e1)[0] <= js[b]
