@@ -28,6 +28,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+
+def _log(msg):
+    """Progress on stderr (the result is the one JSON line on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 BYTES_PER_PARTICLE_STEP = 6 * 8 * 8 * 2  # 6 coords x 8 channels x 8 B, read + write
 
 
@@ -225,6 +230,146 @@ def _batched_timing():
     return {"c4": r4, "c1x256": r5}
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+# network 13 -> 4 x 256 -> 2 on 14 columns per sample (value + 13 tangents)
+SURROGATE_MACS_PER_COLUMN = 13 * 256 + 3 * 256 * 256 + 256 * 2
+SURROGATE_FLOPS_PER_SAMPLE = 2 * 14 * SURROGATE_MACS_PER_COLUMN
+
+
+def _surrogate_setup(nmax):
+    import numpy as np
+    import synth
+    from paper_2511_21839_amd import surrogate as sg
+
+    nom = np.concatenate([synth.NOMINAL_PARAMS, synth.SIGMA_NOMINAL])
+    net = sg.Surrogate(nmax)
+    net.set_normalization(nom, 0.05 * np.abs(nom), [1.2e-6, 1.4e-6], [5e-8, 5e-8])
+    net.set_params(sg.init_params(np.random.default_rng(31)))
+    return net, nom
+
+
+def _surrogate_timing(reps=20):
+    """Inference of 65536 samples (values and 2 x 13 Jacobians) and Adam
+    training steps on batches of 4096, BF16 MFMA with FP32 accumulation;
+    achieved TFLOP/s on the algorithmic flops (14 columns per sample, no
+    padding) against the dense BF16 matrix-core peak."""
+    import numpy as np
+    import torch
+    import synth
+
+    n = 65536
+    net, nom = _surrogate_setup(n)
+    x = net.to_device(synth.c5_inputs(n, seed=32))
+    eps = torch.empty((n, 2), dtype=torch.float64, device="cuda")
+    jac = torch.empty((n, 2, 13), dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        net.predict_dev(x, eps, jac)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        net.predict_dev(x, eps, jac)
+    e1.record()
+    torch.cuda.synchronize()
+    t_inf = e0.elapsed_time(e1) / reps / 1e3
+    bt = 4096
+    rng = np.random.default_rng(33)
+    xt = x[:bt]
+    et = net.to_device(1.3e-6 + 5e-8 * rng.normal(size=(bt, 2)))
+    jt = net.to_device(1e-6 * rng.normal(size=(bt, 2, 13)))
+    for _ in range(3):
+        net.train_step_dev(xt, et, jt, 1.0, 1.0, 1e-4)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        net.train_step_dev(xt, et, jt, 1.0, 1.0, 1e-4)
+    e1.record()
+    torch.cuda.synchronize()
+    t_tr = e0.elapsed_time(e1) / reps / 1e3
+    achieved = SURROGATE_FLOPS_PER_SAMPLE * n / t_inf / 1e12
+    net.close()
+    return {
+        "inference": {"batch": n, "ms": t_inf * 1e3, "samples_per_s": n / t_inf,
+                      "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS,
+                                   "unit": "TFLOP/s", "frac": achieved / MFMA_BF16_PEAK_TFLOPS,
+                                   "flops_per_sample": SURROGATE_FLOPS_PER_SAMPLE}},
+        "train_step": {"batch": bt, "ms": t_tr * 1e3, "samples_per_s": bt / t_tr,
+                       "tflops": 3 * SURROGATE_FLOPS_PER_SAMPLE * bt / t_tr / 1e12},
+    }
+
+
+def _surrogate_full(n_train=20000, epochs=60):
+    """The learned extension end to end: PIC training data (n_train runs of
+    the 1e4-particle, 32^3, 100-step workload with 13 tangents, batched),
+    Sobolev training, held-out accuracy, screening of 65536 candidates
+    against random search at equal PIC cost, and the PIC adjoint as judge
+    of the predicted gradient at the best point."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2511_21839_amd import surrogate as sg
+    from paper_2511_21839_amd.autograd import AdjointRun
+
+    base = synth.c5_base()
+    L = base.lattice
+    setup = sg.PicSetup(grid=base.grid, lo=base.lo, hi=base.hi,
+                        beam=(base.kinetic_eV, base.rest_eV, base.charge_e, base.bunch_charge_C),
+                        lattice=(L.kind, L.n_steps, L.L, L.k, L.L_param, L.k_param, L.n_periods),
+                        n_steps=base.total_steps())
+    xi = base.xi()
+    nom = np.concatenate([synth.NOMINAL_PARAMS, synth.SIGMA_NOMINAL])
+    out = {"workload": base.name, "n_train": n_train}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xtr = synth.c5_inputs(n_train, seed=41)
+    eps, jac, oob = sg.pic_targets(setup, xtr, xi, batch=512)
+    torch.cuda.synchronize()
+    out["t_pic_data_s"] = time.perf_counter() - t0
+    out["out_of_box"] = int(oob.sum())
+    net = sg.Surrogate(65536)
+    net.set_normalization(nom, 0.05 * np.abs(nom), eps.mean(axis=0), eps.std(axis=0))
+    net.set_params(sg.init_params(np.random.default_rng(42)))
+    t0 = time.perf_counter()
+    hist = net.fit(xtr, eps, jac, epochs=epochs, batch=512, lr=2e-3, seed=43)
+    torch.cuda.synchronize()
+    out["t_train_s"] = time.perf_counter() - t0
+    out["loss_first_last"] = [hist[0], hist[-1]]
+    xte = synth.c5_inputs(1024, seed=44)
+    ete, jte, _ = sg.pic_targets(setup, xte, xi, batch=512)
+    ep, jp = net.predict(xte)
+    j_err = np.abs(sg.objective(ep) - sg.objective(ete)) / sg.objective(ete)
+    gt, gp_ = jte[:, 0] + jte[:, 1], jp[:, 0] + jp[:, 1]
+    g_err = np.abs(gp_ - gt).max(axis=1) / np.abs(gt).max(axis=1)
+    out["heldout"] = {"J_rel_err_median": float(np.median(j_err)), "J_rel_err_max": float(j_err.max()),
+                      "grad_rel_err_median": float(np.median(g_err)), "grad_within_1e-3": float(np.mean(g_err <= 1e-3))}
+    cand = synth.c5_inputs(65536, seed=45)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    idx, j_pred, g_pred = sg.screen(net, cand, 64)
+    out["t_screen_65536_s"] = time.perf_counter() - t0
+    e_s, _, _ = sg.pic_targets(setup, cand[idx], xi, batch=64)
+    e_r, _, _ = sg.pic_targets(setup, cand[:64], xi, batch=64)
+    js, jr = sg.objective(e_s), sg.objective(e_r)
+    # random search: how many of 4096 PIC-evaluated random candidates beat the screened best
+    e_rr, _, _ = sg.pic_targets(setup, cand[64:64 + 4096], xi, batch=512)
+    jrr = sg.objective(e_rr)
+    out["screening"] = {"best_J_screened_64": float(js.min()), "best_J_random_64": float(jr.min()),
+                        "best_J_random_4096": float(jrr.min()),
+                        "random_runs_beating_screened_best_of_4096": int(np.sum(jrr < js.min()))}
+    b = int(np.argmin(js))
+    xb = cand[idx[b]]
+    run = AdjointRun(base.n_particles, base.grid, base.lo, base.hi,
+                     (base.kinetic_eV, base.rest_eV, base.charge_e, base.bunch_charge_C),
+                     (L.kind, L.n_steps, L.L, L.k, L.L_param, L.k_param, L.n_periods), xi, base.total_steps(),
+                     checkpoint_every=50)
+    run.forward(xb[:7], xb[7:])
+    gpar, gsig = run.backward([1.0, 1.0, 0.0])
+    ok, err = sg.judge(g_pred[b], np.concatenate([gpar, gsig]))
+    out["judge"] = {"grad_rel_err": err, "within_1e-3": ok, "used": "surrogate" if ok else "PIC adjoint (fallback)"}
+    net.close()
+    return out
+
+
 def _copy_calibration(mib: int) -> int:
     """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give the
     factor that turns counter KiB into HBM bytes for the same profiler setup."""
@@ -250,6 +395,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extensions", action="store_true",
                     help="skip the reverse-mode and batched timings")
+    ap.add_argument("--surrogate-full", action="store_true",
+                    help="also run the learned extension end to end (20k PIC runs, training, screening)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (to scale HBM byte counters)")
     args = ap.parse_args(argv)
@@ -345,11 +492,20 @@ def main(argv=None):
                    "emittance_x": float(emit[0, 0]), "emittance_y": float(emit[1, 0]),
                    "finite": bool(np.isfinite(emit).all())},
     }
+    _log(f"c2: {K} steps in {dt:.3f} s")
     if not args.no_extensions:
         line["adjoint"] = _adjoint_timing()
+        _log("reverse mode timed")
         line["batched"] = _batched_timing()
+        _log("batched runs timed")
+        line["surrogate"] = _surrogate_timing()
+        _log("surrogate timed")
+    if args.surrogate_full:
+        line["surrogate_full"] = _surrogate_full()
+        _log("surrogate pipeline done")
     if not args.no_cpu_baseline and args.cpu_steps > 0:
         line["cpu_baseline"] = _cpu_baseline(w, xi, args.cpu_steps)
+        _log("oracle timed")
     print(json.dumps(line), flush=True)
     return 0
 

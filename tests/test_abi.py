@@ -150,3 +150,44 @@ def test_binding_has_no_compute_fallback():
     src = open(os.path.join(os.path.dirname(pkg.__file__), "dpic.py")).read()
     assert "oracle" not in src
     assert "import torch" in src  # device memory and streams
+
+
+def _declared_in(header):
+    src = open(os.path.join(ROOT, "include", header)).read()
+    return sorted(set(re.findall(r"^int\s+(dmlp_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_surrogate_abi_exports_and_host_checks():
+    from paper_2511_21839_amd import surrogate as sg
+
+    L = sg.lib()
+    names = _declared_in("dmlp.h")
+    assert sorted(sg.SYMBOLS) == names
+    for n in names:
+        assert hasattr(L, n), n
+    # 13 -> 4 x 256 -> 2 with biases
+    assert sg.param_count() == 13 * 256 + 256 + 3 * (256 * 256 + 256) + 2 * 256 + 2
+    with pytest.raises(dpic.DpicError):
+        sg.query_workspace(0)
+    need = sg.query_workspace(100)
+    assert need > 4 * 4 * sg.param_count()
+    ctx = ctypes.c_void_p()
+    assert L.dmlp_create(100, ctypes.c_void_p(0x100008), need, None, ctypes.byref(ctx)) == dpic.DPIC_EINVAL
+    assert L.dmlp_create(100, ctypes.c_void_p(0x100000), need - 1, None, ctypes.byref(ctx)) == dpic.DPIC_EINVAL
+    assert L.dmlp_create(100, ctypes.c_void_p(0x100000), need, None, ctypes.byref(ctx)) == dpic.DPIC_OK
+    try:
+        D = ctypes.POINTER(ctypes.c_double)
+        ok = np.ones(13)
+        bad = np.ones(13)
+        bad[4] = 0.0
+        two = np.ones(2)
+        assert L.dmlp_set_normalization(ctx, ok.ctypes.data_as(D), bad.ctypes.data_as(D), two.ctypes.data_as(D),
+                                        two.ctypes.data_as(D)) == dpic.DPIC_EINVAL
+        # prediction before parameters, and batches outside 1..nmax, stop on the host
+        assert L.dmlp_predict(ctx, 10, ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000), None) == dpic.DPIC_ESTATE
+        assert L.dmlp_set_normalization(ctx, ok.ctypes.data_as(D), ok.ctypes.data_as(D), two.ctypes.data_as(D),
+                                        two.ctypes.data_as(D)) == dpic.DPIC_OK
+        assert L.dmlp_predict(ctx, 101, ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000), None) == dpic.DPIC_EINVAL
+        assert L.dmlp_set_adam(ctx, 1.5, 0.999, 1e-8) == dpic.DPIC_EINVAL
+    finally:
+        L.dmlp_destroy(ctx)
