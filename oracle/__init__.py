@@ -17,6 +17,10 @@ Modules
               self term
   pic      -- deposit, solve, field, gather, kick, split-operator step,
               moments and emittances (Sec. 4)
+  pipe2d   -- the paper's own 2D PIC: rectangular conducting pipe, sine-series
+              Poisson solver, bilinear deposit, perveance kick (Sec. 4)
+  twiss    -- single-particle Twiss transport, matched Twiss of a cell, the
+              matching objective and the BFGS / Nelder-Mead optimisers (Sec. 3)
   mlp      -- the emittance surrogate: MLP with its input Jacobian, the
               Sobolev loss and its weight gradient (exact, and with the
               rounding points of a BF16 matrix-core implementation)
@@ -25,4 +29,4 @@ Every function is pinned by the tests in tests/test_oracle_*.py against
 closed forms, brute force, invariants or finite differences; the pins are
 listed per function in the module docstrings.
 """
-from . import dual, physics, lattice, green, pic, mlp  # noqa: F401
+from . import dual, physics, lattice, green, pic, pipe2d, twiss, mlp  # noqa: F401

@@ -48,6 +48,10 @@ __all__ = [
     "tiny",
     "Batch",
     "perturbed_batch",
+    "PipeWorkload",
+    "pipe2d",
+    "Matching",
+    "matching",
 ]
 
 # Recipe constants (CODATA 2018); used only to turn a peak current into a
@@ -349,3 +353,69 @@ def c5_inputs(n_runs: int, seed: int = 20251125, rel: float = 0.05) -> np.ndarra
     rng = np.random.default_rng(seed)
     nominal = np.concatenate([NOMINAL_PARAMS, SIGMA_NOMINAL])
     return nominal[None, :] * (1.0 + rng.uniform(-rel, rel, size=(n_runs, 13)))
+
+
+# ---------------------------------------------------------------- 2D pipe and matching
+@dataclasses.dataclass
+class PipeWorkload:
+    """The paper's own PIC instance: a 2D beam in a rectangular conducting pipe."""
+    name: str
+    n_particles: int
+    seed: int
+    a: float
+    b: float
+    nx: int            # cells
+    ny: int
+    lattice: Lattice
+    params: Tuple[float, ...] = NOMINAL_PARAMS
+    sigma: Tuple[float, ...] = (1e-3, 1e-3, 1e-3, 1e-3)
+    ntan: int = 7
+    kinetic_eV: float = 1e9
+    rest_eV: float = PROTON_REST_EV
+    charge_e: float = 1.0
+    current_A: float = 100.0
+
+    def xi(self) -> np.ndarray:
+        return truncated_normals(self.n_particles, self.seed, ncoord=4)
+
+    def param_seed(self) -> np.ndarray:
+        s = np.zeros((len(self.params), self.ntan))
+        for j in range(min(len(self.params), self.ntan)):
+            s[j, j] = 1.0
+        return s
+
+    def total_steps(self) -> int:
+        return self.lattice.total_steps()
+
+    def with_(self, **kw) -> "PipeWorkload":
+        return dataclasses.replace(self, **kw)
+
+
+def pipe2d(n_particles: int = 10_000, cells: int = 64, steps_per_element: int = 20, **kw) -> PipeWorkload:
+    """1 GeV protons, 100 A, one FODO cell in a 20 mm x 20 mm pipe (the
+    sensitivity study of the paper's PIC section)."""
+    w = PipeWorkload(name=f"pipe2d: {n_particles} protons, {cells}^2 cells, 20 mm pipe, one FODO cell, 100 A",
+                     n_particles=n_particles, seed=20251126, a=0.02, b=0.02, nx=cells, ny=cells,
+                     lattice=fodo_lattice(steps_per_element, 1))
+    return w.with_(**kw) if kw else w
+
+
+@dataclasses.dataclass
+class Matching:
+    """Four-quadrupole matching section between two periodic FODO lattices
+    (the paper's third example): start from the first lattice's matched
+    Twiss, reach the second's. Lattice lengths and strengths are this
+    build's choice (the paper prints only the +-22 m^-2 cell)."""
+    kind: Tuple[int, ...]
+    L: Tuple[float, ...]
+    k_param: Tuple[int, ...]
+    cell_from: Tuple[float, float]   # quad strengths of the first FODO
+    cell_to: Tuple[float, float]     # and of the second
+    k0: Tuple[float, ...]            # starting strengths of the four matching quads
+
+
+def matching() -> Matching:
+    return Matching(kind=(DRIFT, QUAD, DRIFT, QUAD, DRIFT, QUAD, DRIFT, QUAD, DRIFT),
+                    L=(0.1, 0.1, 0.2, 0.1, 0.2, 0.1, 0.2, 0.1, 0.1),
+                    k_param=(-1, 0, -1, 1, -1, 2, -1, 3, -1),
+                    cell_from=(22.0, -22.0), cell_to=(16.0, -16.0), k0=(20.0, -20.0, 20.0, -20.0))
