@@ -370,6 +370,53 @@ def _surrogate_full(n_train=20000, epochs=60):
     return out
 
 
+def _pipe2d_timing():
+    """The paper's own instance: 2D beam in a conducting pipe (sine-series
+    solver), 1e5 protons, 64^2 cells, one FODO cell of 100 steps, 7 tangents;
+    and the matching example: BFGS against Nelder-Mead evaluation counts."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2511_21839_amd import pipe2d as p2
+
+    w = synth.pipe2d(n_particles=100_000)
+    sim = p2.Pipe2D(w.n_particles, w.ntan, w.nx, w.ny)
+    sim.set_beam(w.kinetic_eV, w.rest_eV, w.charge_e, w.current_A)
+    sim.set_pipe(w.a, w.b)
+    L = w.lattice
+    sim.set_lattice(L.kind, L.n_steps, L.L, L.k, L.L_param, L.k_param, L.n_periods)
+    sim.set_params(w.params, w.param_seed())
+    xi = w.xi()
+    sim.init_beam(xi, w.sigma)
+    sim.step(5)
+    sim.init_beam(xi, w.sigma)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(w.total_steps())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    e = sim.emittance()
+    rel = e[:, 1:] * np.asarray(w.params)[None, :] / e[:, :1]
+    m = synth.matching()
+    cell = [0, 1, 0, 1, 0]
+    Lc = [0.1, 0.1, 0.2, 0.1, 0.1]
+
+    def periodic(kq):
+        tw = p2.Twiss(cell, Lc, [0.0, kq[0], 0.0, kq[1], 0.0], [-1] * 5, [-1] * 5)
+        return tw.eval(np.zeros((1, 0)))[0][:, 0]
+
+    t_from, t_to = periodic(m.cell_from), periodic(m.cell_to)
+    tw = p2.Twiss(m.kind, m.L, [0.0] * len(m.kind), [-1] * len(m.kind), m.k_param)
+    _, fb, nb, _ = tw.match(m.k0, t_from, t_to, method=p2.BFGS, tol=1e-12, max_eval=1000)
+    _, fn, nn, _ = tw.match(m.k0, t_from, t_to, method=p2.NELDER_MEAD, step=2.0, tol=1e-12, max_eval=10000)
+    sim.close()
+    return {"workload": w.name, "dual_particle_steps_per_s": w.n_particles * w.total_steps() / dt,
+            "ms_per_step": dt / w.total_steps() * 1e3,
+            "relative_sensitivities_eps_x": [float(v) for v in rel[0]],
+            "relative_sensitivities_eps_y": [float(v) for v in rel[1]],
+            "matching": {"bfgs_evaluations": nb, "bfgs_f": fb, "nelder_mead_evaluations": nn, "nelder_mead_f": fn}}
+
+
 def _copy_calibration(mib: int) -> int:
     """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give the
     factor that turns counter KiB into HBM bytes for the same profiler setup."""
@@ -500,6 +547,8 @@ def main(argv=None):
         _log("batched runs timed")
         line["surrogate"] = _surrogate_timing()
         _log("surrogate timed")
+        line["pipe2d"] = _pipe2d_timing()
+        _log("2D pipe instance timed")
     if args.surrogate_full:
         line["surrogate_full"] = _surrogate_full()
         _log("surrogate pipeline done")

@@ -60,6 +60,37 @@ __device__ __forceinline__ LD ldload(const double* p, int c) {
 // The channel this lane stores.
 __device__ __forceinline__ double ldchan(LD a, int c) { return c ? a.t : a.v; }
 
+// ---------------------------------------------------------------- maps
+struct Map2 {
+    LD a, b, c, d;
+};
+
+// Exact map of one plane with signed strength kk over length s (Sec. 4
+// quadrupole maps; kk > 0 focusing, kk < 0 defocusing, kk = 0 a drift).
+// Below |kk s^2| < 1e-8 the Taylor series in u = kk s^2 to u^3 is used.
+__device__ inline Map2 plane_map(LD kk, LD s) {
+    LD u = kk * s * s;
+    if (fabs(u.v) < 1e-8) {
+        LD cc = 1.0 - u * 0.5 + u * u * (1.0 / 24.0) - u * u * u * (1.0 / 720.0);
+        LD sn = s * (1.0 - u * (1.0 / 6.0) + u * u * (1.0 / 120.0) - u * u * u * (1.0 / 5040.0));
+        return Map2{cc, sn, -(kk * sn), cc};
+    }
+    if (kk.v > 0) {
+        LD r = dsqrt(kk);
+        LD th = r * s;
+        LD ct = dcos(th), st = dsin(th);
+        return Map2{ct, st / r, -(r * st), ct};
+    }
+    LD r = dsqrt(-kk);
+    LD th = r * s;
+    LD ch = dcosh(th), sh = dsinh(th);
+    return Map2{ch, sh / r, r * sh, ch};
+}
+
+__device__ inline Map2 map_mul(const Map2& B, const Map2& A) {  // B A
+    return Map2{B.a * A.a + B.b * A.c, B.a * A.b + B.b * A.d, B.c * A.a + B.d * A.c, B.c * A.b + B.d * A.d};
+}
+
 // ---------------------------------------------------------------- layout
 // Element constants: per element EC_N duals, each NC doubles. A "map block"
 // is 9 consecutive duals: the (x, px) 2x2 map row-major, the (y, py) map,

@@ -24,32 +24,6 @@ struct ElemTable {
     int nsteps[DPIC_MAX_ELEMENTS];
 };
 
-struct Map2 {
-    LD a, b, c, d;
-};
-
-// Exact half-step map of one plane with signed strength kk over length s
-// (Sec. 4 quadrupole maps; kk > 0 focusing, kk < 0 defocusing). Below
-// |kk s^2| < 1e-8 the Taylor series in u = kk s^2 to u^3 is used.
-__device__ Map2 plane_map(LD kk, LD s) {
-    LD u = kk * s * s;
-    if (fabs(u.v) < 1e-8) {
-        LD cc = 1.0 - u * 0.5 + u * u * (1.0 / 24.0) - u * u * u * (1.0 / 720.0);
-        LD sn = s * (1.0 - u * (1.0 / 6.0) + u * u * (1.0 / 120.0) - u * u * u * (1.0 / 5040.0));
-        return Map2{cc, sn, -(kk * sn), cc};
-    }
-    if (kk.v > 0) {
-        LD r = dsqrt(kk);
-        LD th = r * s;
-        LD ct = dcos(th), st = dsin(th);
-        return Map2{ct, st / r, -(r * st), ct};
-    }
-    LD r = dsqrt(-kk);
-    LD th = r * s;
-    LD ch = dcosh(th), sh = dsinh(th);
-    return Map2{ch, sh / r, r * sh, ch};
-}
-
 template <int NC>
 __global__ void k_element_consts(ElemTable tab, int n_elem, const double* __restrict__ elem_in,
                                  double* __restrict__ ec, double inv_g2) {

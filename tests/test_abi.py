@@ -191,3 +191,33 @@ def test_surrogate_abi_exports_and_host_checks():
         assert L.dmlp_set_adam(ctx, 1.5, 0.999, 1e-8) == dpic.DPIC_EINVAL
     finally:
         L.dmlp_destroy(ctx)
+
+
+def test_pipe2d_and_twiss_abi_exports_and_host_checks():
+    from paper_2511_21839_amd import pipe2d as p2
+
+    L = p2.lib()
+    src2 = open(os.path.join(ROOT, "include", "dpic2d.h")).read()
+    names2 = sorted(set(re.findall(r"^int\s+(dpic2d_\w+)\s*\(", src2, flags=re.M)))
+    assert sorted(p2.SYMBOLS_2D) == names2
+    srct = open(os.path.join(ROOT, "include", "dtwiss.h")).read()
+    namest = sorted(set(re.findall(r"^int\s+(dtwiss_\w+)\s*\(", srct, flags=re.M)))
+    assert sorted(p2.SYMBOLS_TWISS) == namest
+    for n in names2 + namest:
+        assert hasattr(L, n), n
+    b = ctypes.c_size_t(0)
+    for bad in ((10, 16, 32, 32), (10, 7, 2, 32), (10, 7, 32, 300), (0, 7, 32, 32)):
+        d = p2.dpic2d_dims(bad[0], bad[1], bad[2], bad[3], 0)
+        assert L.dpic2d_query_workspace(ctypes.byref(d), ctypes.byref(b)) != 0
+    d = p2.dpic2d_dims(100, 7, 32, 24, 0)
+    assert L.dpic2d_query_workspace(ctypes.byref(d), ctypes.byref(b)) == 0
+    ctx = ctypes.c_void_p()
+    assert L.dpic2d_create(ctypes.byref(d), ctypes.c_void_p(0x100000), b.value, None, ctypes.byref(ctx)) == 0
+    try:
+        assert L.dpic2d_step(ctx, 1) == dpic.DPIC_ESTATE
+        assert L.dpic2d_set_pipe(ctx, -1.0, 0.02) == dpic.DPIC_EINVAL
+        assert L.dpic2d_set_beam(ctx, -1.0, 938e6, 1.0, 100.0) == dpic.DPIC_EINVAL
+    finally:
+        L.dpic2d_destroy(ctx)
+    assert L.dtwiss_query_workspace(0, ctypes.byref(b)) == dpic.DPIC_EINVAL
+    assert L.dtwiss_query_workspace(4, ctypes.byref(b)) == 0
