@@ -307,6 +307,9 @@ struct TiledArgs {
 // of a quad (channels k, k+K, ..) and particles at different nodes spread
 // over the banks.
 constexpr int TILE_NODES = TILE_R * TILE_R * TILE_R;
+// E tile of a work item: the (TILE_EDGE + 1)^3 nodes of its tile's cells
+constexpr int ETILE_R = TILE_EDGE + 1;
+constexpr int ETILE_NODES = ETILE_R * ETILE_R * ETILE_R;
 constexpr int TILE_CSTRIDE = ((TILE_NODES + 15) / 16) * 16 + 1;
 constexpr int PART_THREADS = 256;
 
@@ -396,8 +399,8 @@ __device__ __forceinline__ QD<K> raw_to_qd(const double* r, int q) {
 template <int NC, int F, bool TILED>
 __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& sv, const double* __restrict__ smap,
                                               const double* __restrict__ stau, int64_t p, int q,
-                                              const RawState<Quad<NC>::K>& raw, double* lr, int ox, int oy,
-                                              int oz, bool use_tile, double& e0, double& e1, double& e2) {
+                                              const RawState<Quad<NC>::K>& raw, double* lr, const double* le, int ox,
+                                              int oy, int oz, bool use_tile, double& e0, double& e1, double& e2) {
     constexpr int G = Quad<NC>::G, K = Quad<NC>::K;
     const int64_t cs = a.cap * NC;
     double* sp = a.st + p * NC;
@@ -409,20 +412,43 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& 
         if (g.inside) {
             const QD<K> fx = qd_frac(x, g.sx, g.ix, a.ih0), fy = qd_frac(y, g.sy, g.iy, a.ih1),
                         fz = qd_frac(z, g.sz, g.iz, a.ih2);
-            const int64_t n0 = ((int64_t)g.iz * a.ny + g.iy) * a.nx + g.ix;
             QD<K> ex = qd_zero<K>(), ey = qd_zero<K>(), ez = qd_zero<K>();
+            // the item's E tile in LDS holds the nodes of its tile's cells
+            const int tlx = g.ix - ox - TILE_HALO, tly = g.iy - oy - TILE_HALO, tlz = g.iz - oz - TILE_HALO;
+            const bool in_etile = TILED && use_tile && tlx >= 0 && tlx < TILE_EDGE && tly >= 0 && tly < TILE_EDGE &&
+                                  tlz >= 0 && tlz < TILE_EDGE;
+            if (in_etile) {
+                const int l0 = (tlz * ETILE_R + tly) * ETILE_R + tlx;
 #pragma unroll
-            for (int kz = 0; kz < 2; ++kz) {
+                for (int kz = 0; kz < 2; ++kz) {
 #pragma unroll
-                for (int ky = 0; ky < 2; ++ky) {
-                    const QD<K> wyz = qd_mul(ky ? fy : qd_one_minus(fy), kz ? fz : qd_one_minus(fz));
+                    for (int ky = 0; ky < 2; ++ky) {
+                        const QD<K> wyz = qd_mul(ky ? fy : qd_one_minus(fy), kz ? fz : qd_one_minus(fz));
 #pragma unroll
-                    for (int kx = 0; kx < 2; ++kx) {
-                        const QD<K> w = qd_mul(kx ? fx : qd_one_minus(fx), wyz);
-                        const double* ep = sv.E + (n0 + kx + ky * a.nx + kz * sxy) * 3 * NC;
-                        qd_fmad(w, qd_load<K, G>(ep, q), ex);
-                        qd_fmad(w, qd_load<K, G>(ep + NC, q), ey);
-                        qd_fmad(w, qd_load<K, G>(ep + 2 * NC, q), ez);
+                        for (int kx = 0; kx < 2; ++kx) {
+                            const QD<K> w = qd_mul(kx ? fx : qd_one_minus(fx), wyz);
+                            const double* ep = le + (l0 + kx + ky * ETILE_R + kz * ETILE_R * ETILE_R) * 3 * NC;
+                            qd_fmad(w, qd_load<K, G>(ep, q), ex);
+                            qd_fmad(w, qd_load<K, G>(ep + NC, q), ey);
+                            qd_fmad(w, qd_load<K, G>(ep + 2 * NC, q), ez);
+                        }
+                    }
+                }
+            } else {
+                const int64_t n0 = ((int64_t)g.iz * a.ny + g.iy) * a.nx + g.ix;
+#pragma unroll
+                for (int kz = 0; kz < 2; ++kz) {
+#pragma unroll
+                    for (int ky = 0; ky < 2; ++ky) {
+                        const QD<K> wyz = qd_mul(ky ? fy : qd_one_minus(fy), kz ? fz : qd_one_minus(fz));
+#pragma unroll
+                        for (int kx = 0; kx < 2; ++kx) {
+                            const QD<K> w = qd_mul(kx ? fx : qd_one_minus(fx), wyz);
+                            const double* ep = sv.E + (n0 + kx + ky * a.nx + kz * sxy) * 3 * NC;
+                            qd_fmad(w, qd_load<K, G>(ep, q), ex);
+                            qd_fmad(w, qd_load<K, G>(ep + NC, q), ey);
+                            qd_fmad(w, qd_load<K, G>(ep + 2 * NC, q), ez);
+                        }
                     }
                 }
             }
@@ -524,7 +550,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles(PartArgs a) {
     double e0 = 0.0, e1 = 0.0, e2 = 0.0;
     if (p - sd.off < sd.n) {
         const RawState<Quad<NC>::K> raw = load_raw<NC>(a, p, q);
-        particle_body<NC, F, false>(a, sv, smap, stau, p, q, raw, nullptr, 0, 0, 0, false, e0, e1, e2);
+        particle_body<NC, F, false>(a, sv, smap, stau, p, q, raw, nullptr, nullptr, 0, 0, 0, false, e0, e1, e2);
     }
     if (F & (PF_DEPOSIT | PF_COUNT)) extent_flush(sv.cnt, e0, e1, e2);
 }
@@ -538,7 +564,9 @@ template <int NC, int F>
 __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, TiledArgs t) {
     constexpr int G = Quad<NC>::G;
     constexpr int LDSN = (F & PF_DEPOSIT) ? TILE_CSTRIDE * NC : 1;
+    constexpr int LDSE = (F & PF_KICK) ? ETILE_NODES * 3 * NC : 1;
     __shared__ __align__(16) double lr[LDSN];
+    __shared__ __align__(16) double le[LDSE];
     __shared__ __align__(16) double smap[MB_N * NC];
     __shared__ __align__(16) double stau[NC];
     const uint32_t nck = *t.nchunks;
@@ -558,10 +586,22 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
         }
         if (F & PF_DEPOSIT)
             for (int j = threadIdx.x; j < LDSN; j += PART_THREADS) lr[j] = 0.0;
-        __syncthreads();
         const bool use_tile = ck.x < t.nbins - 1;
         const int tx = ck.x % t.tx, ty = (ck.x / t.tx) % t.ty, tz = ck.x / (t.tx * t.ty);
         const int ox = tx * TILE_EDGE - TILE_HALO, oy = ty * TILE_EDGE - TILE_HALO, oz = tz * TILE_EDGE - TILE_HALO;
+        if ((F & PF_KICK) && use_tile) {
+            // E of the tile's nodes: runs of ETILE_R nodes x 3 x NC doubles along x
+            const int gx0 = tx * TILE_EDGE, gy0 = ty * TILE_EDGE, gz0 = tz * TILE_EDGE;
+            for (int j = threadIdx.x; j < LDSE; j += PART_THREADS) {
+                const int node = j / (3 * NC), r = j - node * (3 * NC);
+                const int lx = node % ETILE_R, ly = (node / ETILE_R) % ETILE_R, lz = node / (ETILE_R * ETILE_R);
+                const int gx = gx0 + lx, gy = gy0 + ly, gz = gz0 + lz;
+                le[j] = (gx < a.nx && gy < a.ny && gz < a.nz)
+                            ? sv.E[(((int64_t)gz * a.ny + gy) * a.nx + gx) * 3 * NC + r]
+                            : 0.0;
+            }
+        }
+        __syncthreads();
         double e0 = 0.0, e1 = 0.0, e2 = 0.0;
         // software pipeline: the next particle's state is loaded while the
         // current one is gathered, pushed and deposited
@@ -572,8 +612,8 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
         for (; i < ck.z; i += STRIDE) {
             const RawState<Quad<NC>::K> curst = next;
             if (i + STRIDE < ck.z) next = load_raw<NC>(a, (int64_t)ck.y + i + STRIDE, q);
-            particle_body<NC, F, true>(a, sv, smap, stau, (int64_t)ck.y + i, q, curst, lr, ox, oy, oz, use_tile, e0,
-                                       e1, e2);
+            particle_body<NC, F, true>(a, sv, smap, stau, (int64_t)ck.y + i, q, curst, lr, le, ox, oy, oz, use_tile,
+                                       e0, e1, e2);
         }
         if (F & PF_DEPOSIT) {
             __syncthreads();

@@ -194,7 +194,8 @@ def test_single_setting_graph_matches_eager():
     for _ in range(2):
         graphed.init_beam(w.xi(), w.sigma, w.sigma_seed())
         graphed.step(w.total_steps())
-        assert_outputs_close(graphed.emittance(), eager.emittance(), vtol=1e-12, dtol=1e-11)
+        # both sides differ only in the order of the deposit atomics
+        assert_outputs_close(graphed.emittance(), eager.emittance(), vtol=1e-11, dtol=1e-9)
 
 
 def test_autotune_keeps_the_state_and_picks_a_candidate():
