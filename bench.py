@@ -483,9 +483,11 @@ def main(argv=None):
         sim.step(W)
     torch.cuda.synchronize()
 
-    # timed: K steps from the start of the schedule, beam resident in HBM
+    # timed: K steps from the start of the schedule, beam resident in HBM,
+    # with HIP events around the particle launches only (mode 2: every event
+    # record idles the GPU for a few microseconds)
     sim.init_beam(xi, w.sigma, w.sigma_seed())
-    sim.set_option(dpic.OPT_STAGE_TIMING, 1)
+    sim.set_option(dpic.OPT_STAGE_TIMING, 2)
     sim.stage_times()  # reset the stage timers
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -493,10 +495,19 @@ def main(argv=None):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms, launches = sim.stage_times()
-    sim.set_option(dpic.OPT_STAGE_TIMING, 0)
     dt = t1 - t0
     oob, steps_done, extent = sim.counters()
     emit = sim.emittance()
+
+    # stage breakdown, outside the timed region: the same steps with events
+    # around every stage
+    sim.init_beam(xi, w.sigma, w.sigma_seed())
+    sim.set_option(dpic.OPT_STAGE_TIMING, 1)
+    sim.stage_times()
+    sim.step(K)
+    torch.cuda.synchronize()
+    sms, slaunches = sim.stage_times()
+    sim.set_option(dpic.OPT_STAGE_TIMING, 0)
 
     part_avg_s = ms[0] / 1e3 / max(int(launches[0]), 1)
     achieved = w.n_particles * BYTES_PER_PARTICLE_STEP / part_avg_s / 1e9
@@ -533,8 +544,8 @@ def main(argv=None):
             "kernel": "k_particles (gather, kick, two half-maps, deposit)",
             "avg_launch_us": part_avg_s * 1e6,
         },
-        "stages_ms": {n: float(ms[i]) for i, n in enumerate(dpic.STAGE_TIMER_NAMES)},
-        "stage_launches": {n: int(launches[i]) for i, n in enumerate(dpic.STAGE_TIMER_NAMES)},
+        "stages_ms": {n: float(sms[i]) for i, n in enumerate(dpic.STAGE_TIMER_NAMES)},
+        "stage_launches": {n: int(slaunches[i]) for i, n in enumerate(dpic.STAGE_TIMER_NAMES)},
         "checks": {"out_of_box": int(oob), "steps_done": int(steps_done),
                    "emittance_x": float(emit[0, 0]), "emittance_y": float(emit[1, 0]),
                    "finite": bool(np.isfinite(emit).all())},

@@ -222,7 +222,9 @@ int dpic_load_state(dpic_ctx* ctx, const void* dev_buf);
  * Options:
  *  DPIC_OPT_SORT_EVERY = re-sort particles by grid tile every k steps (0 = never);
  *  DPIC_OPT_STAGE_TIMING = 1 records HIP events around every stage launch of
- *    dpic_step (read with dpic_stage_times);
+ *    dpic_step, 2 around the particle stage only (fewer event records in the
+ *    stream: each leaves the GPU idle for a few microseconds); read with
+ *    dpic_stage_times; other values are EINVAL;
  *  DPIC_OPT_CHUNK = particles per work item of the tiled particle kernel
  *    (a multiple of 64 in 128..8192, default 1024);
  *  DPIC_OPT_PART_BLOCKS = workgroups of the persistent tiled particle kernel

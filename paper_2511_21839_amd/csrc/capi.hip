@@ -52,37 +52,48 @@ int check_dims(const dpic_dims* d) {
     return DPIC_OK;
 }
 
-// Event pairs around stage launches (optional timing).
-void timer_begin(dpic_ctx* c, int stage, hipEvent_t* out_end) {
-    *out_end = nullptr;
-    if (!c->stage_timing) return;
-    auto& pool = c->ev_pool[stage];
-    size_t i = c->ev_used[stage]++;
-    if (i >= pool.size()) {
-        hipEvent_t a, b;
-        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
-            c->ev_used[stage]--;
-            return;
-        }
-        pool.emplace_back(a, b);
-    }
-    (void)hipEventRecord(pool[i].first, c->stream);
-    *out_end = pool[i].second;
-}
-
-void timer_end(dpic_ctx* c, int stage, hipEvent_t end) {
-    if (!end) return;
-    (void)hipEventRecord(end, c->stream);
-    c->stage_launches[stage]++;
-}
-
 enum { T_PART = 0, T_SOLVE = 1, T_FIELD = 2, T_SORT = 3 };
 
+// Timing-only events: the default record performs a system-scope release (an
+// L2 write-back) that idled the GPU for ~10 us per record in kernel traces.
+// These are read only after a stream synchronisation.
+constexpr unsigned TIMER_EVENT_FLAGS = hipEventDisableSystemFence;
+
+// Event pair around one stage's launches while stage timing covers that
+// stage; at scope exit the end is recorded and the launch counted, also on
+// an early error return.
+struct StageTimer {
+    dpic_ctx* c;
+    int stage;
+    hipEvent_t end = nullptr;
+    StageTimer(dpic_ctx* c_, int s) : c(c_), stage(s) {
+        if (c->stage_timing == 0 || (c->stage_timing == 2 && stage != T_PART)) return;
+        auto& pool = c->ev_pool[stage];
+        const size_t i = c->ev_used[stage];
+        if (i >= pool.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreateWithFlags(&a, TIMER_EVENT_FLAGS) != hipSuccess) return;
+            if (hipEventCreateWithFlags(&b, TIMER_EVENT_FLAGS) != hipSuccess) {
+                (void)hipEventDestroy(a);
+                return;
+            }
+            pool.emplace_back(a, b);
+        }
+        if (hipEventRecord(pool[i].first, c->stream) != hipSuccess) return;
+        c->ev_used[stage]++;
+        end = pool[i].second;
+    }
+    ~StageTimer() {
+        if (!end) return;
+        (void)hipEventRecord(end, c->stream);
+        c->stage_launches[stage]++;
+    }
+};
+
+
 int run_particles(dpic_ctx* c, int flags, int e_tau, int map_off) {
-    hipEvent_t end;
-    timer_begin(c, T_PART, &end);
+    StageTimer tm(c, T_PART);
     HIPCHK(c, launch_particles(c, flags, e_tau, map_off, c->sort_every > 0 && c->chunks_valid));
-    timer_end(c, T_PART, end);
     return DPIC_OK;
 }
 
@@ -116,21 +127,18 @@ int single_step(dpic_ctx* c, int64_t s, double* e_store) {
 }
 
 int run_solve_field(dpic_ctx* c) {
-    hipEvent_t end;
-    timer_begin(c, T_SOLVE, &end);
-    HIPCHK(c, launch_solve(c));
-    timer_end(c, T_SOLVE, end);
-    timer_begin(c, T_FIELD, &end);
+    {
+        StageTimer tm(c, T_SOLVE);
+        HIPCHK(c, launch_solve(c));
+    }
+    StageTimer tm(c, T_FIELD);
     HIPCHK(c, launch_field(c));
-    timer_end(c, T_FIELD, end);
     return DPIC_OK;
 }
 
 int run_sort(dpic_ctx* c) {
-    hipEvent_t end;
-    timer_begin(c, T_SORT, &end);
+    StageTimer tm(c, T_SORT);
     HIPCHK(c, launch_sort(c));
-    timer_end(c, T_SORT, end);
     return DPIC_OK;
 }
 
@@ -890,7 +898,8 @@ int dpic_set_option(dpic_ctx* c, int option, int64_t value) {
             c->sort_every = value;
             return DPIC_OK;
         case DPIC_OPT_STAGE_TIMING:
-            c->stage_timing = value != 0;
+            if (value < 0 || value > 2) return fail(c, DPIC_EINVAL, "stage timing: 0, 1 or 2");
+            c->stage_timing = (int)value;
             return DPIC_OK;
         case DPIC_OPT_CHUNK:
             if (value < CHUNK_MIN || value > CHUNK_MAX || value % 64 != 0)
@@ -960,12 +969,13 @@ int dpic_autotune(dpic_ctx* c, void* scratch, size_t scratch_bytes, int trial_st
     std::vector<unsigned long long> cnt((size_t)c->B * CNT_N);
     HIPCHK(c, hipMemcpyAsync(cnt.data(), c->ws.counters, cnt.size() * 8, hipMemcpyDeviceToHost, c->stream));
     if ((r = dpic_save_state(c, scratch)) != DPIC_OK) return r;
-    const bool graph0 = c->use_graph, timing0 = c->stage_timing;
+    const bool graph0 = c->use_graph;
+    const int timing0 = c->stage_timing;
     c->use_graph = false;
-    c->stage_timing = false;
+    c->stage_timing = 0;
     hipEvent_t e0, e1;
-    HIPCHK(c, hipEventCreate(&e0));
-    HIPCHK(c, hipEventCreate(&e1));
+    HIPCHK(c, hipEventCreateWithFlags(&e0, TIMER_EVENT_FLAGS));
+    HIPCHK(c, hipEventCreateWithFlags(&e1, TIMER_EVENT_FLAGS));
     auto trial = [&](int64_t se, int64_t ch, int64_t pb, double* ms) -> int {
         int rr;
         if ((rr = dpic_set_option(c, DPIC_OPT_SORT_EVERY, se)) != DPIC_OK) return rr;

@@ -154,7 +154,7 @@ struct dpic_ctx {
     int64_t chunk = dpic::TILE_CHUNK;  // particles per tiled work item
     int64_t part_blocks = 0;           // workgroups of the tiled particle kernel (0: resident capacity)
     bool chunks_valid = false;  // the tiled work list matches the stored order
-    bool stage_timing = false;
+    int stage_timing = 0;  // 0 off, 1 every stage, 2 the particle stage only
     bool use_graph = false;
     int cu_count = 0;
     dpic::AdjointWs adj;

@@ -2,13 +2,13 @@
 // the fused gather / kick / map / deposit kernel, canonical read-back.
 //
 // Particle state is SoA over coordinates with the tangents interleaved:
-// st[coord][particle][NC]. In the fused step a particle owns a quad of G = 4
-// consecutive lanes (G = 1 when NC = 1); lane q of the quad holds channels
-// q*K .. q*K+K-1 (K = NC/G) of every dual plus the value, so one 16-byte load
-// per lane moves a particle's 64-byte coordinate and a wavefront touches one
-// contiguous kilobyte. The value reaches the other lanes of the quad by a DPP
-// quad broadcast. Lane 0's slot for channel 0 is kept at zero (its value is
-// the separate `v`), so the dual rules need no per-lane branch.
+// st[coord][particle][NC]. In the fused step a particle owns a group of
+// G = NC / 2 consecutive lanes (G = 1 when NC = 1); lane q of the group holds
+// channels 2q, 2q + 1 of every dual plus the value, so one 16-byte load per
+// lane moves its part of a coordinate and a wavefront touches one contiguous
+// kilobyte. The value reaches the other lanes of the group by DPP broadcasts.
+// Lane 0's slot for channel 0 is kept at zero (its value is the separate
+// `v`), so the dual rules need no per-lane branch.
 //
 // The step runs storage-ordered (deposit by global atomics) or tiled: a
 // workgroup takes one chunk of particles sorted into one grid tile and
@@ -157,25 +157,41 @@ hipError_t launch_init_beam(dpic_ctx* cx, const double* xi) {
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- quad duals
-// Lanes per particle and channels per lane.
+// ---------------------------------------------------------------- group duals
+// A particle owns a group of G consecutive lanes; lane q holds channels
+// [q K, q K + K). Two channels per lane (one 16-byte load per coordinate)
+// measured fastest at both 8 and 16 channels: one channel per lane frees
+// registers for a third wave per SIMD but doubles the memory and LDS
+// instructions per byte, four per lane cost the second wave.
 template <int NC>
 struct Quad {
-    static constexpr int G = NC == 1 ? 1 : 4;
+    static constexpr int G = NC == 1 ? 1 : NC / 2;
     static constexpr int K = NC / G;
 };
 
 template <int K>
 struct QD {
-    double v;     // value, equal in every lane of the quad
+    double v;     // value, equal in every lane of the group
     double t[K];  // this lane's channels (slot 0 of lane 0 stays 0)
 };
 
-// value of lane 0 of the quad, by DPP quad_perm [0,0,0,0]
-__device__ __forceinline__ double quad_bcast(double x) {
+// 32-bit broadcast of the first lane of each group of G lanes by DPP: the
+// quad_perm [0,0,0,0] copy, then row_shr:4 into the odd banks (lanes 4-7 and
+// 12-15 of a row) for G >= 8, then row_shr:8 into banks 2 and 3 for G = 16.
+template <int G>
+__device__ __forceinline__ int group_bcast_u32(int x) {
+    int b = __builtin_amdgcn_mov_dpp(x, 0x00, 0xf, 0xf, false);
+    if constexpr (G >= 8) b = __builtin_amdgcn_update_dpp(b, b, 0x114, 0xf, 0xa, false);
+    if constexpr (G >= 16) b = __builtin_amdgcn_update_dpp(b, b, 0x118, 0xf, 0xc, false);
+    return b;
+}
+
+template <int G>
+__device__ __forceinline__ double group_bcast(double x) {
+    static_assert(G == 4 || G == 8 || G == 16, "group of 4, 8 or 16 lanes");
     const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x00, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x00, 0xf, 0xf, false);
+    const int lo = group_bcast_u32<G>((int)(b & 0xffffffffll));
+    const int hi = group_bcast_u32<G>((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
@@ -196,7 +212,7 @@ __device__ __forceinline__ QD<K> qd_load(const double* __restrict__ p, int q) {
     if constexpr (G == 1)
         r.v = r.t[0];
     else
-        r.v = quad_bcast(r.t[0]);
+        r.v = group_bcast<G>(r.t[0]);
     if (q == 0) r.t[0] = 0.0;
     return r;
 }
@@ -304,12 +320,18 @@ struct TiledArgs {
 
 // LDS copy of the deposit tile, channel-major. The channel stride is 1 mod 16
 // doubles, so channel c of node n sits in bank pair (c + n) mod 16: the lanes
-// of a quad (channels k, k+K, ..) and particles at different nodes spread
+// of a group (channels k, k+K, ..) and particles at different nodes spread
 // over the banks.
 constexpr int TILE_NODES = TILE_R * TILE_R * TILE_R;
 // E tile of a work item: the (TILE_EDGE + 1)^3 nodes of its tile's cells
 constexpr int ETILE_R = TILE_EDGE + 1;
 constexpr int ETILE_NODES = ETILE_R * ETILE_R * ETILE_R;
+// The E tile is staged only where it leaves room for three workgroups per
+// CU: at 16 channels it and the deposit tile would take 93 KB.
+template <int NC, int F>
+constexpr bool use_etile() {
+    return (F & PF_KICK) && NC <= 8;
+}
 constexpr int TILE_CSTRIDE = ((TILE_NODES + 15) / 16) * 16 + 1;
 constexpr int PART_THREADS = 256;
 
@@ -348,7 +370,7 @@ __device__ __forceinline__ CellPos cell_of(double x, double y, double z, const P
     return r;
 }
 
-// One particle's share of a fused step, lane q of its quad: gather and kick
+// One particle's share of a fused step, lane q of its group: gather and kick
 // (PF_KICK), one map block (PF_MAP), then deposit (PF_DEPOSIT) or count
 // (PF_COUNT). With TILED the deposit goes to the workgroup's LDS copy `lr` of
 // the nodes [o, o + TILE_R) when all 8 corners fall inside it, else to global
@@ -391,7 +413,7 @@ __device__ __forceinline__ QD<K> raw_to_qd(const double* r, int q) {
     if constexpr (G == 1)
         x.v = x.t[0];
     else
-        x.v = quad_bcast(x.t[0]);
+        x.v = group_bcast<G>(x.t[0]);
     if (q == 0) x.t[0] = 0.0;
     return x;
 }
@@ -415,7 +437,7 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& 
             QD<K> ex = qd_zero<K>(), ey = qd_zero<K>(), ez = qd_zero<K>();
             // the item's E tile in LDS holds the nodes of its tile's cells
             const int tlx = g.ix - ox - TILE_HALO, tly = g.iy - oy - TILE_HALO, tlz = g.iz - oz - TILE_HALO;
-            const bool in_etile = TILED && use_tile && tlx >= 0 && tlx < TILE_EDGE && tly >= 0 && tly < TILE_EDGE &&
+            const bool in_etile = TILED && use_etile<NC, F>() && use_tile && tlx >= 0 && tlx < TILE_EDGE && tly >= 0 && tly < TILE_EDGE &&
                                   tlz >= 0 && tlz < TILE_EDGE;
             if (in_etile) {
                 const int l0 = (tlz * ETILE_R + tly) * ETILE_R + tlx;
@@ -564,7 +586,7 @@ template <int NC, int F>
 __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, TiledArgs t) {
     constexpr int G = Quad<NC>::G;
     constexpr int LDSN = (F & PF_DEPOSIT) ? TILE_CSTRIDE * NC : 1;
-    constexpr int LDSE = (F & PF_KICK) ? ETILE_NODES * 3 * NC : 1;
+    constexpr int LDSE = use_etile<NC, F>() ? ETILE_NODES * 3 * NC : 1;
     __shared__ __align__(16) double lr[LDSN];
     __shared__ __align__(16) double le[LDSE];
     __shared__ __align__(16) double smap[MB_N * NC];
@@ -589,7 +611,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
         const bool use_tile = ck.x < t.nbins - 1;
         const int tx = ck.x % t.tx, ty = (ck.x / t.tx) % t.ty, tz = ck.x / (t.tx * t.ty);
         const int ox = tx * TILE_EDGE - TILE_HALO, oy = ty * TILE_EDGE - TILE_HALO, oz = tz * TILE_EDGE - TILE_HALO;
-        if ((F & PF_KICK) && use_tile) {
+        if (use_etile<NC, F>() && use_tile) {
             // E of the tile's nodes: runs of ETILE_R nodes x 3 x NC doubles along x
             const int gx0 = tx * TILE_EDGE, gy0 = ty * TILE_EDGE, gz0 = tz * TILE_EDGE;
             for (int j = threadIdx.x; j < LDSE; j += PART_THREADS) {

@@ -198,6 +198,55 @@ def test_single_setting_graph_matches_eager():
         assert_outputs_close(graphed.emittance(), eager.emittance(), vtol=1e-11, dtol=1e-9)
 
 
+def _expected_sorts(calls, sort_every):
+    """Re-sorts of dpic_step calls of the given lengths from a fresh beam:
+    one on entry while the work list is stale (only the first call), and one
+    after every step s with (s + 1) % sort_every == 0 except a call's last."""
+    n, s0 = 1, 0
+    for c in calls:
+        n += sum(1 for s in range(s0, s0 + c - 1) if (s + 1) % sort_every == 0)
+        s0 += c
+    return n
+
+
+def test_stage_timing_counts_launches_and_keeps_results():
+    """Stage timing binds events to the stages' own kernels: every stage
+    launch is counted, every time is positive, and the run is unchanged."""
+    from paper_2511_21839_amd import dpic
+    from gpu_util import make_sim
+
+    w = synth.tiny(n_particles=2500, grid=16, steps_per_element=3)
+    T = w.total_steps()
+    calls = [T // 2, T - T // 2]
+    plain = make_sim(w, sort_every=5)
+    for c in calls:
+        plain.step(c)
+    timed = make_sim(w, sort_every=5)
+    timed.set_option(dpic.OPT_STAGE_TIMING, 1)
+    timed.stage_times()
+    for c in calls:
+        timed.step(c)
+    ms, launches = timed.stage_times()
+    want = {"particles": T + len(calls), "solve": T, "field": T, "sort": _expected_sorts(calls, 5)}
+    for i, name in enumerate(dpic.STAGE_TIMER_NAMES):
+        assert launches[i] == want[name], name
+        assert ms[i] > 0.0, name
+    ms2, launches2 = timed.stage_times()  # read-back resets
+    assert all(v == 0 for v in launches2) and all(v == 0.0 for v in ms2)
+    assert_outputs_close(timed.emittance(), plain.emittance(), vtol=1e-11, dtol=1e-9)
+    # mode 2 times the particle stage only
+    part = make_sim(w, sort_every=5)
+    part.set_option(dpic.OPT_STAGE_TIMING, 2)
+    part.stage_times()
+    for c in calls:
+        part.step(c)
+    ms3, launches3 = part.stage_times()
+    assert list(launches3) == [T + len(calls), 0, 0, 0] and ms3[0] > 0.0
+    assert_outputs_close(part.emittance(), plain.emittance(), vtol=1e-11, dtol=1e-9)
+    with pytest.raises(dpic.DpicError):
+        part.set_option(dpic.OPT_STAGE_TIMING, 3)
+
+
 def test_autotune_keeps_the_state_and_picks_a_candidate():
     from paper_2511_21839_amd import dpic
 
