@@ -234,6 +234,53 @@ __device__ __forceinline__ void qd_store(double* __restrict__ p, const QD<K>& x,
     }
 }
 
+// LDS duals in split layout: lds_dual<NC>() doubles per dual. Slots
+// [0, NC) hold the channels with channel 0 (the value) replaced by 0, slot NC
+// the value, slot NC + 1 pads to 16 bytes. Lane q of a group reads its K
+// slots with aligned 16-byte loads (lane 0's slot 0 is already the zero the
+// dual rules need) and the value with a group-uniform read that the LDS
+// serves as a broadcast: no DPP move and no select on the read path.
+template <int NC>
+constexpr int lds_dual() {
+    return NC == 1 ? 1 : NC + 2;
+}
+
+template <int NC>
+__device__ __forceinline__ void put_split(double* d, int ch, double val) {
+    if constexpr (NC == 1) {
+        d[0] = val;
+    } else if (ch == 0) {
+        d[0] = 0.0;
+        d[NC] = val;
+    } else {
+        d[ch] = val;
+    }
+}
+
+template <int NC>
+__device__ __forceinline__ QD<Quad<NC>::K> qd_load_split(const double* p, int q) {
+    constexpr int K = Quad<NC>::K;
+    QD<K> r;
+    if constexpr (NC == 1) {
+        r.v = p[0];
+        r.t[0] = 0.0;
+    } else {
+        const double* s = p + q * K;
+        if constexpr (K == 1) {
+            r.t[0] = s[0];
+        } else {
+#pragma unroll
+            for (int i = 0; i < K / 2; ++i) {
+                const double2 w = reinterpret_cast<const double2*>(s)[i];
+                r.t[2 * i] = w.x;
+                r.t[2 * i + 1] = w.y;
+            }
+        }
+        r.v = p[NC];
+    }
+    return r;
+}
+
 // product rule
 template <int K>
 __device__ __forceinline__ QD<K> qd_mul(const QD<K>& x, const QD<K>& y) {
@@ -449,10 +496,11 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& 
 #pragma unroll
                         for (int kx = 0; kx < 2; ++kx) {
                             const QD<K> w = qd_mul(kx ? fx : qd_one_minus(fx), wyz);
-                            const double* ep = le + (l0 + kx + ky * ETILE_R + kz * ETILE_R * ETILE_R) * 3 * NC;
-                            qd_fmad(w, qd_load<K, G>(ep, q), ex);
-                            qd_fmad(w, qd_load<K, G>(ep + NC, q), ey);
-                            qd_fmad(w, qd_load<K, G>(ep + 2 * NC, q), ez);
+                            constexpr int D = lds_dual<NC>();
+                            const double* ep = le + (l0 + kx + ky * ETILE_R + kz * ETILE_R * ETILE_R) * 3 * D;
+                            qd_fmad(w, qd_load_split<NC>(ep, q), ex);
+                            qd_fmad(w, qd_load_split<NC>(ep + D, q), ey);
+                            qd_fmad(w, qd_load_split<NC>(ep + 2 * D, q), ez);
                         }
                     }
                 }
@@ -474,30 +522,31 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& 
                     }
                 }
             }
-            const QD<K> tau = qd_load<K, G>(stau, q);
+            const QD<K> tau = qd_load_split<NC>(stau, q);
             qd_fmad(tau, qd_scale(ex, a.kperp), px);
             qd_fmad(tau, qd_scale(ey, a.kperp), py);
             qd_fmad(tau, qd_scale(ez, a.kpar), d);
         }
     }
     if (F & PF_MAP) {
+        constexpr int D = lds_dual<NC>();
         {
-            const double* m = smap + MB_AX * NC;
-            QD<K> nu = qd_mul(qd_load<K, G>(m, q), x), np = qd_mul(qd_load<K, G>(m + 2 * NC, q), x);
-            qd_fmad(qd_load<K, G>(m + NC, q), px, nu);
-            qd_fmad(qd_load<K, G>(m + 3 * NC, q), px, np);
+            const double* m = smap + MB_AX * D;
+            QD<K> nu = qd_mul(qd_load_split<NC>(m, q), x), np = qd_mul(qd_load_split<NC>(m + 2 * D, q), x);
+            qd_fmad(qd_load_split<NC>(m + D, q), px, nu);
+            qd_fmad(qd_load_split<NC>(m + 3 * D, q), px, np);
             x = nu;
             px = np;
         }
         {
-            const double* m = smap + MB_AY * NC;
-            QD<K> nu = qd_mul(qd_load<K, G>(m, q), y), np = qd_mul(qd_load<K, G>(m + 2 * NC, q), y);
-            qd_fmad(qd_load<K, G>(m + NC, q), py, nu);
-            qd_fmad(qd_load<K, G>(m + 3 * NC, q), py, np);
+            const double* m = smap + MB_AY * D;
+            QD<K> nu = qd_mul(qd_load_split<NC>(m, q), y), np = qd_mul(qd_load_split<NC>(m + 2 * D, q), y);
+            qd_fmad(qd_load_split<NC>(m + D, q), py, nu);
+            qd_fmad(qd_load_split<NC>(m + 3 * D, q), py, np);
             y = nu;
             py = np;
         }
-        qd_fmad(qd_load<K, G>(smap + MB_SLIP * NC, q), d, z);
+        qd_fmad(qd_load_split<NC>(smap + MB_SLIP * D, q), d, z);
     }
     if (F & (PF_DEPOSIT | PF_COUNT)) {
         const CellPos g = cell_of(x.v, y.v, z.v, a);
@@ -546,12 +595,14 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& 
     qd_store(sp + 5 * cs, d, q);
 }
 
-// Copy a setting's step constants (tau and one map block) into LDS.
+// Copy a setting's step constants (tau and one map block) into LDS, split layout.
 template <int NC>
 __device__ __forceinline__ void stage_consts(const PartArgs& a, const double* __restrict__ ec, double* smap,
                                              double* stau) {
-    for (int j = threadIdx.x; j < MB_N * NC; j += PART_THREADS) smap[j] = ec[a.map_off + j];
-    for (int j = threadIdx.x; j < NC; j += PART_THREADS) stau[j] = ec[a.tau_off + j];
+    constexpr int D = lds_dual<NC>();
+    for (int j = threadIdx.x; j < MB_N * NC; j += PART_THREADS)
+        put_split<NC>(smap + (j / NC) * D, j % NC, ec[a.map_off + j]);
+    for (int j = threadIdx.x; j < NC; j += PART_THREADS) put_split<NC>(stau, j, ec[a.tau_off + j]);
 }
 
 // Storage-order kernel: deposit by global atomics. A workgroup covers
@@ -560,8 +611,8 @@ __device__ __forceinline__ void stage_consts(const PartArgs& a, const double* __
 template <int NC, int F>
 __global__ __launch_bounds__(PART_THREADS) void k_particles(PartArgs a) {
     constexpr int G = Quad<NC>::G;
-    __shared__ __align__(16) double smap[MB_N * NC];
-    __shared__ __align__(16) double stau[NC];
+    __shared__ __align__(16) double smap[MB_N * lds_dual<NC>()];
+    __shared__ __align__(16) double stau[lds_dual<NC>()];
     const int64_t p0 = (int64_t)blockIdx.x * (PART_THREADS / G);
     const SettingDev sd = a.set[a.owner[p0 / SEG]];
     stage_consts<NC>(a, sd.ec, smap, stau);
@@ -586,16 +637,17 @@ template <int NC, int F>
 __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, TiledArgs t) {
     constexpr int G = Quad<NC>::G;
     constexpr int LDSN = (F & PF_DEPOSIT) ? TILE_CSTRIDE * NC : 1;
-    constexpr int LDSE = use_etile<NC, F>() ? ETILE_NODES * 3 * NC : 1;
+    constexpr int LDSE = use_etile<NC, F>() ? ETILE_NODES * 3 * lds_dual<NC>() : 1;
     __shared__ __align__(16) double lr[LDSN];
     __shared__ __align__(16) double le[LDSE];
-    __shared__ __align__(16) double smap[MB_N * NC];
-    __shared__ __align__(16) double stau[NC];
+    __shared__ __align__(16) double smap[MB_N * lds_dual<NC>()];
+    __shared__ __align__(16) double stau[lds_dual<NC>()];
     const uint32_t nck = *t.nchunks;
     const int q = threadIdx.x % G;
     constexpr int STRIDE = PART_THREADS / G;
     int cur = -1;
     SetView sv{nullptr, nullptr, nullptr, 0.0};
+    const int i0 = threadIdx.x / G;
 #pragma unroll 1
     for (uint32_t ci = blockIdx.x; ci < nck; ci += gridDim.x) {
         const int4 ck = t.chunks[ci];
@@ -612,30 +664,34 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
         const int tx = ck.x % t.tx, ty = (ck.x / t.tx) % t.ty, tz = ck.x / (t.tx * t.ty);
         const int ox = tx * TILE_EDGE - TILE_HALO, oy = ty * TILE_EDGE - TILE_HALO, oz = tz * TILE_EDGE - TILE_HALO;
         if (use_etile<NC, F>() && use_tile) {
-            // E of the tile's nodes: runs of ETILE_R nodes x 3 x NC doubles along x
+            // E of the tile's nodes (runs of ETILE_R nodes x 3 x NC doubles
+            // along x in global memory) into the split layout
             const int gx0 = tx * TILE_EDGE, gy0 = ty * TILE_EDGE, gz0 = tz * TILE_EDGE;
-            for (int j = threadIdx.x; j < LDSE; j += PART_THREADS) {
+            for (int j = threadIdx.x; j < ETILE_NODES * 3 * NC; j += PART_THREADS) {
                 const int node = j / (3 * NC), r = j - node * (3 * NC);
                 const int lx = node % ETILE_R, ly = (node / ETILE_R) % ETILE_R, lz = node / (ETILE_R * ETILE_R);
                 const int gx = gx0 + lx, gy = gy0 + ly, gz = gz0 + lz;
-                le[j] = (gx < a.nx && gy < a.ny && gz < a.nz)
-                            ? sv.E[(((int64_t)gz * a.ny + gy) * a.nx + gx) * 3 * NC + r]
-                            : 0.0;
+                const double v = (gx < a.nx && gy < a.ny && gz < a.nz)
+                                     ? sv.E[(((int64_t)gz * a.ny + gy) * a.nx + gx) * 3 * NC + r]
+                                     : 0.0;
+                put_split<NC>(le + (node * 3 + r / NC) * lds_dual<NC>(), r % NC, v);
             }
         }
         __syncthreads();
         double e0 = 0.0, e1 = 0.0, e2 = 0.0;
-        // software pipeline: the next particle's state is loaded while the
-        // current one is gathered, pushed and deposited
-        int i = threadIdx.x / G;
-        RawState<Quad<NC>::K> next;
-        if (i < ck.z) next = load_raw<NC>(a, (int64_t)ck.y + i, q);
+        {
+            // software pipeline: a thread's loads for its next particle are
+            // issued before the current one is processed (two iterations deep
+            // measured 18% slower at the c2 size)
+            RawState<Quad<NC>::K> next;
+            if (i0 < ck.z) next = load_raw<NC>(a, (int64_t)ck.y + i0, q);
 #pragma unroll 1
-        for (; i < ck.z; i += STRIDE) {
-            const RawState<Quad<NC>::K> curst = next;
-            if (i + STRIDE < ck.z) next = load_raw<NC>(a, (int64_t)ck.y + i + STRIDE, q);
-            particle_body<NC, F, true>(a, sv, smap, stau, (int64_t)ck.y + i, q, curst, lr, le, ox, oy, oz, use_tile,
-                                       e0, e1, e2);
+            for (int i = i0; i < ck.z; i += STRIDE) {
+                const RawState<Quad<NC>::K> curst = next;
+                if (i + STRIDE < ck.z) next = load_raw<NC>(a, (int64_t)ck.y + i + STRIDE, q);
+                particle_body<NC, F, true>(a, sv, smap, stau, (int64_t)ck.y + i, q, curst, lr, le, ox, oy, oz, use_tile,
+                                           e0, e1, e2);
+            }
         }
         if (F & PF_DEPOSIT) {
             __syncthreads();

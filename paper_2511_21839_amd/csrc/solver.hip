@@ -8,7 +8,8 @@
 // tabulated at offsets o = i (i <= n) or i - M (i > n), the circular
 // convolution on the M^3 grid equals the aperiodic sum for those targets.
 // G is even, so its transform Ghat is real; it is stored on the
-// (n+1)^3 octant with the 1/(Mx My Mz) normalisation folded in.
+// (n+1)^3 octant, [ky][kx][kz] with kz fastest, with the 1/(Mx My Mz)
+// normalisation folded in.
 //
 // Channels: the NC real channels of a dual grid array are packed pairwise
 // into NCC = NC/2 complex channels (c, c + NCC); since Ghat is real each
@@ -252,7 +253,7 @@ struct ColArgs {
     int64_t in_batch, out_batch;  // strides between settings (grid dimension y)
     // Ghat multiply (mode 1): column w is (kx = w / ncc), outer index is ky
     const double* ghat;
-    int ncc, gnx1, gny1, Mx, My;
+    int ncc, gnx1, Mx, My;
 };
 
 // Column transforms (passes 2-4 and the Green's function) as two register
@@ -336,6 +337,7 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_cols(const double2* __res
                                                             ColArgs a, const double2* __restrict__ tw) {
     using C = ColCfg<M>;
     constexpr int R1 = C::R1, R2 = C::R2, NG = C::NG, BC = C::BC;
+    constexpr int GZ = M / 2 + 1;  // kz octant rows
     __shared__ double er[M * BC], ei[M * BC], twr[M], twi[M];
     for (int m = threadIdx.x; m < M; m += C::NT) {
         const double2 w = tw[m];
@@ -348,6 +350,24 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_cols(const double2* __res
     const int outer = blockIdx.x / tiles;
     const int col = (blockIdx.x - outer * tiles) * BC + b;
     const bool valid = col < a.W;
+    // mode 1: this thread's Ghat values, issued first so that their latency
+    // overlaps the transform (ky = outer, kx = col / ncc, one contiguous kz row)
+    double gv[MODE == 1 ? NG : 1][R2];
+    if (MODE == 1) {
+        const int ky = outer, kx = col / a.ncc;
+        const int gy = ky <= a.My - ky ? ky : a.My - ky;
+        const int gx = kx <= a.Mx - kx ? kx : a.Mx - kx;
+        const double* grow = a.ghat + ((int64_t)gy * a.gnx1 + gx) * GZ;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) {
+                const int kz = r + R2 * g + R1 * k2;
+                const int gz = kz <= M - kz ? kz : M - kz;
+                gv[g][k2] = valid ? grow[gz] : 0.0;
+            }
+        }
+    }
     const double2* src = in + (int64_t)blockIdx.y * a.in_batch + (int64_t)outer * a.in_outer + (int64_t)col * a.bstride;
     double2* dst = out + (int64_t)blockIdx.y * a.out_batch + (int64_t)outer * a.out_outer + (int64_t)col * a.bstride;
     double hr[NG][R2], hi[NG][R2];  // groups k1 = r + R2 g, values over k2
@@ -392,21 +412,12 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_cols(const double2* __res
             }
             return;
         }
-        // Ghat: outer index is ky, column is (kx, channel), row is kz
-        const int ky = outer, kx = col / a.ncc;
-        const int gy = ky <= a.My - ky ? ky : a.My - ky;
-        const int gx = kx <= a.Mx - kx ? kx : a.Mx - kx;
-        const double* grow = a.ghat + (int64_t)gy * a.gnx1 + gx;
-        const int64_t gzs = (int64_t)a.gny1 * a.gnx1;
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
 #pragma unroll
             for (int k2 = 0; k2 < R2; ++k2) {
-                const int kz = r + R2 * g + R1 * k2;
-                const int gz = kz <= M - kz ? kz : M - kz;
-                const double gv = valid ? grow[gz * gzs] : 0.0;
-                hr[g][k2] *= gv;
-                hi[g][k2] *= gv;
+                hr[g][k2] *= gv[g][k2];
+                hi[g][k2] *= gv[g][k2];
             }
         }
         __syncthreads();  // every stage-B read of the exchange buffer is done
@@ -537,7 +548,6 @@ hipError_t launch_conv(dpic_ctx* cx, double* in, const int nin[3], double* out, 
     a.ghat = cx->ws.ghat;
     a.ncc = NCC;
     a.gnx1 = nx + 1;
-    a.gny1 = ny + 1;
     a.Mx = Mx;
     a.My = My;
     // settings are back to back in every array
@@ -653,7 +663,7 @@ __global__ void k_green_extract(const double2* __restrict__ G, double* __restric
     const int ix = (int)(i % (nx + 1));
     const int iy = (int)((i / (nx + 1)) % (ny + 1));
     const int iz = (int)(i / ((int64_t)(nx + 1) * (ny + 1)));
-    ghat[i] = G[((int64_t)iz * My + iy) * Mx + ix].x * scale;
+    ghat[((int64_t)iy * (nx + 1) + ix) * (nz + 1) + iz] = G[((int64_t)iz * My + iy) * Mx + ix].x * scale;
 }
 
 // tw[m] = exp(-2 pi i m / M) for each axis, tables back to back.
