@@ -166,3 +166,63 @@ def test_c2_full_run_derivatives_match_central_differences(c2):
         err = normwise_err(ad[pl, 1:1 + len(w.params)], fd[pl])
         print(f"plane {pl}: forward mode vs central differences, normwise {err:.3e}")
         assert err <= 2e-4, (pl, err, ad[pl, 1:], fd[pl])
+
+
+def _single(w):
+    from paper_2511_21839_amd import dpic
+
+    one = dpic.Simulation(w.n_particles, w.ntan, w.grid)
+    one.set_beam(w.kinetic_eV, w.rest_eV, w.charge_e, w.bunch_charge_C)
+    one.set_grid(w.lo, w.hi)
+    L = w.lattice
+    one.set_lattice(L.kind, L.n_steps, L.L, L.k, L.L_param, L.k_param, L.n_periods)
+    one.set_params(w.params, w.param_seed())
+    one.init_beam(w.xi(), w.sigma, w.sigma_seed())
+    return one
+
+
+def test_c4_full_batch_sampled_settings():
+    """The 64-setting workload in full (2.4e7 particles, 500 steps, autotuned
+    like the benchmark): no particle leaves its box; four sampled settings
+    (the smallest, the largest and two others) equal their single runs on
+    the GPU; and their centroids follow the zero-current transport of their
+    initial centroids (the oracle tracks one point per setting)."""
+    from paper_2511_21839_amd import dpic
+
+    bt = synth.c4()
+    w = bt.base
+    T = w.total_steps()
+    sim = dpic.Simulation(dpic.batch_capacity(bt.ns), w.ntan, w.grid, nbatch=bt.nbatch)
+    sim.set_beam(w.kinetic_eV, w.rest_eV, w.charge_e, w.bunch_charge_C)
+    sim.set_grid(w.lo, w.hi)
+    L = w.lattice
+    sim.set_lattice(L.kind, L.n_steps, L.L, L.k, L.L_param, L.k_param, L.n_periods)
+    sim.set_params_batch(bt.params, w.param_seed())
+    xi = bt.xi()
+    sim.init_beam_batch(bt.ns, xi, bt.sigma, w.sigma_seed())
+    sim.step(1)
+    sim.autotune(20)
+    sim.init_beam_batch(bt.ns, xi, bt.sigma, w.sigma_seed())
+    sim.step(T)
+    assert sim.batch_counters().sum() == 0
+    eb, mb = sim.emittance(), sim.moments()
+    sim.close()
+    del xi
+    for b in sorted({int(np.argmin(bt.ns)), int(np.argmax(bt.ns)), 17, 42}):
+        ws = bt.setting(b)
+        one = _single(ws)
+        one.step(T)
+        assert_outputs_close(eb[b], one.emittance(), vtol=1e-10, dtol=1e-9, what=f"setting {b}")
+        one.close()
+        point = pic.simulate(xi=ws.xi().mean(axis=0)[None, :], sigma=ws.sigma, sigma_seed=ws.sigma_seed(),
+                             params=ws.params, param_seed=ws.param_seed(), lat=ws.lattice, grid_n=ws.grid,
+                             lo=ws.lo, hi=ws.hi, kinetic_eV=ws.kinetic_eV, rest_eV=ws.rest_eV,
+                             charge_e=ws.charge_e, bunch_charge_C=0.0, ntan=ws.ntan)
+        want = point.particles[0]
+        for pl in range(3):
+            for m, coord in ((3, 2 * pl), (4, 2 * pl + 1)):
+                second = mb[b, pl, 0] if m == 3 else mb[b, pl, 2]
+                rms = np.sqrt(second[0])
+                drms = np.abs(second[1:]).max() / (2.0 * rms)
+                assert abs(mb[b, pl, m, 0] - want[coord, 0]) <= 1e-10 * rms, (b, pl, m)
+                assert np.abs(mb[b, pl, m, 1:] - want[coord, 1:]).max() <= 1e-9 * drms, (b, pl, m)

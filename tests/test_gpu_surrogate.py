@@ -76,6 +76,48 @@ def test_forward_values_and_jacobian_match_oracle(n):
     assert np.abs(o_gpu - oe).max() <= 5e-2 * np.abs(oe).max()
 
 
+def test_full_inference_batch_matches_oracle_on_sampled_rows():
+    """The benchmark's inference launch (65536 samples, values and 13-input
+    Jacobians in one predict) against the oracle's BF16 forward on 512 rows
+    sampled over every column tile, the first and last included."""
+    flat, layers = _bf16_params(7, scale=2.0)
+    net = _net(65536, flat)
+    x = _inputs(65536, 8)
+    eps, jac = net.predict(x)
+    rows = np.unique(np.concatenate([[0, 65535], np.random.default_rng(9).choice(65536, 510, replace=False)]))
+    o, J, _ = mlp.forward(layers, _u(x[rows]), bf16=True)
+    o_gpu = (eps[rows] - OC) / OS
+    J_gpu = jac[rows] * (0.05 * np.abs(NOM))[None, None, :] / OS[None, :, None]
+    assert np.abs(o_gpu - o).max() <= 2e-3 * np.abs(o).max()
+    assert np.abs(J_gpu - J).max() <= 2e-3 * np.abs(J).max()
+
+
+def test_training_batch_gradient_is_the_mean_of_its_parts():
+    """At the benchmark's training batch (4096 samples) the loss and every
+    weight gradient equal the mean over four 1024-sample parts (the loss is
+    a sample mean and the backward seeds scale by 1/n, a power of two, so
+    the BF16 roundings agree): the split-K reduction at full size, up to
+    FP32 summation order."""
+    from paper_2511_21839_amd import surrogate as sg
+
+    flat, _ = _bf16_params(3, scale=2.0)
+    net = _net(4096, flat)
+    x = _inputs(4096, 10)
+    rng = np.random.default_rng(11)
+    eps_t = OC + OS * rng.normal(size=(4096, 2))
+    jac_t = (OS[None, :, None] / (0.05 * np.abs(NOM))[None, None, :]) * rng.normal(size=(4096, 2, 13))
+    loss, g = net.loss_grad(x, eps_t, jac_t, 1.0, 1.0)
+    parts = [net.loss_grad(x[i:i + 1024], eps_t[i:i + 1024], jac_t[i:i + 1024], 1.0, 1.0)
+             for i in range(0, 4096, 1024)]
+    assert loss == pytest.approx(np.mean([p[0] for p in parts]), rel=1e-6)
+    gm = np.mean([p[1].astype(np.float64) for p in parts], axis=0)
+    got = mlp.unflatten(g.astype(np.float64), sg.WIDTHS)
+    want = mlp.unflatten(gm, sg.WIDTHS)
+    for l, ((gW, gb), (wW, wb)) in enumerate(zip(got, want)):
+        assert np.abs(gW - wW).max() <= 1e-4 * np.abs(wW).max(), l
+        assert np.abs(gb - wb).max() <= 1e-4 * np.abs(wb).max(), l
+
+
 @pytest.mark.parametrize("n,wv,wj", [(64, 1.0, 1.0), (333, 0.3, 2.0)])
 def test_loss_gradient_matches_oracle(n, wv, wj):
     from paper_2511_21839_amd import surrogate as sg
