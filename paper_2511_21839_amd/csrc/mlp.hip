@@ -252,21 +252,6 @@ __global__ void k_pack_inputs(const double* __restrict__ x, int n, int npad, Nor
     X0[gid] = (bf16)v;
 }
 
-// OUT [16 npad][32] -> eps [n][2] = oc + os o, jac [n][2][13] = os J / is
-__global__ void k_unpack(const float* __restrict__ out, int n, Norm nm, double* __restrict__ eps,
-                         double* __restrict__ jac) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const float* o = out + (int64_t)s * CPS * FPAD;
-#pragma unroll
-    for (int k = 0; k < NOUT; ++k) {
-        eps[(int64_t)s * NOUT + k] = nm.oc[k] + nm.os[k] * (double)o[k];
-        if (jac)
-            for (int t = 0; t < NIN; ++t)
-                jac[((int64_t)s * NOUT + k) * NIN + t] = nm.os[k] * (double)o[(1 + t) * FPAD + k] / nm.is[t];
-    }
-}
-
 // Sobolev loss head: Zbar_5 [16 npad][32] (BF16) and per-block loss sums.
 constexpr int HEAD_THREADS = 256;
 __global__ __launch_bounds__(HEAD_THREADS) void k_loss_head(const float* __restrict__ out, int n, int npad, Norm nm,
@@ -360,6 +345,187 @@ __global__ void k_weights_bf16(const float* __restrict__ p, LayerTab tb, bf16* _
     const int m = (int)(i / tb.fip[l]), k = (int)(i % tb.fip[l]);
     const float v = (m < tb.fo[l] && k < tb.fi[l]) ? p[tb.w[l] + (int64_t)m * tb.fi[l] + k] : 0.f;
     wb[tb.wp[l] + i] = (bf16)v;
+}
+
+// ---------------------------------------------------------------- fused inference
+// One workgroup carries FT_COLS columns (FT_COLS / 16 samples) through the
+// whole network with its activations in LDS. Per layer, Z = W A with the
+// weights streamed from L2 in BK-wide chunks (double-buffered in LDS) and
+// the accumulators in registers; the epilogue then writes the next layer's
+// activations over the current ones. The MFMA sequence and the epilogue
+// arithmetic are those of the layer-by-layer GEMM, and the outputs go
+// straight to eps and the Jacobian (the unpack formulas).
+constexpr int FT_COLS = 128;
+constexpr int FT_LD = H + 8;  // activation row stride (BF16)
+constexpr int FT_THREADS = 256;
+
+// Weight fragments of one layer for this wave: rows r0 + 16 i + (lane & 15)
+// (i < NI), k = BK ks + 8 (lane >> 4) (ks < KS), in MFMA A-operand order.
+template <int KS, int NI>
+__device__ __forceinline__ void ft_load_w(const bf16* __restrict__ W, int K, int r0, bf16x8 (&wa)[8][4]) {
+    const int lane = threadIdx.x & 63;
+    const bf16* wrow = W + (int64_t)(r0 + (lane & 15)) * K + 8 * (lane >> 4);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int i = 0; i < NI; ++i) wa[ks][i] = *reinterpret_cast<const bf16x8*>(wrow + (int64_t)16 * i * K + ks * BK);
+}
+
+// bias of this lane's rows r0 + 16 i + 4 (lane >> 4) + r
+__device__ __forceinline__ void ft_load_b(const float* __restrict__ bias, int r0, float (&bv)[4][4]) {
+    const int q = (threadIdx.x & 63) >> 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bv[i][r] = bias[r0 + 16 * i + 4 * q + r];
+}
+
+// One hidden layer of a fused tile (K inputs): wave owns rows 64 wave .. + 63
+// and all 8 column blocks, with its weight fragments already in registers
+// (the kernel loads the next layer's while this one runs: one wave per SIMD
+// leaves the registers), so the K loop reads only LDS activations, with no
+// weight staging and no barrier per K step.
+// Epilogue: silu on value columns, silu'(z_value) z on tangents. Only the
+// value column's 16 rows per block are distinct arguments, so the wave
+// writes its 512 of them to its LDS scratch `vs` ([2][512]), each lane
+// evaluates 8 (silu into vs[0], silu' into vs[1]) and every lane reads its
+// rows back: 8 sigmoid evaluations per lane, not 128.
+template <int K>
+__device__ __forceinline__ void ft_hidden(const bf16x8 (&wa)[8][4], const float (&bv)[4][4], bf16* act, float* vs) {
+    constexpr int KS = K / BK;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = lane & 15, q = lane >> 4;
+    __syncthreads();  // the layer's input is in act
+    floatx4 acc[4][8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        bf16x8 bfr[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            bfr[j] = *reinterpret_cast<const bf16x8*>(&act[(16 * j + c) * FT_LD + ks * BK + 8 * q]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[ks][i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+    float* vz = vs;        // value-column pre-activations, then silu
+    float* vd = vs + 512;  // silu'
+    if (c == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                *reinterpret_cast<float4*>(&vz[(i * 8 + j) * 16 + 4 * q]) =
+                    make_float4(acc[i][j][0] + bv[i][0], acc[i][j][1] + bv[i][1], acc[i][j][2] + bv[i][2],
+                                acc[i][j][3] + bv[i][3]);
+    }
+    __syncthreads();  // every read of act is done; the scratch is written
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float z = vz[lane * 8 + k];
+        vd[lane * 8 + k] = dsilu_f(z);
+        vz[lane * 8 + k] = silu_f(z);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int mb = wave * 64 + 16 * i + 4 * q;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float4 sv = *reinterpret_cast<const float4*>(&vz[(i * 8 + j) * 16 + 4 * q]);
+            const float4 dv = *reinterpret_cast<const float4*>(&vd[(i * 8 + j) * 16 + 4 * q]);
+            const float sa[4] = {sv.x, sv.y, sv.z, sv.w}, da[4] = {dv.x, dv.y, dv.z, dv.w};
+            V8 pk;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) pk.h[r] = (bf16)(c == 0 ? sa[r] : da[r] * acc[i][j][r]);
+            *reinterpret_cast<uint2*>(&act[(16 * j + c) * FT_LD + mb]) = make_uint2(pk.u.x, pk.u.y);
+        }
+    }
+}
+
+// The output layer (FPAD padded rows, NOUT real): row block wave & 1 (its
+// weight fragments in wa[ks][0]), column blocks 4 (wave >> 1) + j; rows 0, 1
+// go to eps (value column) and the Jacobian (tangent columns).
+__device__ __forceinline__ void ft_output(const bf16x8 (&wa)[8][4], const float* __restrict__ bias, const bf16* act,
+                                          int s0, int n, const Norm& nm, double* __restrict__ eps,
+                                          double* __restrict__ jac) {
+    constexpr int KS = H / BK;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = lane & 15, q = lane >> 4;
+    __syncthreads();  // the last hidden layer's output is in act
+    floatx4 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bf16x8 bfr =
+                *reinterpret_cast<const bf16x8*>(&act[(16 * (4 * (wave >> 1) + j) + c) * FT_LD + ks * BK + 8 * q]);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[ks][0], bfr, acc[j], 0, 0, 0);
+        }
+    if ((wave & 1) != 0 || q != 0) return;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int s = s0 + 4 * (wave >> 1) + j;
+        if (s >= n) continue;
+#pragma unroll
+        for (int k = 0; k < NOUT; ++k) {
+            float z = acc[j][k];
+            if (c == 0) {
+                z += bias[k];
+                eps[(int64_t)s * NOUT + k] = nm.oc[k] + nm.os[k] * (double)z;
+            } else if (jac && c <= NIN) {
+                jac[((int64_t)s * NOUT + k) * NIN + c - 1] = nm.os[k] * (double)z / nm.is[c - 1];
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(FT_THREADS) void k_mlp_infer(const double* __restrict__ x, int n, Norm nm,
+                                                          const bf16* __restrict__ wb, const float* __restrict__ params,
+                                                          LayerTab tb, double* __restrict__ eps,
+                                                          double* __restrict__ jac) {
+    static_assert(NL == 5, "the layer sequence below is written out for 4 hidden layers");
+    __shared__ __align__(16) bf16 act[FT_COLS * FT_LD];             // [column][feature]
+    __shared__ __align__(16) float vsc[FT_THREADS / 64][2 * 512];  // per-wave epilogue scratch
+    const int s0 = blockIdx.x * (FT_COLS / CPS);
+    const int wave = threadIdx.x >> 6;
+    auto bias = [&](int l) { return params + tb.w[l] + (int64_t)tb.fo[l] * tb.fi[l]; };
+    bf16x8 wA[8][4], wB[8][4];
+    float bA[4][4], bB[4][4];
+    ft_load_w<FPAD / BK, 4>(wb + tb.wp[0], FPAD, 64 * wave, wA);
+    ft_load_b(bias(0), 64 * wave, bA);
+    // layer-0 input: value column u = (x - ic) / is, tangent column 1 + f the unit vector
+    for (int i = threadIdx.x; i < FT_COLS * FPAD; i += FT_THREADS) {
+        const int col = i / FPAD, f = i % FPAD, s = s0 + col / CPS, cc = col % CPS;
+        float v = 0.f;
+        if (s < n && f < NIN) {
+            if (cc == 0)
+                v = (float)((x[(int64_t)s * NIN + f] - nm.ic[f]) / nm.is[f]);
+            else if (cc == 1 + f)
+                v = 1.f;
+        }
+        act[col * FT_LD + f] = (bf16)v;
+    }
+    float* vs = vsc[wave];
+    // each layer's weights are loaded while the previous one runs
+    ft_load_w<H / BK, 4>(wb + tb.wp[1], H, 64 * wave, wB);
+    ft_load_b(bias(1), 64 * wave, bB);
+    ft_hidden<FPAD>(wA, bA, act, vs);
+    ft_load_w<H / BK, 4>(wb + tb.wp[2], H, 64 * wave, wA);
+    ft_load_b(bias(2), 64 * wave, bA);
+    ft_hidden<H>(wB, bB, act, vs);
+    ft_load_w<H / BK, 4>(wb + tb.wp[3], H, 64 * wave, wB);
+    ft_load_b(bias(3), 64 * wave, bB);
+    ft_hidden<H>(wA, bA, act, vs);
+    ft_load_w<H / BK, 1>(wb + tb.wp[4], H, 16 * (wave & 1), wA);
+    ft_hidden<H>(wB, bB, act, vs);
+    ft_output(wA, bias(4), act, s0, n, nm, eps, jac);
 }
 
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m1,
@@ -675,8 +841,9 @@ int dmlp_predict(dmlp_ctx* c, int n, const double* x, double* eps, double* jac) 
     if (!c || !x || !eps) return DPIC_EINVAL;
     int r = check_batch(c, n);
     if (r != DPIC_OK) return r;
-    HIPCHK(c, forward(c, n, x, false));
-    hipLaunchKernelGGL(k_unpack, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->out, n, c->norm, eps, jac);
+    const int tiles = npad_of(n) * CPS / FT_COLS;
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)tiles), dim3(FT_THREADS), 0, c->stream, x, n, c->norm, c->wb,
+                       c->params, layer_tab(), eps, jac);
     HIPCHK(c, hipGetLastError());
     return DPIC_OK;
 }

@@ -92,6 +92,21 @@ def test_full_inference_batch_matches_oracle_on_sampled_rows():
     assert np.abs(J_gpu - J).max() <= 2e-3 * np.abs(J).max()
 
 
+def test_inference_kernel_equals_the_training_forward():
+    """predict runs the fused whole-network kernel; the loss head runs after
+    the layer-by-layer GEMMs of the training path. Both issue the same MFMA
+    sequence and epilogue arithmetic, so with predict's own outputs as the
+    targets the Sobolev loss is zero to rounding (2000 samples, a ragged
+    last tile)."""
+    flat, _ = _bf16_params(5, scale=2.0)
+    net = _net(2048, flat)
+    x = _inputs(2000, 12)
+    eps, jac = net.predict(x)
+    loss, _ = net.loss_grad(x, eps, jac, 1.0, 1.0)
+    scale = np.mean(((eps - OC) / OS) ** 2)
+    assert loss <= 1e-12 * scale, (loss, scale)
+
+
 def test_training_batch_gradient_is_the_mean_of_its_parts():
     """At the benchmark's training batch (4096 samples) the loss and every
     weight gradient equal the mean over four 1024-sample parts (the loss is
