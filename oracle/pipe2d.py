@@ -75,13 +75,14 @@ def solve(rho: np.ndarray, pipe: Pipe) -> np.ndarray:
     """rho [Nx+1][Ny+1][ch] node densities -> phi [Nx+1][Ny+1][ch] (walls 0)."""
     Sx, Sy = sine_matrix(pipe.nx), sine_matrix(pipe.ny)
     inner = rho[1:-1, 1:-1, :]
-    coef = 4.0 / (pipe.nx * pipe.ny) * np.einsum("li,ijc,mj->lmc", Sx, inner, Sy)
+    # the double sums as matrix products (the library's contraction order)
+    coef = 4.0 / (pipe.nx * pipe.ny) * np.einsum("li,ijc,mj->lmc", Sx, inner, Sy, optimize=True)
     al = np.arange(1, pipe.nx) * np.pi / pipe.a
     be = np.arange(1, pipe.ny) * np.pi / pipe.b
     g2 = al[:, None] ** 2 + be[None, :] ** 2
     phic = coef / (physics.EPS0 * g2[:, :, None])
     phi = np.zeros_like(rho)
-    phi[1:-1, 1:-1, :] = np.einsum("li,lmc,mj->ijc", Sx, phic, Sy)
+    phi[1:-1, 1:-1, :] = np.einsum("li,lmc,mj->ijc", Sx, phic, Sy, optimize=True)
     return phi
 
 
