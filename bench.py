@@ -103,12 +103,13 @@ def _adjoint_timing():
     L = w.lattice
     xi = w.xi()
 
-    def plain(ntan):
+    def plain(ntan, graph):
         sim = dpic.Simulation(w.n_particles, ntan, w.grid)
         sim.set_beam(w.kinetic_eV, w.rest_eV, w.charge_e, w.bunch_charge_C)
         sim.set_grid(w.lo, w.hi)
         sim.set_lattice(L.kind, L.n_steps, L.L, L.k, L.L_param, L.k_param, L.n_periods)
         sim.set_params(w.params, w.param_seed() if ntan else None)
+        sim.set_option(dpic.OPT_GRAPH, int(graph))
         ss = w.sigma_seed() if ntan else None
 
         def go():
@@ -116,20 +117,25 @@ def _adjoint_timing():
             sim.step(w.total_steps())
         return go, sim
 
-    go13, s13 = plain(13)
-    go0, s0 = plain(0)
-    run = AdjointRun(w.n_particles, w.grid, w.lo, w.hi, (w.kinetic_eV, w.rest_eV, w.charge_e, w.bunch_charge_C),
-                     (L.kind, L.n_steps, L.L, L.k, L.L_param, L.k_param, L.n_periods), xi, w.total_steps(),
-                     checkpoint_every=50)
+    out = {"workload": "1e4 protons, 32^3 grid, 100 steps, J = eps_x + eps_y, 13 gradient components",
+           "checkpoint_every": 50}
+    # eager launches, and every run replayed from HIP graphs (at this size
+    # the runs are bound by launch overhead)
+    for mode, graph in (("", False), ("graph_", True)):
+        go13, s13 = plain(13, graph)
+        go0, s0 = plain(0, graph)
+        run = AdjointRun(w.n_particles, w.grid, w.lo, w.hi, (w.kinetic_eV, w.rest_eV, w.charge_e, w.bunch_charge_C),
+                         (L.kind, L.n_steps, L.L, L.k, L.L_param, L.k_param, L.n_periods), xi, w.total_steps(),
+                         checkpoint_every=50, graph=graph)
 
-    def adj():
-        run.forward(w.params, w.sigma)
-        run.backward([1.0, 1.0, 0.0])
+        def adj():
+            run.forward(w.params, w.sigma)
+            run.backward([1.0, 1.0, 0.0])
 
-    t13, t0, ta = _median_ms(go13), _median_ms(go0), _median_ms(adj)
-    return {"workload": "1e4 protons, 32^3 grid, 100 steps, J = eps_x + eps_y, 13 gradient components",
-            "checkpoint_every": 50, "t_forward_13_tangents_ms": t13, "t_value_only_ms": t0,
-            "t_adjoint_ms": ta, "adjoint_over_forward_13": ta / t13, "adjoint_over_value_only": ta / t0}
+        t13, t0, ta = _median_ms(go13), _median_ms(go0), _median_ms(adj)
+        out.update({f"{mode}t_forward_13_tangents_ms": t13, f"{mode}t_value_only_ms": t0, f"{mode}t_adjoint_ms": ta,
+                    f"{mode}adjoint_over_forward_13": ta / t13, f"{mode}adjoint_over_value_only": ta / t0})
+    return out
 
 
 def _sim_for(w, capacity, nbatch=1):

@@ -231,7 +231,11 @@ int dpic_load_state(dpic_ctx* ctx, const void* dev_buf);
  *    (0 = twice the device's resident capacity for it, the default);
  *  DPIC_OPT_GRAPH = 1 captures each distinct dpic_step(n) call (same start
  *    step, same n, same batch layout) in a HIP graph on first use and replays
- *    it afterwards; ignored while stage timing or the adjoint is on. The
+ *    it afterwards, and likewise the adjoint sweep of dpic_adjoint_backward
+ *    (same number of forward steps, same weights); ignored while stage
+ *    timing is on. Replays see new parameter values and beams (device
+ *    memory); changing the beam, grid, lattice, particle counts or the
+ *    adjoint binding, or loading a state, drops the captured graphs. The
  *    stream bound at dpic_create may be the null stream: capture runs on a
  *    stream the context creates.
  */

@@ -18,14 +18,18 @@ from . import dpic
 
 class AdjointRun:
     def __init__(self, n_particles: int, grid, lo, hi, beam, lattice, xi: np.ndarray, n_steps: int,
-                 checkpoint_every: int = 50, sort_every: int = 20):
+                 checkpoint_every: int = 50, sort_every: int = 20, graph: bool = False):
         """beam = (kinetic_eV, rest_eV, charge_e, bunch_charge_C);
-        lattice = (kind, n_steps, L, k, L_param, k_param, n_periods)."""
+        lattice = (kind, n_steps, L, k, L_param, k_param, n_periods);
+        graph: capture the forward steps and the adjoint sweep in HIP graphs
+        on first use and replay them afterwards."""
         self.sim = dpic.Simulation(n_particles, 0, grid)
         self.sim.set_beam(*beam)
         self.sim.set_grid(lo, hi)
         self.sim.set_lattice(*lattice)
         self.sim.set_option(dpic.OPT_SORT_EVERY, sort_every)
+        if graph:
+            self.sim.set_option(dpic.OPT_GRAPH, 1)
         self.sim.bind_adjoint(n_steps, checkpoint_every)
         self.xi = np.ascontiguousarray(xi, dtype=np.float64)
         self.n_steps = int(n_steps)

@@ -205,6 +205,9 @@ void clear_graphs(dpic_ctx* c) {
     for (auto& g : c->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     c->graphs.clear();
+    for (auto& g : c->bgraphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    c->bgraphs.clear();
 }
 
 // Storage slots that settings with these particle counts need.
@@ -309,7 +312,7 @@ int step_body(dpic_ctx* c, int n) {
 int step_graph(dpic_ctx* c, int n) {
     for (auto& g : c->graphs) {
         if (g.s0 == c->steps_done && g.n == n && g.swapped_in == c->swapped && g.chunks_in == c->chunks_valid &&
-            g.layout == c->layout_gen) {
+            g.adj == c->adj.bound && g.layout == c->layout_gen) {
             HIPCHK(c, hipGraphLaunch(g.exec, c->stream));
             set_swapped(c, g.swapped_out);
             c->chunks_valid = g.chunks_out;
@@ -324,6 +327,7 @@ int step_graph(dpic_ctx* c, int n) {
     ge.n = n;
     ge.swapped_in = c->swapped;
     ge.chunks_in = c->chunks_valid;
+    ge.adj = c->adj.bound;
     ge.layout = c->layout_gen;
     const Workspace ws0 = c->ws;
     const bool sw0 = c->swapped, ck0 = c->chunks_valid;
@@ -687,7 +691,7 @@ int dpic_step(dpic_ctx* c, int n) {
                     c->schedule.size());
     if (c->adj.bound && c->steps_done + n > c->adj.nmax)
         return fail(c, DPIC_EINVAL, "step: the adjoint workspace covers %d steps", c->adj.nmax);
-    if (c->use_graph && !c->stage_timing && !c->adj.bound) return step_graph(c, n);
+    if (c->use_graph && !c->stage_timing) return step_graph(c, n);
     return step_body(c, n);
 }
 
@@ -1064,20 +1068,18 @@ int dpic_adjoint_bind(dpic_ctx* c, void* adj_dev, size_t bytes, int n_steps, int
     return DPIC_OK;
 }
 
-int dpic_adjoint_backward(dpic_ctx* c, const double w[3], double* grad_params, double* grad_sigma) {
-    if (!c || !w) return DPIC_EINVAL;
-    if (!c->adj.bound) return fail(c, DPIC_ESTATE, "backward: no adjoint workspace bound");
-    if (!c->beam_init) return fail(c, DPIC_ESTATE, "backward: no forward run to differentiate");
-    const int np = c->np;
-    if (np > 15) return fail(c, DPIC_EUNSUPPORTED, "backward: at most 15 parameters");
-    for (int k = 0; k < 3; ++k)
-        if (!isfinite(w[k])) return fail(c, DPIC_EINVAL, "backward: non-finite weight");
+}  // extern "C"
+
+namespace {
+
+// The adjoint sweep of dpic_adjoint_backward, all on c->stream with no host
+// synchronisation: terminal adjoint, then per segment (last first) the
+// replay from its checkpoint keeping each step's start state and field, and
+// the adjoint steps backwards through it.
+int adjoint_sweep(dpic_ctx* c, const double w[3]) {
     const bool sc = c->bunch_charge != 0.0;
     const size_t cap = (size_t)c->dims.n_particles;
     const size_t nodes = grid_nodes(c);
-    unsigned long long cnt[CNT_N];
-    HIPCHK(c, hipMemcpyAsync(cnt, c->ws.counters, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, launch_adj_terminal(c, w));
     HIPCHK(c, launch_zero(c, c->adj.gacc, (size_t)DPIC_MAX_ELEMENTS * 10));
     const int64_t nf = c->steps_done;
@@ -1085,7 +1087,6 @@ int dpic_adjoint_backward(dpic_ctx* c, const double w[3], double* grad_params, d
     int r;
     for (int64_t g = (nf + K - 1) / K - 1; g >= 0; --g) {
         const int64_t sa = g * K, sb = std::min<int64_t>(sa + K, nf);
-        // replay the segment from its checkpoint, keeping each step's start state and field
         HIPCHK(c, hipMemcpyAsync(c->ws.st, c->adj.ckpt + (size_t)g * 6 * cap, 6 * cap * sizeof(double),
                                  hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, launch_zero(c, c->ws.rho, nodes));
@@ -1097,6 +1098,71 @@ int dpic_adjoint_backward(dpic_ctx* c, const double w[3], double* grad_params, d
         for (int64_t s = sb - 1; s >= sa; --s)
             HIPCHK(c, launch_adj_step(c, c->schedule[s], c->adj.states + (size_t)(s - sa) * 6 * cap,
                                       c->adj.fields + (size_t)(s - sa) * 3 * nodes, sc));
+    }
+    return DPIC_OK;
+}
+
+// The same sweep captured once per (steps, weights, buffer parity, layout)
+// on the context's own stream and replayed afterwards; the sweep changes no
+// host state. Parameter values live in device memory, so replays see new ones.
+int adjoint_sweep_graph(dpic_ctx* c, const double w[3]) {
+    for (auto& g : c->bgraphs)
+        if (g.nf == c->steps_done && g.w[0] == w[0] && g.w[1] == w[1] && g.w[2] == w[2] && g.swapped == c->swapped &&
+            g.chunks == c->chunks_valid && g.layout == c->layout_gen) {
+            HIPCHK(c, hipGraphLaunch(g.exec, c->stream));
+            return DPIC_OK;
+        }
+    if (c->bgraphs.size() >= MAX_GRAPHS) clear_graphs(c);
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    BwdGraph bg;
+    bg.nf = c->steps_done;
+    for (int k = 0; k < 3; ++k) bg.w[k] = w[k];
+    bg.swapped = c->swapped;
+    bg.chunks = c->chunks_valid;
+    bg.layout = c->layout_gen;
+    hipStream_t orig = c->stream;
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    c->stream = c->cap_stream;
+    int r = adjoint_sweep(c, w);
+    c->stream = orig;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+    if (r == DPIC_OK && e == hipSuccess && graph) e = hipGraphInstantiate(&bg.exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (r != DPIC_OK || e != hipSuccess) {
+        if (bg.exec) (void)hipGraphExecDestroy(bg.exec);
+        if (r != DPIC_OK) return r;
+        return fail(c, DPIC_EHIP, "backward: graph capture failed: %s", hipGetErrorString(e));
+    }
+    e = hipGraphLaunch(bg.exec, c->stream);
+    if (e != hipSuccess) {
+        (void)hipGraphExecDestroy(bg.exec);
+        return fail(c, DPIC_EHIP, "backward: graph launch failed: %s", hipGetErrorString(e));
+    }
+    c->bgraphs.push_back(bg);
+    return DPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dpic_adjoint_backward(dpic_ctx* c, const double w[3], double* grad_params, double* grad_sigma) {
+    if (!c || !w) return DPIC_EINVAL;
+    if (!c->adj.bound) return fail(c, DPIC_ESTATE, "backward: no adjoint workspace bound");
+    if (!c->beam_init) return fail(c, DPIC_ESTATE, "backward: no forward run to differentiate");
+    const int np = c->np;
+    if (np > 15) return fail(c, DPIC_EUNSUPPORTED, "backward: at most 15 parameters");
+    for (int k = 0; k < 3; ++k)
+        if (!isfinite(w[k])) return fail(c, DPIC_EINVAL, "backward: non-finite weight");
+    unsigned long long cnt[CNT_N];
+    HIPCHK(c, hipMemcpyAsync(cnt, c->ws.counters, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int r;
+    if (c->use_graph && !c->stage_timing) {
+        if ((r = adjoint_sweep_graph(c, w)) != DPIC_OK) return r;
+    } else if ((r = adjoint_sweep(c, w)) != DPIC_OK) {
+        return r;
     }
     // element constants with one tangent per parameter (identity seeds)
     std::vector<double> in((size_t)DPIC_MAX_ELEMENTS * 2 * 16, 0.0);

@@ -109,9 +109,20 @@ struct GraphEntry {
     int64_t s0 = 0;
     int n = 0;
     bool swapped_in = false, chunks_in = false;
+    bool adj = false;  // captured with the adjoint bound (checkpointed single steps)
     uint64_t layout = 0;
     hipGraphExec_t exec = nullptr;
     bool swapped_out = false, chunks_out = false;
+};
+
+// One captured adjoint sweep (terminal adjoint, segment replays and adjoint
+// steps) of dpic_adjoint_backward after nf forward steps with weights w.
+struct BwdGraph {
+    int64_t nf = 0;
+    double w[3] = {0.0, 0.0, 0.0};
+    bool swapped = false, chunks = false;
+    uint64_t layout = 0;
+    hipGraphExec_t exec = nullptr;
 };
 
 }  // namespace dpic
@@ -162,6 +173,7 @@ struct dpic_ctx {
     uint64_t layout_gen = 1;
     hipStream_t cap_stream = nullptr;
     std::vector<dpic::GraphEntry> graphs;
+    std::vector<dpic::BwdGraph> bgraphs;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[DPIC_N_STAGE_TIMERS];
     size_t ev_used[DPIC_N_STAGE_TIMERS] = {0, 0, 0, 0};
     int64_t stage_launches[DPIC_N_STAGE_TIMERS] = {0, 0, 0, 0};

@@ -164,7 +164,7 @@ hipError_t launch_init_beam(dpic_ctx* cx, const double* xi) {
 // registers for a third wave per SIMD but doubles the memory and LDS
 // instructions per byte, four per lane cost the second wave.
 template <int NC>
-struct Quad {
+struct LaneGroup {
     static constexpr int G = NC == 1 ? 1 : NC / 2;
     static constexpr int K = NC / G;
 };
@@ -258,8 +258,8 @@ __device__ __forceinline__ void put_split(double* d, int ch, double val) {
 }
 
 template <int NC>
-__device__ __forceinline__ QD<Quad<NC>::K> qd_load_split(const double* p, int q) {
-    constexpr int K = Quad<NC>::K;
+__device__ __forceinline__ QD<LaneGroup<NC>::K> qd_load_split(const double* p, int q) {
+    constexpr int K = LaneGroup<NC>::K;
     QD<K> r;
     if constexpr (NC == 1) {
         r.v = p[0];
@@ -431,8 +431,8 @@ struct RawState {
 };
 
 template <int NC>
-__device__ __forceinline__ RawState<Quad<NC>::K> load_raw(const PartArgs& a, int64_t p, int q) {
-    constexpr int K = Quad<NC>::K;
+__device__ __forceinline__ RawState<LaneGroup<NC>::K> load_raw(const PartArgs& a, int64_t p, int q) {
+    constexpr int K = LaneGroup<NC>::K;
     RawState<K> s;
     const int64_t cs = a.cap * NC;
     const double* sp = a.st + p * NC + q * K;
@@ -468,9 +468,9 @@ __device__ __forceinline__ QD<K> raw_to_qd(const double* r, int q) {
 template <int NC, int F, bool TILED>
 __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& sv, const double* __restrict__ smap,
                                               const double* __restrict__ stau, int64_t p, int q,
-                                              const RawState<Quad<NC>::K>& raw, double* lr, const double* le, int ox,
+                                              const RawState<LaneGroup<NC>::K>& raw, double* lr, const double* le, int ox,
                                               int oy, int oz, bool use_tile, double& e0, double& e1, double& e2) {
-    constexpr int G = Quad<NC>::G, K = Quad<NC>::K;
+    constexpr int G = LaneGroup<NC>::G, K = LaneGroup<NC>::K;
     const int64_t cs = a.cap * NC;
     double* sp = a.st + p * NC;
     QD<K> x = raw_to_qd<K, G>(raw.r[0], q), px = raw_to_qd<K, G>(raw.r[1], q), y = raw_to_qd<K, G>(raw.r[2], q);
@@ -610,7 +610,7 @@ __device__ __forceinline__ void stage_consts(const PartArgs& a, const double* __
 // so its setting is that of its first slot.
 template <int NC, int F>
 __global__ __launch_bounds__(PART_THREADS) void k_particles(PartArgs a) {
-    constexpr int G = Quad<NC>::G;
+    constexpr int G = LaneGroup<NC>::G;
     __shared__ __align__(16) double smap[MB_N * lds_dual<NC>()];
     __shared__ __align__(16) double stau[lds_dual<NC>()];
     const int64_t p0 = (int64_t)blockIdx.x * (PART_THREADS / G);
@@ -622,7 +622,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles(PartArgs a) {
     const int q = (int)(threadIdx.x % G);
     double e0 = 0.0, e1 = 0.0, e2 = 0.0;
     if (p - sd.off < sd.n) {
-        const RawState<Quad<NC>::K> raw = load_raw<NC>(a, p, q);
+        const RawState<LaneGroup<NC>::K> raw = load_raw<NC>(a, p, q);
         particle_body<NC, F, false>(a, sv, smap, stau, p, q, raw, nullptr, nullptr, 0, 0, 0, false, e0, e1, e2);
     }
     if (F & (PF_DEPOSIT | PF_COUNT)) extent_flush(sv.cnt, e0, e1, e2);
@@ -635,7 +635,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles(PartArgs a) {
 // only nodes that received charge issue global atomics.
 template <int NC, int F>
 __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, TiledArgs t) {
-    constexpr int G = Quad<NC>::G;
+    constexpr int G = LaneGroup<NC>::G;
     constexpr int LDSN = (F & PF_DEPOSIT) ? TILE_CSTRIDE * NC : 1;
     constexpr int LDSE = use_etile<NC, F>() ? ETILE_NODES * 3 * lds_dual<NC>() : 1;
     __shared__ __align__(16) double lr[LDSN];
@@ -683,11 +683,11 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
             // software pipeline: a thread's loads for its next particle are
             // issued before the current one is processed (two iterations deep
             // measured 18% slower at the c2 size)
-            RawState<Quad<NC>::K> next;
+            RawState<LaneGroup<NC>::K> next;
             if (i0 < ck.z) next = load_raw<NC>(a, (int64_t)ck.y + i0, q);
 #pragma unroll 1
             for (int i = i0; i < ck.z; i += STRIDE) {
-                const RawState<Quad<NC>::K> curst = next;
+                const RawState<LaneGroup<NC>::K> curst = next;
                 if (i + STRIDE < ck.z) next = load_raw<NC>(a, (int64_t)ck.y + i + STRIDE, q);
                 particle_body<NC, F, true>(a, sv, smap, stau, (int64_t)ck.y + i, q, curst, lr, le, ox, oy, oz, use_tile,
                                            e0, e1, e2);
@@ -759,7 +759,7 @@ int particle_resident_blocks(dpic_ctx* cx) {
 
 template <int NC, int FL, bool TL>
 static void launch_one(dpic_ctx* cx, const PartArgs& a, const TiledArgs& t, size_t max_items) {
-    constexpr int G = Quad<NC>::G;
+    constexpr int G = LaneGroup<NC>::G;
     dim3 block(PART_THREADS);
     if (TL) {
         // default: twice the resident workgroups, so that the hardware

@@ -27,14 +27,14 @@ def _gpu():
     yield
 
 
-def _run(w, K, n_steps=None):
+def _run(w, K, n_steps=None, graph=False):
     from paper_2511_21839_amd.autograd import AdjointRun
 
     L = w.lattice
     return AdjointRun(w.n_particles, w.grid, w.lo, w.hi,
                       (w.kinetic_eV, w.rest_eV, w.charge_e, w.bunch_charge_C),
                       (L.kind, L.n_steps, L.L, L.k, L.L_param, L.k_param, L.n_periods),
-                      w.xi(), n_steps or w.total_steps(), checkpoint_every=K)
+                      w.xi(), n_steps or w.total_steps(), checkpoint_every=K, graph=graph)
 
 
 def _oracle_grad(w, weights):
@@ -86,6 +86,34 @@ def test_adjoint_repeats_with_new_parameters():
     gp, gs = run.backward([1.0, 1.0, 0.0])
     _, ref = _oracle_grad(w.with_(params=p2, sigma=s2), (1.0, 1.0, 0.0))
     _check(gp, gs, ref)
+
+
+def test_graph_replays_of_forward_and_adjoint_sweep_match_the_oracle():
+    """With graph replay the forward steps and the adjoint sweep are captured
+    on the first call and replayed afterwards: every call, at the first and
+    at a second parameter point (new device-side values under the same
+    graphs), gives the oracle's gradients, and the replayed result equals the
+    captured one."""
+    w = synth.tiny(n_particles=1200, grid=16, steps_per_element=2, ntan=0)
+    w = w.with_(bunch_charge_C=w.bunch_charge_C * 10)
+    run = _run(w, 3, graph=True)
+    _, ref = _oracle_grad(w, (1.0, 1.0, 0.0))
+    first = None
+    for _ in range(2):
+        run.forward(w.params, w.sigma)
+        gp, gs = run.backward([1.0, 1.0, 0.0])
+        _check(gp, gs, ref)
+        if first is None:
+            first = (gp, gs)
+        else:
+            np.testing.assert_allclose(gp, first[0], rtol=1e-11, atol=0)
+            np.testing.assert_allclose(gs, first[1], rtol=1e-11, atol=0)
+    p2 = tuple(np.asarray(w.params) * (1 + 0.03 * np.array([1, -1, 1, 1, -1, 1, -1])))
+    s2 = tuple(np.asarray(w.sigma) * 1.02)
+    run.forward(p2, s2)
+    gp, gs = run.backward([1.0, 1.0, 0.0])
+    _, ref2 = _oracle_grad(w.with_(params=p2, sigma=s2), (1.0, 1.0, 0.0))
+    _check(gp, gs, ref2)
 
 
 def test_adjoint_c1_workload_two_segments():

@@ -100,3 +100,42 @@ def test_particles_outside_the_pipe_are_counted():
     assert ref.lost > 0
     assert sim.counters()[0] == ref.lost
     assert_outputs_close(sim.emittance(), ref.emittance)
+
+
+@pytest.mark.parametrize("ntan,nx,ny", [(0, 4, 4), (15, 16, 8), (3, 8, 32)])
+def test_channel_counts_and_small_grids_match_oracle(ntan, nx, ny):
+    """Value-only, 3 and the maximum 15 tangents (1, 8 and 16 channels), on
+    the smallest grid and on elongated ones, over a whole FODO cell."""
+    w = synth.pipe2d(n_particles=999, cells=nx, steps_per_element=2).with_(ny=ny, ntan=ntan)
+    sim = _make(w)
+    sim.step(w.total_steps())
+    ref = _oracle(w)
+    got = sim.particles()
+    for j in range(4):
+        assert normwise_err(got[:, j, 0], ref.particles[:, j, 0]) <= 1e-10, j
+        if ntan:
+            assert normwise_err(got[:, j, 1:], ref.particles[:, j, 1:]) <= 1e-9, j
+    assert_outputs_close(sim.emittance(), ref.emittance)
+    assert sim.counters() == (ref.lost, w.total_steps())
+
+
+def test_solve_and_field_at_the_largest_grid():
+    """256 x 256 cells (255^2 interior nodes, the ABI's maximum): the dense
+    sine passes against the oracle's sine sums on a random charge."""
+    from paper_2511_21839_amd import pipe2d as p2
+
+    w = synth.pipe2d(n_particles=10, cells=256)
+    sim = _make(w)
+    pipe = pipe2d.Pipe(w.a, w.b, w.nx, w.ny)
+    r = np.random.default_rng(8).normal(size=(w.nx + 1, w.ny + 1, w.ntan + 1)) * 1e-9
+    sim.write_grid(p2.GRID_RHO, r)
+    sim.stage(p2.STAGE_SOLVE)
+    phi = pipe2d.solve(r, pipe)
+    got = sim.read_grid(p2.GRID_PHI)
+    for ch in range(w.ntan + 1):
+        assert normwise_err(got[..., ch], phi[..., ch]) <= 1e-12, ch
+    sim.stage(p2.STAGE_FIELD)
+    E = pipe2d.field(phi, pipe)
+    got = sim.read_grid(p2.GRID_E)
+    for comp in range(2):
+        assert normwise_err(got[:, :, comp], E[comp]) <= 1e-12, comp
