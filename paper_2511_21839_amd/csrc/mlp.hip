@@ -380,18 +380,27 @@ __device__ __forceinline__ void ft_load_b(const float* __restrict__ bias, int r0
         for (int r = 0; r < 4; ++r) bv[i][r] = bias[r0 + 16 * i + 4 * q + r];
 }
 
+// The next layer a hidden layer prefetches into its weight registers.
+struct FtNext {
+    const bf16* W;      // weights [rows][K]
+    const float* bias;  // nullptr for the output layer (its bias is read at the end)
+    int K, r0;          // inputs, this wave's first row
+};
+
 // One hidden layer of a fused tile (K inputs): wave owns rows 64 wave .. + 63
-// and all 8 column blocks, with its weight fragments already in registers
-// (the kernel loads the next layer's while this one runs: one wave per SIMD
-// leaves the registers), so the K loop reads only LDS activations, with no
-// weight staging and no barrier per K step.
+// and all 8 column blocks, with its weight fragments in registers, so the K
+// loop reads only LDS activations (double-buffered per K step), with no
+// weight staging and no barrier per K step. Once its last MFMA has issued,
+// the next layer's fragments (KSN steps of NNI row blocks) and biases are
+// loaded into the same registers while the epilogue runs.
 // Epilogue: silu on value columns, silu'(z_value) z on tangents. Only the
 // value column's 16 rows per block are distinct arguments, so the wave
 // writes its 512 of them to its LDS scratch `vs` ([2][512]), each lane
 // evaluates 8 (silu into vs[0], silu' into vs[1]) and every lane reads its
 // rows back: 8 sigmoid evaluations per lane, not 128.
-template <int K>
-__device__ __forceinline__ void ft_hidden(const bf16x8 (&wa)[8][4], const float (&bv)[4][4], bf16* act, float* vs) {
+template <int K, int KSN, int NNI>
+__device__ __forceinline__ void ft_hidden(bf16x8 (&wa)[8][4], float (&bv)[4][4], FtNext nx, bf16* __restrict__ act,
+                                          float* __restrict__ vs) {
     constexpr int KS = K / BK;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c = lane & 15, q = lane >> 4;
@@ -401,19 +410,25 @@ __device__ __forceinline__ void ft_hidden(const bf16x8 (&wa)[8][4], const float 
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 8; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 bfr[2][8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) bfr[0][j] = *reinterpret_cast<const bf16x8*>(&act[(16 * j + c) * FT_LD + 8 * q]);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-        bf16x8 bfr[8];
+        if (ks + 1 < KS) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-            bfr[j] = *reinterpret_cast<const bf16x8*>(&act[(16 * j + c) * FT_LD + ks * BK + 8 * q]);
+            for (int j = 0; j < 8; ++j)
+                bfr[(ks + 1) & 1][j] =
+                    *reinterpret_cast<const bf16x8*>(&act[(16 * j + c) * FT_LD + (ks + 1) * BK + 8 * q]);
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 8; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[ks][i], bfr[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < 8; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[ks][i], bfr[ks & 1][j], acc[i][j], 0, 0, 0);
     }
-    float* vz = vs;        // value-column pre-activations, then silu
-    float* vd = vs + 512;  // silu'
+    float* __restrict__ vz = vs;        // value-column pre-activations, then silu
+    float* __restrict__ vd = vs + 512;  // silu'
     if (c == 0) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -423,22 +438,38 @@ __device__ __forceinline__ void ft_hidden(const bf16x8 (&wa)[8][4], const float 
                     make_float4(acc[i][j][0] + bv[i][0], acc[i][j][1] + bv[i][1], acc[i][j][2] + bv[i][2],
                                 acc[i][j][3] + bv[i][3]);
     }
+    if (KSN > 0) ft_load_w<KSN, NNI>(nx.W, nx.K, nx.r0, wa);
+    if (nx.bias) ft_load_b(nx.bias, nx.r0, bv);
     __syncthreads();  // every read of act is done; the scratch is written
+    {
+        const float4 z0 = *reinterpret_cast<const float4*>(&vz[lane * 8]);
+        const float4 z1 = *reinterpret_cast<const float4*>(&vz[lane * 8 + 4]);
+        const float z[8] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w};
+        float sv[8], dv[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const float z = vz[lane * 8 + k];
-        vd[lane * 8 + k] = dsilu_f(z);
-        vz[lane * 8 + k] = silu_f(z);
+        for (int k = 0; k < 8; ++k) {
+            dv[k] = dsilu_f(z[k]);
+            sv[k] = silu_f(z[k]);
+        }
+        *reinterpret_cast<float4*>(&vd[lane * 8]) = make_float4(dv[0], dv[1], dv[2], dv[3]);
+        *reinterpret_cast<float4*>(&vd[lane * 8 + 4]) = make_float4(dv[4], dv[5], dv[6], dv[7]);
+        *reinterpret_cast<float4*>(&vz[lane * 8]) = make_float4(sv[0], sv[1], sv[2], sv[3]);
+        *reinterpret_cast<float4*>(&vz[lane * 8 + 4]) = make_float4(sv[4], sv[5], sv[6], sv[7]);
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int mb = wave * 64 + 16 * i + 4 * q;
+        // this row block's factors for all 8 column blocks first, then the writes
+        float4 sv[8], dv[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const float4 sv = *reinterpret_cast<const float4*>(&vz[(i * 8 + j) * 16 + 4 * q]);
-            const float4 dv = *reinterpret_cast<const float4*>(&vd[(i * 8 + j) * 16 + 4 * q]);
-            const float sa[4] = {sv.x, sv.y, sv.z, sv.w}, da[4] = {dv.x, dv.y, dv.z, dv.w};
+            sv[j] = *reinterpret_cast<const float4*>(&vz[(i * 8 + j) * 16 + 4 * q]);
+            dv[j] = *reinterpret_cast<const float4*>(&vd[(i * 8 + j) * 16 + 4 * q]);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float sa[4] = {sv[j].x, sv[j].y, sv[j].z, sv[j].w}, da[4] = {dv[j].x, dv[j].y, dv[j].z, dv[j].w};
             V8 pk;
 #pragma unroll
             for (int r = 0; r < 4; ++r) pk.h[r] = (bf16)(c == 0 ? sa[r] : da[r] * acc[i][j][r]);
@@ -496,10 +527,10 @@ __global__ __launch_bounds__(FT_THREADS) void k_mlp_infer(const double* __restri
     const int s0 = blockIdx.x * (FT_COLS / CPS);
     const int wave = threadIdx.x >> 6;
     auto bias = [&](int l) { return params + tb.w[l] + (int64_t)tb.fo[l] * tb.fi[l]; };
-    bf16x8 wA[8][4], wB[8][4];
-    float bA[4][4], bB[4][4];
-    ft_load_w<FPAD / BK, 4>(wb + tb.wp[0], FPAD, 64 * wave, wA);
-    ft_load_b(bias(0), 64 * wave, bA);
+    bf16x8 wa[8][4];
+    float bv[4][4];
+    ft_load_w<FPAD / BK, 4>(wb + tb.wp[0], FPAD, 64 * wave, wa);
+    ft_load_b(bias(0), 64 * wave, bv);
     // layer-0 input: value column u = (x - ic) / is, tangent column 1 + f the unit vector
     for (int i = threadIdx.x; i < FT_COLS * FPAD; i += FT_THREADS) {
         const int col = i / FPAD, f = i % FPAD, s = s0 + col / CPS, cc = col % CPS;
@@ -513,19 +544,12 @@ __global__ __launch_bounds__(FT_THREADS) void k_mlp_infer(const double* __restri
         act[col * FT_LD + f] = (bf16)v;
     }
     float* vs = vsc[wave];
-    // each layer's weights are loaded while the previous one runs
-    ft_load_w<H / BK, 4>(wb + tb.wp[1], H, 64 * wave, wB);
-    ft_load_b(bias(1), 64 * wave, bB);
-    ft_hidden<FPAD>(wA, bA, act, vs);
-    ft_load_w<H / BK, 4>(wb + tb.wp[2], H, 64 * wave, wA);
-    ft_load_b(bias(2), 64 * wave, bA);
-    ft_hidden<H>(wB, bB, act, vs);
-    ft_load_w<H / BK, 4>(wb + tb.wp[3], H, 64 * wave, wB);
-    ft_load_b(bias(3), 64 * wave, bB);
-    ft_hidden<H>(wA, bA, act, vs);
-    ft_load_w<H / BK, 1>(wb + tb.wp[4], H, 16 * (wave & 1), wA);
-    ft_hidden<H>(wB, bB, act, vs);
-    ft_output(wA, bias(4), act, s0, n, nm, eps, jac);
+    // each layer loads the next one's weights and biases while its epilogue runs
+    ft_hidden<FPAD, H / BK, 4>(wa, bv, FtNext{wb + tb.wp[1], bias(1), H, 64 * wave}, act, vs);
+    ft_hidden<H, H / BK, 4>(wa, bv, FtNext{wb + tb.wp[2], bias(2), H, 64 * wave}, act, vs);
+    ft_hidden<H, H / BK, 4>(wa, bv, FtNext{wb + tb.wp[3], bias(3), H, 64 * wave}, act, vs);
+    ft_hidden<H, H / BK, 1>(wa, bv, FtNext{wb + tb.wp[4], nullptr, H, 16 * (wave & 1)}, act, vs);
+    ft_output(wa, bias(4), act, s0, n, nm, eps, jac);
 }
 
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m1,
