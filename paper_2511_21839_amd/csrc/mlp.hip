@@ -371,6 +371,15 @@ __device__ __forceinline__ void ft_load_w(const bf16* __restrict__ W, int K, int
         for (int i = 0; i < NI; ++i) wa[ks][i] = *reinterpret_cast<const bf16x8*>(wrow + (int64_t)16 * i * K + ks * BK);
 }
 
+// fragment ks of rows r0 + 16 i + (lane & 15), i < NI, of a [rows][K] matrix
+template <int NI>
+__device__ __forceinline__ void ft_load_frag(const bf16* __restrict__ W, int K, int r0, int ks, bf16x8 (&wa)[8][4]) {
+    const int lane = threadIdx.x & 63;
+    const bf16* wrow = W + (int64_t)(r0 + (lane & 15)) * K + 8 * (lane >> 4) + ks * BK;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) wa[ks][i] = *reinterpret_cast<const bf16x8*>(wrow + (int64_t)16 * i * K);
+}
+
 // bias of this lane's rows r0 + 16 i + 4 (lane >> 4) + r
 __device__ __forceinline__ void ft_load_b(const float* __restrict__ bias, int r0, float (&bv)[4][4]) {
     const int q = (threadIdx.x & 63) >> 4;
@@ -390,9 +399,9 @@ struct FtNext {
 // One hidden layer of a fused tile (K inputs): wave owns rows 64 wave .. + 63
 // and all 8 column blocks, with its weight fragments in registers, so the K
 // loop reads only LDS activations (double-buffered per K step), with no
-// weight staging and no barrier per K step. Once its last MFMA has issued,
-// the next layer's fragments (KSN steps of NNI row blocks) and biases are
-// loaded into the same registers while the epilogue runs.
+// weight staging and no barrier per K step. As soon as K step ks has issued
+// its MFMAs, fragment ks of the next layer (KSN steps of NNI row blocks) is
+// loaded into the same registers; the next biases load during the epilogue.
 // Epilogue: silu on value columns, silu'(z_value) z on tangents. Only the
 // value column's 16 rows per block are distinct arguments, so the wave
 // writes its 512 of them to its LDS scratch `vs` ([2][512]), each lane
@@ -426,7 +435,10 @@ __device__ __forceinline__ void ft_hidden(bf16x8 (&wa)[8][4], float (&bv)[4][4],
 #pragma unroll
             for (int j = 0; j < 8; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[ks][i], bfr[ks & 1][j], acc[i][j], 0, 0, 0);
+        if (ks < KSN) ft_load_frag<NNI>(nx.W, nx.K, nx.r0, ks, wa);  // step ks is done with these registers
     }
+#pragma unroll
+    for (int ks = KS; ks < KSN; ++ks) ft_load_frag<NNI>(nx.W, nx.K, nx.r0, ks, wa);
     float* __restrict__ vz = vs;        // value-column pre-activations, then silu
     float* __restrict__ vd = vs + 512;  // silu'
     if (c == 0) {
@@ -438,7 +450,6 @@ __device__ __forceinline__ void ft_hidden(bf16x8 (&wa)[8][4], float (&bv)[4][4],
                     make_float4(acc[i][j][0] + bv[i][0], acc[i][j][1] + bv[i][1], acc[i][j][2] + bv[i][2],
                                 acc[i][j][3] + bv[i][3]);
     }
-    if (KSN > 0) ft_load_w<KSN, NNI>(nx.W, nx.K, nx.r0, wa);
     if (nx.bias) ft_load_b(nx.bias, nx.r0, bv);
     __syncthreads();  // every read of act is done; the scratch is written
     {
