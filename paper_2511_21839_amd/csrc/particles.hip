@@ -365,16 +365,15 @@ struct TiledArgs {
     int tx, ty, nbins;
 };
 
-// LDS copy of the deposit tile, channel-major. The channel stride is 1 mod 16
-// doubles, so channel c of node n sits in bank pair (c + n) mod 16: the lanes
-// of a group (channels k, k+K, ..) and particles at different nodes spread
-// over the banks.
-constexpr int TILE_NODES = TILE_R * TILE_R * TILE_R;
-// E tile of a work item: the (TILE_EDGE + 1)^3 nodes of its tile's cells
-constexpr int ETILE_R = TILE_EDGE + 1;
-constexpr int ETILE_NODES = ETILE_R * ETILE_R * ETILE_R;
-// The E tile is staged only where it leaves room for three workgroups per
-// CU: at 16 channels it and the deposit tile would take 93 KB.
+// LDS tiles of a work item: the nodes [o, o + TILE_R) x [.., + TILE_R) x
+// [.., + TILE_RZ) around its grid tile. The deposit copy is channel-major
+// with a channel stride of 1 mod 16 doubles, so channel c of node n sits in
+// bank pair (c + n) mod 16: the lanes of a group (channels k, k+K, ..) and
+// particles at different nodes spread over the banks. The E copy covers the
+// same nodes, so a particle gathers from LDS exactly when it deposits there.
+constexpr int TILE_NODES = TILE_R * TILE_R * TILE_RZ;
+// The E tile is staged only where it leaves room for two workgroups per
+// CU: at 16 channels it and the deposit tile would take 122 KB.
 template <int NC, int F>
 constexpr bool use_etile() {
     return (F & PF_KICK) && NC <= 8;
@@ -482,12 +481,11 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& 
             const QD<K> fx = qd_frac(x, g.sx, g.ix, a.ih0), fy = qd_frac(y, g.sy, g.iy, a.ih1),
                         fz = qd_frac(z, g.sz, g.iz, a.ih2);
             QD<K> ex = qd_zero<K>(), ey = qd_zero<K>(), ez = qd_zero<K>();
-            // the item's E tile in LDS holds the nodes of its tile's cells
-            const int tlx = g.ix - ox - TILE_HALO, tly = g.iy - oy - TILE_HALO, tlz = g.iz - oz - TILE_HALO;
-            const bool in_etile = TILED && use_etile<NC, F>() && use_tile && tlx >= 0 && tlx < TILE_EDGE && tly >= 0 && tly < TILE_EDGE &&
-                                  tlz >= 0 && tlz < TILE_EDGE;
+            const int tlx = g.ix - ox, tly = g.iy - oy, tlz = g.iz - oz;
+            const bool in_etile = TILED && use_etile<NC, F>() && use_tile && tlx >= 0 && tlx <= TILE_R - 2 &&
+                                  tly >= 0 && tly <= TILE_R - 2 && tlz >= 0 && tlz <= TILE_RZ - 2;
             if (in_etile) {
-                const int l0 = (tlz * ETILE_R + tly) * ETILE_R + tlx;
+                const int l0 = (tlz * TILE_R + tly) * TILE_R + tlx;
 #pragma unroll
                 for (int kz = 0; kz < 2; ++kz) {
 #pragma unroll
@@ -497,7 +495,7 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& 
                         for (int kx = 0; kx < 2; ++kx) {
                             const QD<K> w = qd_mul(kx ? fx : qd_one_minus(fx), wyz);
                             constexpr int D = lds_dual<NC>();
-                            const double* ep = le + (l0 + kx + ky * ETILE_R + kz * ETILE_R * ETILE_R) * 3 * D;
+                            const double* ep = le + (l0 + kx + ky * TILE_R + kz * TILE_R * TILE_R) * 3 * D;
                             qd_fmad(w, qd_load_split<NC>(ep, q), ex);
                             qd_fmad(w, qd_load_split<NC>(ep + D, q), ey);
                             qd_fmad(w, qd_load_split<NC>(ep + 2 * D, q), ez);
@@ -556,22 +554,34 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& 
                             fz = qd_frac(z, g.sz, g.iz, a.ih2);
                 const int lx = g.ix - ox, ly = g.iy - oy, lz = g.iz - oz;
                 const bool local = TILED && use_tile && lx >= 0 && lx <= TILE_R - 2 && ly >= 0 &&
-                                   ly <= TILE_R - 2 && lz >= 0 && lz <= TILE_R - 2;
-                const int64_t n0 = ((int64_t)g.iz * a.ny + g.iy) * a.nx + g.ix;
-                const int l0 = (lz * TILE_R + ly) * TILE_R + lx;
+                                   ly <= TILE_R - 2 && lz >= 0 && lz <= TILE_RZ - 2;
+                if (TILED && local) {
+                    const int l0 = (lz * TILE_R + ly) * TILE_R + lx;
 #pragma unroll
-                for (int kz = 0; kz < 2; ++kz) {
+                    for (int kz = 0; kz < 2; ++kz) {
 #pragma unroll
-                    for (int ky = 0; ky < 2; ++ky) {
-                        const QD<K> wyz = qd_mul(ky ? fy : qd_one_minus(fy), kz ? fz : qd_one_minus(fz));
+                        for (int ky = 0; ky < 2; ++ky) {
+                            const QD<K> wyz = qd_mul(ky ? fy : qd_one_minus(fy), kz ? fz : qd_one_minus(fz));
 #pragma unroll
-                        for (int kx = 0; kx < 2; ++kx) {
-                            const QD<K> w = qd_mul(kx ? fx : qd_one_minus(fx), wyz);
-                            if (TILED && local) {
+                            for (int kx = 0; kx < 2; ++kx) {
+                                const QD<K> w = qd_mul(kx ? fx : qd_one_minus(fx), wyz);
                                 double* l = lr + (q * K) * TILE_CSTRIDE + l0 + kx + ky * TILE_R + kz * TILE_R * TILE_R;
 #pragma unroll
-                                for (int k = 0; k < K; ++k) unsafeAtomicAdd(l + k * TILE_CSTRIDE, qd_chan(w, q, k) * sv.q);
-                            } else {
+                                for (int k = 0; k < K; ++k)
+                                    unsafeAtomicAdd(l + k * TILE_CSTRIDE, qd_chan(w, q, k) * sv.q);
+                            }
+                        }
+                    }
+                } else {
+                    const int64_t n0 = ((int64_t)g.iz * a.ny + g.iy) * a.nx + g.ix;
+#pragma unroll
+                    for (int kz = 0; kz < 2; ++kz) {
+#pragma unroll
+                        for (int ky = 0; ky < 2; ++ky) {
+                            const QD<K> wyz = qd_mul(ky ? fy : qd_one_minus(fy), kz ? fz : qd_one_minus(fz));
+#pragma unroll
+                            for (int kx = 0; kx < 2; ++kx) {
+                                const QD<K> w = qd_mul(kx ? fx : qd_one_minus(fx), wyz);
                                 double* r = sv.rho + (n0 + kx + ky * a.nx + kz * sxy) * NC + q * K;
 #pragma unroll
                                 for (int k = 0; k < K; ++k) unsafeAtomicAdd(r + k, qd_chan(w, q, k) * sv.q);
@@ -637,7 +647,7 @@ template <int NC, int F>
 __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, TiledArgs t) {
     constexpr int G = LaneGroup<NC>::G;
     constexpr int LDSN = (F & PF_DEPOSIT) ? TILE_CSTRIDE * NC : 1;
-    constexpr int LDSE = use_etile<NC, F>() ? ETILE_NODES * 3 * lds_dual<NC>() : 1;
+    constexpr int LDSE = use_etile<NC, F>() ? TILE_NODES * 3 * lds_dual<NC>() : 1;
     __shared__ __align__(16) double lr[LDSN];
     __shared__ __align__(16) double le[LDSE];
     __shared__ __align__(16) double smap[MB_N * lds_dual<NC>()];
@@ -662,16 +672,15 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
             for (int j = threadIdx.x; j < LDSN; j += PART_THREADS) lr[j] = 0.0;
         const bool use_tile = ck.x < t.nbins - 1;
         const int tx = ck.x % t.tx, ty = (ck.x / t.tx) % t.ty, tz = ck.x / (t.tx * t.ty);
-        const int ox = tx * TILE_EDGE - TILE_HALO, oy = ty * TILE_EDGE - TILE_HALO, oz = tz * TILE_EDGE - TILE_HALO;
+        const int ox = tx * TILE_EDGE - TILE_HALO, oy = ty * TILE_EDGE - TILE_HALO, oz = tz * TILE_EDGE - TILE_HALO_Z;
         if (use_etile<NC, F>() && use_tile) {
-            // E of the tile's nodes (runs of ETILE_R nodes x 3 x NC doubles
+            // E of the tile's nodes (runs of TILE_R nodes x 3 x NC doubles
             // along x in global memory) into the split layout
-            const int gx0 = tx * TILE_EDGE, gy0 = ty * TILE_EDGE, gz0 = tz * TILE_EDGE;
-            for (int j = threadIdx.x; j < ETILE_NODES * 3 * NC; j += PART_THREADS) {
+            for (int j = threadIdx.x; j < TILE_NODES * 3 * NC; j += PART_THREADS) {
                 const int node = j / (3 * NC), r = j - node * (3 * NC);
-                const int lx = node % ETILE_R, ly = (node / ETILE_R) % ETILE_R, lz = node / (ETILE_R * ETILE_R);
-                const int gx = gx0 + lx, gy = gy0 + ly, gz = gz0 + lz;
-                const double v = (gx < a.nx && gy < a.ny && gz < a.nz)
+                const int lx = node % TILE_R, ly = (node / TILE_R) % TILE_R, lz = node / (TILE_R * TILE_R);
+                const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+                const double v = (gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz)
                                      ? sv.E[(((int64_t)gz * a.ny + gy) * a.nx + gx) * 3 * NC + r]
                                      : 0.0;
                 put_split<NC>(le + (node * 3 + r / NC) * lds_dual<NC>(), r % NC, v);
