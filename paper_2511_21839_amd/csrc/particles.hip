@@ -380,9 +380,16 @@ constexpr bool use_etile() {
 }
 constexpr int TILE_CSTRIDE = ((TILE_NODES + 15) / 16) * 16 + 1;
 constexpr int PART_THREADS = 256;
+constexpr int STAGE_BATCH = 8;  // E-tile staging loads in flight per thread
 
-// wavefront max of the extents (all 64 lanes take part), one atomic per wave
-__device__ __forceinline__ void extent_flush(unsigned long long* cnt, double e0, double e1, double e2) {
+// Workgroup max of the extents (every thread of the workgroup calls it),
+// merged into the setting's counters by one thread, with an atomic only
+// where it raises the stored value. All workgroups update the same three
+// words: atomics there queue behind each other, and a wave's later loads
+// wait for its earlier atomics, so they are kept rare (once per workgroup
+// and setting; the extents stop growing after the first steps).
+__device__ __forceinline__ void extent_flush(unsigned long long* cnt, double e0, double e1, double e2,
+                                             double (*sext)[3]) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         e0 = fmax(e0, __shfl_xor(e0, off, 64));
@@ -390,10 +397,23 @@ __device__ __forceinline__ void extent_flush(unsigned long long* cnt, double e0,
         e2 = fmax(e2, __shfl_xor(e2, off, 64));
     }
     if ((threadIdx.x & 63) == 0) {
-        atomicMax(cnt + CNT_EXT_X, (unsigned long long)__double_as_longlong(e0));
-        atomicMax(cnt + CNT_EXT_Y, (unsigned long long)__double_as_longlong(e1));
-        atomicMax(cnt + CNT_EXT_Z, (unsigned long long)__double_as_longlong(e2));
+        sext[threadIdx.x / 64][0] = e0;
+        sext[threadIdx.x / 64][1] = e1;
+        sext[threadIdx.x / 64][2] = e2;
     }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double m = sext[0][d];
+            for (int w = 1; w < (int)(blockDim.x / 64); ++w) m = fmax(m, sext[w][d]);
+            // non-negative doubles order like their bit patterns
+            const unsigned long long v = (unsigned long long)__double_as_longlong(m);
+            if (v > __hip_atomic_load(cnt + CNT_EXT_X + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                atomicMax(cnt + CNT_EXT_X + d, v);
+        }
+    }
+    __syncthreads();  // sext is reused
 }
 
 struct CellPos {
@@ -623,6 +643,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles(PartArgs a) {
     constexpr int G = LaneGroup<NC>::G;
     __shared__ __align__(16) double smap[MB_N * lds_dual<NC>()];
     __shared__ __align__(16) double stau[lds_dual<NC>()];
+    __shared__ double sext[PART_THREADS / 64][3];
     const int64_t p0 = (int64_t)blockIdx.x * (PART_THREADS / G);
     const SettingDev sd = a.set[a.owner[p0 / SEG]];
     stage_consts<NC>(a, sd.ec, smap, stau);
@@ -635,7 +656,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles(PartArgs a) {
         const RawState<LaneGroup<NC>::K> raw = load_raw<NC>(a, p, q);
         particle_body<NC, F, false>(a, sv, smap, stau, p, q, raw, nullptr, nullptr, 0, 0, 0, false, e0, e1, e2);
     }
-    if (F & (PF_DEPOSIT | PF_COUNT)) extent_flush(sv.cnt, e0, e1, e2);
+    if (F & (PF_DEPOSIT | PF_COUNT)) extent_flush(sv.cnt, e0, e1, e2, sext);
 }
 
 // Tiled kernel, persistent: each workgroup walks the work list with a grid
@@ -652,17 +673,23 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
     __shared__ __align__(16) double le[LDSE];
     __shared__ __align__(16) double smap[MB_N * lds_dual<NC>()];
     __shared__ __align__(16) double stau[lds_dual<NC>()];
+    __shared__ double sext[PART_THREADS / 64][3];
     const uint32_t nck = *t.nchunks;
     const int q = threadIdx.x % G;
     constexpr int STRIDE = PART_THREADS / G;
     int cur = -1;
     SetView sv{nullptr, nullptr, nullptr, 0.0};
     const int i0 = threadIdx.x / G;
+    double e0 = 0.0, e1 = 0.0, e2 = 0.0;  // this thread's extents in the current setting
 #pragma unroll 1
     for (uint32_t ci = blockIdx.x; ci < nck; ci += gridDim.x) {
         const int4 ck = t.chunks[ci];
         if (ci != blockIdx.x) __syncthreads();  // the previous item's flush is done with lr and smap
         if (ck.w != cur) {
+            if ((F & (PF_DEPOSIT | PF_COUNT)) && cur >= 0) {
+                extent_flush(sv.cnt, e0, e1, e2, sext);
+                e0 = e1 = e2 = 0.0;
+            }
             cur = ck.w;
             const SettingDev sd = a.set[cur];
             sv = set_view(sd);
@@ -675,19 +702,31 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
         const int ox = tx * TILE_EDGE - TILE_HALO, oy = ty * TILE_EDGE - TILE_HALO, oz = tz * TILE_EDGE - TILE_HALO_Z;
         if (use_etile<NC, F>() && use_tile) {
             // E of the tile's nodes (runs of TILE_R nodes x 3 x NC doubles
-            // along x in global memory) into the split layout
-            for (int j = threadIdx.x; j < TILE_NODES * 3 * NC; j += PART_THREADS) {
-                const int node = j / (3 * NC), r = j - node * (3 * NC);
-                const int lx = node % TILE_R, ly = (node / TILE_R) % TILE_R, lz = node / (TILE_R * TILE_R);
-                const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
-                const double v = (gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz)
-                                     ? sv.E[(((int64_t)gz * a.ny + gy) * a.nx + gx) * 3 * NC + r]
-                                     : 0.0;
-                put_split<NC>(le + (node * 3 + r / NC) * lds_dual<NC>(), r % NC, v);
+            // along x in global memory) into the split layout, SB loads in
+            // flight per thread before their LDS writes
+            constexpr int SN = TILE_NODES * 3 * NC, SB = STAGE_BATCH;
+#pragma unroll 1
+            for (int j0 = 0; j0 < SN; j0 += SB * PART_THREADS) {
+                double v[SB];
+#pragma unroll
+                for (int k = 0; k < SB; ++k) {
+                    const int j = j0 + threadIdx.x + k * PART_THREADS;
+                    const int node = j / (3 * NC), r = j - node * (3 * NC);
+                    const int lx = node % TILE_R, ly = (node / TILE_R) % TILE_R, lz = node / (TILE_R * TILE_R);
+                    const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+                    v[k] = (j < SN && gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz)
+                               ? sv.E[(((int64_t)gz * a.ny + gy) * a.nx + gx) * 3 * NC + r]
+                               : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < SB; ++k) {
+                    const int j = j0 + threadIdx.x + k * PART_THREADS;
+                    const int node = j / (3 * NC), r = j - node * (3 * NC);
+                    if (j < SN) put_split<NC>(le + (node * 3 + r / NC) * lds_dual<NC>(), r % NC, v[k]);
+                }
             }
         }
         __syncthreads();
-        double e0 = 0.0, e1 = 0.0, e2 = 0.0;
         {
             // software pipeline: a thread's loads for its next particle are
             // issued before the current one is processed (two iterations deep
@@ -721,8 +760,8 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
                 }
             }
         }
-        if (F & (PF_DEPOSIT | PF_COUNT)) extent_flush(sv.cnt, e0, e1, e2);
     }
+    if ((F & (PF_DEPOSIT | PF_COUNT)) && cur >= 0) extent_flush(sv.cnt, e0, e1, e2, sext);
 }
 
 // Resident workgroups per CU of one tiled-kernel instance (queried once).
