@@ -24,222 +24,12 @@
 // Forward transforms read only the n nonzero inputs; inverse transforms write
 // only the n+2 outputs needed (positions M-1, 0, .., n).
 //
-// Each pass holds a tile of TILE complex values (one M-point transform per
-// column, B = TILE/M columns) in LDS and runs a Stockham autosort FFT
-// (radix 4, then one radix-2 stage when log2 M is odd) between two LDS
-// buffers; global loads and stores touch B contiguous complex values per row.
+// Every pass runs its M-point transforms as two register stages with one
+// LDS exchange between them (ColCfg below); the x passes treat channel j of
+// a row, its values interleaved with the row's other channels, as a column.
 #include "context.hpp"
 
 namespace dpic {
-
-constexpr int FFT_THREADS = 256;
-constexpr int TILE = 1024;
-
-// ---------------------------------------------------------------- FFT core
-template <int M, bool INV>
-__device__ __forceinline__ void stage4(const double* __restrict__ sr, const double* __restrict__ si,
-                                       double* __restrict__ dr, double* __restrict__ di, int Ns, int lb,
-                                       const double* __restrict__ twr, const double* __restrict__ twi) {
-    constexpr int Q = M / 4;
-    const int B = 1 << lb;
-    const int total = Q << lb;
-    const int tstride = M / (Ns * 4);
-    for (int t = threadIdx.x; t < total; t += FFT_THREADS) {
-        const int b = t & (B - 1);
-        const int j = t >> lb;
-        const int k = j & (Ns - 1);
-        double ar[4], ai[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            ar[r] = sr[((j + r * Q) << lb) + b];
-            ai[r] = si[((j + r * Q) << lb) + b];
-        }
-        if (k != 0) {
-#pragma unroll
-            for (int r = 1; r < 4; ++r) {
-                const int m = r * k * tstride;
-                const double wr = twr[m];
-                const double wi = INV ? -twi[m] : twi[m];
-                const double xr = ar[r] * wr - ai[r] * wi;
-                const double xi = ar[r] * wi + ai[r] * wr;
-                ar[r] = xr;
-                ai[r] = xi;
-            }
-        }
-        const double t0r = ar[0] + ar[2], t0i = ai[0] + ai[2];
-        const double t1r = ar[0] - ar[2], t1i = ai[0] - ai[2];
-        const double t2r = ar[1] + ar[3], t2i = ai[1] + ai[3];
-        const double t3r = ar[1] - ar[3], t3i = ai[1] - ai[3];
-        const int base = (j - k) * 4 + k;
-        dr[(base << lb) + b] = t0r + t2r;
-        di[(base << lb) + b] = t0i + t2i;
-        dr[((base + 2 * Ns) << lb) + b] = t0r - t2r;
-        di[((base + 2 * Ns) << lb) + b] = t0i - t2i;
-        if (!INV) {  // X1 = t1 - i t3, X3 = t1 + i t3
-            dr[((base + Ns) << lb) + b] = t1r + t3i;
-            di[((base + Ns) << lb) + b] = t1i - t3r;
-            dr[((base + 3 * Ns) << lb) + b] = t1r - t3i;
-            di[((base + 3 * Ns) << lb) + b] = t1i + t3r;
-        } else {  // X1 = t1 + i t3, X3 = t1 - i t3
-            dr[((base + Ns) << lb) + b] = t1r - t3i;
-            di[((base + Ns) << lb) + b] = t1i + t3r;
-            dr[((base + 3 * Ns) << lb) + b] = t1r + t3i;
-            di[((base + 3 * Ns) << lb) + b] = t1i - t3r;
-        }
-    }
-}
-
-template <int M, bool INV>
-__device__ __forceinline__ void stage2(const double* __restrict__ sr, const double* __restrict__ si,
-                                       double* __restrict__ dr, double* __restrict__ di, int Ns, int lb,
-                                       const double* __restrict__ twr, const double* __restrict__ twi) {
-    constexpr int Q = M / 2;
-    const int B = 1 << lb;
-    const int total = Q << lb;
-    const int tstride = M / (Ns * 2);
-    for (int t = threadIdx.x; t < total; t += FFT_THREADS) {
-        const int b = t & (B - 1);
-        const int j = t >> lb;
-        const int k = j & (Ns - 1);
-        const double a0r = sr[(j << lb) + b], a0i = si[(j << lb) + b];
-        double a1r = sr[((j + Q) << lb) + b], a1i = si[((j + Q) << lb) + b];
-        if (k != 0) {
-            const int m = k * tstride;
-            const double wr = twr[m];
-            const double wi = INV ? -twi[m] : twi[m];
-            const double xr = a1r * wr - a1i * wi;
-            const double xi = a1r * wi + a1i * wr;
-            a1r = xr;
-            a1i = xi;
-        }
-        const int base = (j - k) * 2 + k;
-        dr[(base << lb) + b] = a0r + a1r;
-        di[(base << lb) + b] = a0i + a1i;
-        dr[((base + Ns) << lb) + b] = a0r - a1r;
-        di[((base + Ns) << lb) + b] = a0i - a1i;
-    }
-}
-
-// M-point transform of each column of the [M][B] tile in (sr, si); (dr, di)
-// is scratch. On return (sr, si) point at the result.
-template <int M, bool INV>
-__device__ __forceinline__ void fft_tile(double*& sr, double*& si, double*& dr, double*& di, int lb,
-                                         const double* twr, const double* twi) {
-    int Ns = 1;
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        if (Ns * 4 > M) break;
-        stage4<M, INV>(sr, si, dr, di, Ns, lb, twr, twi);
-        __syncthreads();
-        double* t = sr; sr = dr; dr = t;
-        t = si; si = di; di = t;
-        Ns *= 4;
-    }
-    if (Ns < M) {
-        stage2<M, INV>(sr, si, dr, di, Ns, lb, twr, twi);
-        __syncthreads();
-        double* t = sr; sr = dr; dr = t;
-        t = si; si = di; di = t;
-    }
-}
-
-template <int M>
-__device__ __forceinline__ void load_twiddles(double* twr, double* twi, const double2* __restrict__ tw) {
-    for (int m = threadIdx.x; m < M; m += FFT_THREADS) {
-        const double2 w = tw[m];
-        twr[m] = w.x;
-        twi[m] = w.y;
-    }
-}
-
-__device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
-
-// ---------------------------------------------------------------- pass 1
-template <int M, int NC>
-__global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_fwd(double* __restrict__ rho, double2* __restrict__ out,
-                                                              int nx, int rows, const double2* __restrict__ tw) {
-    constexpr int NCC = NC == 1 ? 1 : NC / 2;
-    constexpr int B = TILE / M;
-    constexpr int RB = B / NCC;
-    constexpr int LB = (B == 1) ? 0 : (B == 2) ? 1 : (B == 4) ? 2 : (B == 8) ? 3 : (B == 16) ? 4 : (B == 32) ? 5 : (B == 64) ? 6 : 7;
-    __shared__ double s0r[TILE], s0i[TILE], s1r[TILE], s1i[TILE], twr[M], twi[M];
-    load_twiddles<M>(twr, twi, tw);
-    for (int t = threadIdx.x; t < TILE; t += FFT_THREADS) {
-        s0r[t] = 0.0;
-        s0i[t] = 0.0;
-    }
-    __syncthreads();
-    const int row0 = blockIdx.x * RB;
-    const int per_row = nx * NC;
-    for (int t = threadIdx.x; t < RB * per_row; t += FFT_THREADS) {
-        const int r = t / per_row;
-        const int rem = t - r * per_row;
-        const int x = rem / NC;
-        const int ch = rem - x * NC;
-        const int row = row0 + r;
-        if (row < rows) {
-            const size_t gi = (size_t)row * per_row + rem;
-            const double v = rho[gi];
-            rho[gi] = 0.0;
-            const int col = r * NCC + (ch % NCC);
-            if (NC == 1 || ch < NCC)
-                s0r[x * B + col] = v;
-            else
-                s0i[x * B + col] = v;
-        }
-    }
-    __syncthreads();
-    double *sr = s0r, *si = s0i, *dr = s1r, *di = s1i;
-    fft_tile<M, false>(sr, si, dr, di, LB, twr, twi);
-    for (int t = threadIdx.x; t < RB * M * NCC; t += FFT_THREADS) {
-        const int r = t / (M * NCC);
-        const int rem = t - r * M * NCC;
-        const int kx = rem / NCC;
-        const int j = rem - kx * NCC;
-        const int row = row0 + r;
-        if (row < rows) out[(size_t)row * M * NCC + rem] = make_double2(sr[kx * B + r * NCC + j], si[kx * B + r * NCC + j]);
-    }
-}
-
-// ---------------------------------------------------------------- pass 5
-template <int M, int NC>
-__global__ __launch_bounds__(FFT_THREADS) void k_fft_rows_inv(const double2* __restrict__ in, double* __restrict__ phi,
-                                                              int nxo, int shift, int rows, const double2* __restrict__ tw) {
-    constexpr int NCC = NC == 1 ? 1 : NC / 2;
-    constexpr int B = TILE / M;
-    constexpr int RB = B / NCC;
-    constexpr int LB = (B == 1) ? 0 : (B == 2) ? 1 : (B == 4) ? 2 : (B == 8) ? 3 : (B == 16) ? 4 : (B == 32) ? 5 : (B == 64) ? 6 : 7;
-    __shared__ double s0r[TILE], s0i[TILE], s1r[TILE], s1i[TILE], twr[M], twi[M];
-    load_twiddles<M>(twr, twi, tw);
-    const int row0 = blockIdx.x * RB;
-    for (int t = threadIdx.x; t < RB * M * NCC; t += FFT_THREADS) {
-        const int r = t / (M * NCC);
-        const int rem = t - r * M * NCC;
-        const int kx = rem / NCC;
-        const int j = rem - kx * NCC;
-        const int row = row0 + r;
-        double2 v = make_double2(0.0, 0.0);
-        if (row < rows) v = in[(size_t)row * M * NCC + rem];
-        s0r[kx * B + r * NCC + j] = v.x;
-        s0i[kx * B + r * NCC + j] = v.y;
-    }
-    __syncthreads();
-    double *sr = s0r, *si = s0i, *dr = s1r, *di = s1i;
-    fft_tile<M, true>(sr, si, dr, di, LB, twr, twi);
-    const int per_row = nxo * NC;
-    for (int t = threadIdx.x; t < RB * per_row; t += FFT_THREADS) {
-        const int r = t / per_row;
-        const int rem = t - r * per_row;
-        const int xo = rem / NC;
-        const int ch = rem - xo * NC;
-        const int row = row0 + r;
-        if (row < rows) {
-            const int xs = (xo - shift + M) & (M - 1);  // output slot xo holds position xo - shift
-            const int col = r * NCC + (ch % NCC);
-            phi[(size_t)row * per_row + rem] = (NC == 1 || ch < NCC) ? sr[xs * B + col] : si[xs * B + col];
-        }
-    }
-}
 
 // ---------------------------------------------------------------- passes 2-4
 struct ColArgs {
@@ -338,7 +128,7 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_cols(const double2* __res
     using C = ColCfg<M>;
     constexpr int R1 = C::R1, R2 = C::R2, NG = C::NG, BC = C::BC;
     constexpr int GZ = M / 2 + 1;  // kz octant rows
-    __shared__ double er[M * BC], ei[M * BC], twr[M], twi[M];
+    __shared__ double ex[M * BC], twr[M], twi[M];  // exchange buffer: real parts, then imaginary parts
     for (int m = threadIdx.x; m < M; m += C::NT) {
         const double2 w = tw[m];
         twr[m] = w.x;
@@ -386,19 +176,20 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_cols(const double2* __res
 #pragma unroll
         for (int k1 = 1; k1 < R1; ++k1) twiddle<M, false>(xr[k1], xi[k1], r * k1, twr, twi);
 #pragma unroll
-        for (int k1 = 0; k1 < R1; ++k1) {
-            er[(k1 * R2 + r) * BC + b] = xr[k1];
-            ei[(k1 * R2 + r) * BC + b] = xi[k1];
-        }
+        for (int k1 = 0; k1 < R1; ++k1) ex[(k1 * R2 + r) * BC + b] = xr[k1];
+        __syncthreads();
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+#pragma unroll
+            for (int n2 = 0; n2 < R2; ++n2) hr[g][n2] = ex[((r + R2 * g) * R2 + n2) * BC + b];
+        __syncthreads();
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) ex[(k1 * R2 + r) * BC + b] = xi[k1];
         __syncthreads();
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
-            const int k1 = r + R2 * g;
 #pragma unroll
-            for (int n2 = 0; n2 < R2; ++n2) {
-                hr[g][n2] = er[(k1 * R2 + n2) * BC + b];
-                hi[g][n2] = ei[(k1 * R2 + n2) * BC + b];
-            }
+            for (int n2 = 0; n2 < R2; ++n2) hi[g][n2] = ex[((r + R2 * g) * R2 + n2) * BC + b];
             dft_reg<M, R2, false>(hr[g], hi[g], twr, twi);
         }
         if (MODE == 0) {
@@ -442,19 +233,22 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_cols(const double2* __res
         dft_reg<M, R2, true>(hr[g], hi[g], twr, twi);
 #pragma unroll
         for (int n2 = 0; n2 < R2; ++n2) {
-            double zr = hr[g][n2], zi = hi[g][n2];
-            twiddle<M, true>(zr, zi, n2 * k1, twr, twi);
-            er[(n2 * R1 + k1) * BC + b] = zr;
-            ei[(n2 * R1 + k1) * BC + b] = zi;
+            twiddle<M, true>(hr[g][n2], hi[g][n2], n2 * k1, twr, twi);
+            ex[(n2 * R1 + k1) * BC + b] = hr[g][n2];
         }
     }
     __syncthreads();
     double xr[R1], xi[R1];
 #pragma unroll
-    for (int k1 = 0; k1 < R1; ++k1) {
-        xr[k1] = er[(r * R1 + k1) * BC + b];
-        xi[k1] = ei[(r * R1 + k1) * BC + b];
-    }
+    for (int k1 = 0; k1 < R1; ++k1) xr[k1] = ex[(r * R1 + k1) * BC + b];
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) ex[(n2 * R1 + r + R2 * g) * BC + b] = hi[g][n2];
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) xi[k1] = ex[(r * R1 + k1) * BC + b];
     dft_reg<M, R1, true>(xr, xi, twr, twi);
 #pragma unroll
     for (int n1 = 0; n1 < R1; ++n1) {
@@ -462,6 +256,145 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_cols(const double2* __res
         if (valid && t < a.n_out) dst[(int64_t)t * a.out_stride] = make_double2(xr[n1], xi[n1]);
     }
 }
+
+// ---------------------------------------------------------------- passes 1 and 5
+// x transforms with the column kernels' stages: column b of a block is
+// complex channel j = b % NCC of row b / NCC; its value at x is the pair of
+// real channels (j, j + NCC) (the real channel alone when NC = 1).
+
+// pass 1: rho[row][x < nx][NC] -> out[row][kx < M][NCC], clearing rho
+template <int M, int NC>
+__global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_rows_fwd(double* __restrict__ rho, double2* __restrict__ out,
+                                                                int nx, int rows, const double2* __restrict__ tw) {
+    using C = ColCfg<M>;
+    constexpr int R1 = C::R1, R2 = C::R2, NG = C::NG, BC = C::BC;
+    constexpr int NCC = NC == 1 ? 1 : NC / 2;
+    static_assert(BC % NCC == 0, "whole rows per block");
+    __shared__ double ex[M * BC], twr[M], twi[M];  // exchange buffer: real parts, then imaginary parts
+    for (int m = threadIdx.x; m < M; m += C::NT) {
+        const double2 w = tw[m];
+        twr[m] = w.x;
+        twi[m] = w.y;
+    }
+    const int b = threadIdx.x % BC;
+    const int r = threadIdx.x / BC;
+    const int64_t row = (int64_t)blockIdx.x * (BC / NCC) + b / NCC;
+    const int j = b % NCC;
+    const bool valid = row < rows;
+    double* src = rho + row * nx * NC + j;
+    double xr[R1], xi[R1];
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) {
+        const int x = R2 * n1 + r;
+        xr[n1] = 0.0;
+        xi[n1] = 0.0;
+        if (valid && x < nx) {
+            xr[n1] = src[x * NC];
+            src[x * NC] = 0.0;
+            if (NC > 1) {
+                xi[n1] = src[x * NC + NCC];
+                src[x * NC + NCC] = 0.0;
+            }
+        }
+    }
+    __syncthreads();  // twiddle table
+    dft_reg<M, R1, false>(xr, xi, twr, twi);
+#pragma unroll
+    for (int k1 = 1; k1 < R1; ++k1) twiddle<M, false>(xr[k1], xi[k1], r * k1, twr, twi);
+    double hr[NG][R2], hi[NG][R2];
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) ex[(k1 * R2 + r) * BC + b] = xr[k1];
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) hr[g][n2] = ex[((r + R2 * g) * R2 + n2) * BC + b];
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) ex[(k1 * R2 + r) * BC + b] = xi[k1];
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) hi[g][n2] = ex[((r + R2 * g) * R2 + n2) * BC + b];
+        dft_reg<M, R2, false>(hr[g], hi[g], twr, twi);
+    }
+    if (!valid) return;
+    double2* dst = out + row * M * NCC + j;
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) dst[(r + R2 * g + R1 * k2) * NCC] = make_double2(hr[g][k2], hi[g][k2]);
+}
+
+// pass 5: in[row][kx < M][NCC] -> phi[row][xo < nxo][NC]; output slot xo
+// holds transform position xo - shift
+template <int M, int NC>
+__global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_rows_inv(const double2* __restrict__ in, double* __restrict__ phi,
+                                                                int nxo, int shift, int rows,
+                                                                const double2* __restrict__ tw) {
+    using C = ColCfg<M>;
+    constexpr int R1 = C::R1, R2 = C::R2, NG = C::NG, BC = C::BC;
+    constexpr int NCC = NC == 1 ? 1 : NC / 2;
+    static_assert(BC % NCC == 0, "whole rows per block");
+    __shared__ double ex[M * BC], twr[M], twi[M];
+    for (int m = threadIdx.x; m < M; m += C::NT) {
+        const double2 w = tw[m];
+        twr[m] = w.x;
+        twi[m] = w.y;
+    }
+    const int b = threadIdx.x % BC;
+    const int r = threadIdx.x / BC;
+    const int64_t row = (int64_t)blockIdx.x * (BC / NCC) + b / NCC;
+    const int j = b % NCC;
+    const bool valid = row < rows;
+    const double2* src = in + row * M * NCC + j;
+    double hr[NG][R2], hi[NG][R2];  // groups k1 = r + R2 g, values over k2
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) {
+            double2 v = make_double2(0.0, 0.0);
+            if (valid) v = src[(r + R2 * g + R1 * k2) * NCC];
+            hr[g][k2] = v.x;
+            hi[g][k2] = v.y;
+        }
+    __syncthreads();  // twiddle table
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        const int k1 = r + R2 * g;
+        dft_reg<M, R2, true>(hr[g], hi[g], twr, twi);
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) {
+            twiddle<M, true>(hr[g][n2], hi[g][n2], n2 * k1, twr, twi);
+            ex[(n2 * R1 + k1) * BC + b] = hr[g][n2];
+        }
+    }
+    __syncthreads();
+    double xr[R1], xi[R1];
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) xr[k1] = ex[(r * R1 + k1) * BC + b];
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) ex[(n2 * R1 + r + R2 * g) * BC + b] = hi[g][n2];
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) xi[k1] = ex[(r * R1 + k1) * BC + b];
+    dft_reg<M, R1, true>(xr, xi, twr, twi);
+    if (!valid) return;
+    double* dst = phi + row * nxo * NC + j;
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) {
+        const int xo = (r + R2 * n1 + shift) & (M - 1);
+        if (xo < nxo) {
+            dst[xo * NC] = xr[n1];
+            if (NC > 1) dst[xo * NC + NCC] = xi[n1];
+        }
+    }
+}
+
 
 template <int MODE>
 static hipError_t launch_cols(int M, int n_outer, int nb, const ColArgs& a, const double2* in, double2* out,
@@ -485,12 +418,12 @@ template <int NC>
 static hipError_t launch_rows_fwd_nc(int M, double* rho, double2* out, int nx, int rows, const double2* tw, hipStream_t s) {
     constexpr int NCC = NC == 1 ? 1 : NC / 2;
     switch (M) {
-#define DPIC_ROWS_FWD(MM)                                                                                       \
-    case MM: {                                                                                                  \
-        constexpr int RB = (TILE / MM) / NCC;                                                                   \
-        hipLaunchKernelGGL((k_fft_rows_fwd<MM, NC>), dim3((rows + RB - 1) / RB), dim3(FFT_THREADS), 0, s, rho, \
-                           out, nx, rows, tw);                                                                  \
-        break;                                                                                                  \
+#define DPIC_ROWS_FWD(MM)                                                                                        \
+    case MM: {                                                                                                   \
+        constexpr int RB = ColCfg<MM>::BC / NCC;                                                                 \
+        hipLaunchKernelGGL((k_fft_rows_fwd<MM, NC>), dim3((rows + RB - 1) / RB), dim3(ColCfg<MM>::NT), 0, s, rho, \
+                           out, nx, rows, tw);                                                                   \
+        break;                                                                                                   \
     }
         DPIC_ROWS_FWD(16) DPIC_ROWS_FWD(32) DPIC_ROWS_FWD(64) DPIC_ROWS_FWD(128)
 #undef DPIC_ROWS_FWD
@@ -504,12 +437,12 @@ static hipError_t launch_rows_inv_nc(int M, const double2* in, double* phi, int 
                                      const double2* tw, hipStream_t s) {
     constexpr int NCC = NC == 1 ? 1 : NC / 2;
     switch (M) {
-#define DPIC_ROWS_INV(MM)                                                                                      \
-    case MM: {                                                                                                 \
-        constexpr int RB = (TILE / MM) / NCC;                                                                  \
-        hipLaunchKernelGGL((k_fft_rows_inv<MM, NC>), dim3((rows + RB - 1) / RB), dim3(FFT_THREADS), 0, s, in, \
-                           phi, nxo, shift, rows, tw);                                                         \
-        break;                                                                                                 \
+#define DPIC_ROWS_INV(MM)                                                                                       \
+    case MM: {                                                                                                  \
+        constexpr int RB = ColCfg<MM>::BC / NCC;                                                                \
+        hipLaunchKernelGGL((k_fft_rows_inv<MM, NC>), dim3((rows + RB - 1) / RB), dim3(ColCfg<MM>::NT), 0, s, in, \
+                           phi, nxo, shift, rows, tw);                                                          \
+        break;                                                                                                  \
     }
         DPIC_ROWS_INV(16) DPIC_ROWS_INV(32) DPIC_ROWS_INV(64) DPIC_ROWS_INV(128)
 #undef DPIC_ROWS_INV
