@@ -220,7 +220,8 @@ int dpic_load_state(dpic_ctx* ctx, const void* dev_buf);
 
 /*
  * Options:
- *  DPIC_OPT_SORT_EVERY = re-sort particles by grid tile every k steps (0 = never);
+ *  DPIC_OPT_SORT_EVERY = re-sort particles by grid tile every k steps (0 = never,
+ *    default 12);
  *  DPIC_OPT_STAGE_TIMING = 1 records HIP events around every stage launch of
  *    dpic_step, 2 around the particle stage only (fewer event records in the
  *    stream: each leaves the GPU idle for a few microseconds); read with

@@ -1015,7 +1015,7 @@ int dpic_autotune(dpic_ctx* c, void* scratch, size_t scratch_bytes, int trial_st
             pb = v;
         }
     }
-    for (int64_t v : {5, 10, 20, 40}) {
+    for (int64_t v : {5, 10, 12, 20, 40}) {
         if (r != DPIC_OK || v == se) continue;
         if ((r = trial(v, ch, pb, &t)) == DPIC_OK && t < bms) {
             bms = t;
