@@ -68,13 +68,13 @@ struct Workspace {
 constexpr int MOM_BLOCKS = 512;
 constexpr int NUM_TILE_BINS_MAX = 4096;
 constexpr int TILE_EDGE = 4;                             // cells per tile edge
-// LDS tiles of a work item: the tile's cells plus a drift allowance on both
-// sides, one cell transversely and none longitudinally (per step a particle
-// moves about 1/200 of a cell in x and y but 1/1000 in z)
-constexpr int TILE_HALO = 1;                             // drift allowance (cells) in x and y
-constexpr int TILE_HALO_Z = 0;                           // and in z
-constexpr int TILE_R = TILE_EDGE + 2 * TILE_HALO + 1;    // LDS nodes in x and y
-constexpr int TILE_RZ = TILE_EDGE + 2 * TILE_HALO_Z + 1; // LDS nodes in z
+// LDS tiles of a work item: its tile's cells plus a drift allowance of one
+// cell on each side for the deposit tile; the E tile (three components per
+// node) has it at most in x and y, where particles drift most between
+// re-sorts (per step about 1/200 of a cell transversely, 1/1000 in z).
+constexpr int TILE_HALO = 1;                             // drift allowance (cells)
+constexpr int TILE_R = TILE_EDGE + 2 * TILE_HALO + 1;    // deposit tile nodes per dimension
+constexpr int TILE_RZ_E = TILE_EDGE + 1;                 // E tile nodes in z
 constexpr int TILE_CHUNK = 1024;                         // default particles per tiled work item
 constexpr int CHUNK_MIN = 128;                           // smallest work item (sizes the work list)
 constexpr int CHUNK_MAX = 8192;

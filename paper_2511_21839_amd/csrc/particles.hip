@@ -365,22 +365,77 @@ struct TiledArgs {
     int tx, ty, nbins;
 };
 
-// LDS tiles of a work item: the nodes [o, o + TILE_R) x [.., + TILE_R) x
-// [.., + TILE_RZ) around its grid tile. The deposit copy is channel-major
-// with a channel stride of 1 mod 16 doubles, so channel c of node n sits in
-// bank pair (c + n) mod 16: the lanes of a group (channels k, k+K, ..) and
-// particles at different nodes spread over the banks. The E copy covers the
-// same nodes, so a particle gathers from LDS exactly when it deposits there.
-constexpr int TILE_NODES = TILE_R * TILE_R * TILE_RZ;
-// The E tile is staged only where it leaves room for two workgroups per
-// CU: at 16 channels it and the deposit tile would take 122 KB.
+// LDS copy of the deposit tile: the nodes [o, o + TILE_R)^2 x [oz, oz +
+// dep_rz) around the grid tile, channel-major with a channel stride of 1 mod
+// 16 doubles, so channel c of node n sits in bank pair (c + n) mod 16: the
+// lanes of a group (channels k, k+K, ..) and particles at different nodes
+// spread over the banks. It has the drift allowance in z only without
+// PF_EHALO: with the fields in the caches, the few particles that cross a z
+// face deposit by global atomics at no measurable cost, and the smaller tile
+// is cheaper to clear and flush; with the fields (and charges) streaming from
+// HBM those atomics cost more than the larger tile.
+template <int F>
+constexpr int dep_rz() {
+    return (F & PF_EHALO) ? TILE_EDGE + 1 : TILE_R;
+}
+template <int F>
+constexpr int dep_offz() {
+    return (F & PF_EHALO) ? 0 : TILE_HALO;
+}
+template <int F>
+constexpr int dep_nodes() {
+    return TILE_R * TILE_R * dep_rz<F>();
+}
+template <int F>
+constexpr int dep_cstride() {
+    return ((dep_nodes<F>() + 15) / 16) * 16 + 1;
+}
+// LDS copy of E: the nodes [o + EO, o + EO + ER)^2 x [tile z, + TILE_RZ_E),
+// [node][component] duals in the split layout. With PF_EHALO it has
+// the transverse drift allowance (ER = TILE_R nodes, EO = 0), else it covers
+// the tile's own nodes (ER = TILE_EDGE + 1, EO = TILE_HALO). The allowance
+// keeps drifted particles on the LDS path, but each item stages twice the
+// nodes: it pays while the fields of all settings stay in the caches (one
+// beam of 1e6 particles on 64^3 nodes: 2% faster) and not once they stream
+// from HBM (64 beams of 1e5-1e6 particles: 7% slower).
+// The E tile is staged only where it leaves room for two workgroups per CU:
+// at 16 channels it and the deposit tile would take 122 KB.
+template <int F>
+constexpr int etile_r() {
+    return (F & PF_EHALO) ? TILE_R : TILE_EDGE + 1;
+}
+template <int F>
+constexpr int etile_off() {
+    return (F & PF_EHALO) ? 0 : TILE_HALO;
+}
+template <int F>
+constexpr int etile_nodes() {
+    return etile_r<F>() * etile_r<F>() * TILE_RZ_E;
+}
 template <int NC, int F>
 constexpr bool use_etile() {
     return (F & PF_KICK) && NC <= 8;
 }
-constexpr int TILE_CSTRIDE = ((TILE_NODES + 15) / 16) * 16 + 1;
 constexpr int PART_THREADS = 256;
 constexpr int STAGE_BATCH = 8;  // E-tile staging loads in flight per thread
+constexpr double EHALO_MAX_BYTES = 128.0 * (1 << 20);  // fields of all settings, for PF_EHALO
+
+// Wavefront max of the extents (all 64 lanes take part), one atomic per
+// wave and dimension, nothing waited for: for a workgroup that moves on to
+// another setting's items (each setting has its own counters).
+__device__ __forceinline__ void extent_flush_wave(unsigned long long* cnt, double e0, double e1, double e2) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        e0 = fmax(e0, __shfl_xor(e0, off, 64));
+        e1 = fmax(e1, __shfl_xor(e1, off, 64));
+        e2 = fmax(e2, __shfl_xor(e2, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(cnt + CNT_EXT_X, (unsigned long long)__double_as_longlong(e0));
+        atomicMax(cnt + CNT_EXT_Y, (unsigned long long)__double_as_longlong(e1));
+        atomicMax(cnt + CNT_EXT_Z, (unsigned long long)__double_as_longlong(e2));
+    }
+}
 
 // Workgroup max of the extents (every thread of the workgroup calls it),
 // merged into the setting's counters by one thread, with an atomic only
@@ -488,7 +543,7 @@ template <int NC, int F, bool TILED>
 __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& sv, const double* __restrict__ smap,
                                               const double* __restrict__ stau, int64_t p, int q,
                                               const RawState<LaneGroup<NC>::K>& raw, double* lr, const double* le, int ox,
-                                              int oy, int oz, bool use_tile, double& e0, double& e1, double& e2) {
+                                              int oy, int oz, int oze, bool use_tile, double& e0, double& e1, double& e2) {
     constexpr int G = LaneGroup<NC>::G, K = LaneGroup<NC>::K;
     const int64_t cs = a.cap * NC;
     double* sp = a.st + p * NC;
@@ -501,11 +556,12 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& 
             const QD<K> fx = qd_frac(x, g.sx, g.ix, a.ih0), fy = qd_frac(y, g.sy, g.iy, a.ih1),
                         fz = qd_frac(z, g.sz, g.iz, a.ih2);
             QD<K> ex = qd_zero<K>(), ey = qd_zero<K>(), ez = qd_zero<K>();
-            const int tlx = g.ix - ox, tly = g.iy - oy, tlz = g.iz - oz;
-            const bool in_etile = TILED && use_etile<NC, F>() && use_tile && tlx >= 0 && tlx <= TILE_R - 2 &&
-                                  tly >= 0 && tly <= TILE_R - 2 && tlz >= 0 && tlz <= TILE_RZ - 2;
+            constexpr int ER = etile_r<F>();
+            const int tlx = g.ix - ox - etile_off<F>(), tly = g.iy - oy - etile_off<F>(), tlz = g.iz - oze;
+            const bool in_etile = TILED && use_etile<NC, F>() && use_tile && tlx >= 0 && tlx <= ER - 2 &&
+                                  tly >= 0 && tly <= ER - 2 && tlz >= 0 && tlz <= TILE_RZ_E - 2;
             if (in_etile) {
-                const int l0 = (tlz * TILE_R + tly) * TILE_R + tlx;
+                const int l0 = (tlz * ER + tly) * ER + tlx;
 #pragma unroll
                 for (int kz = 0; kz < 2; ++kz) {
 #pragma unroll
@@ -515,7 +571,7 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& 
                         for (int kx = 0; kx < 2; ++kx) {
                             const QD<K> w = qd_mul(kx ? fx : qd_one_minus(fx), wyz);
                             constexpr int D = lds_dual<NC>();
-                            const double* ep = le + (l0 + kx + ky * TILE_R + kz * TILE_R * TILE_R) * 3 * D;
+                            const double* ep = le + (l0 + kx + ky * ER + kz * ER * ER) * 3 * D;
                             qd_fmad(w, qd_load_split<NC>(ep, q), ex);
                             qd_fmad(w, qd_load_split<NC>(ep + D, q), ey);
                             qd_fmad(w, qd_load_split<NC>(ep + 2 * D, q), ez);
@@ -574,7 +630,7 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& 
                             fz = qd_frac(z, g.sz, g.iz, a.ih2);
                 const int lx = g.ix - ox, ly = g.iy - oy, lz = g.iz - oz;
                 const bool local = TILED && use_tile && lx >= 0 && lx <= TILE_R - 2 && ly >= 0 &&
-                                   ly <= TILE_R - 2 && lz >= 0 && lz <= TILE_RZ - 2;
+                                   ly <= TILE_R - 2 && lz >= 0 && lz <= dep_rz<F>() - 2;
                 if (TILED && local) {
                     const int l0 = (lz * TILE_R + ly) * TILE_R + lx;
 #pragma unroll
@@ -585,10 +641,11 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& 
 #pragma unroll
                             for (int kx = 0; kx < 2; ++kx) {
                                 const QD<K> w = qd_mul(kx ? fx : qd_one_minus(fx), wyz);
-                                double* l = lr + (q * K) * TILE_CSTRIDE + l0 + kx + ky * TILE_R + kz * TILE_R * TILE_R;
+                                constexpr int CS = dep_cstride<F>();
+                                double* l = lr + (q * K) * CS + l0 + kx + ky * TILE_R + kz * TILE_R * TILE_R;
 #pragma unroll
                                 for (int k = 0; k < K; ++k)
-                                    unsafeAtomicAdd(l + k * TILE_CSTRIDE, qd_chan(w, q, k) * sv.q);
+                                    unsafeAtomicAdd(l + k * CS, qd_chan(w, q, k) * sv.q);
                             }
                         }
                     }
@@ -654,7 +711,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles(PartArgs a) {
     double e0 = 0.0, e1 = 0.0, e2 = 0.0;
     if (p - sd.off < sd.n) {
         const RawState<LaneGroup<NC>::K> raw = load_raw<NC>(a, p, q);
-        particle_body<NC, F, false>(a, sv, smap, stau, p, q, raw, nullptr, nullptr, 0, 0, 0, false, e0, e1, e2);
+        particle_body<NC, F, false>(a, sv, smap, stau, p, q, raw, nullptr, nullptr, 0, 0, 0, 0, false, e0, e1, e2);
     }
     if (F & (PF_DEPOSIT | PF_COUNT)) extent_flush(sv.cnt, e0, e1, e2, sext);
 }
@@ -667,8 +724,8 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles(PartArgs a) {
 template <int NC, int F>
 __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, TiledArgs t) {
     constexpr int G = LaneGroup<NC>::G;
-    constexpr int LDSN = (F & PF_DEPOSIT) ? TILE_CSTRIDE * NC : 1;
-    constexpr int LDSE = use_etile<NC, F>() ? TILE_NODES * 3 * lds_dual<NC>() : 1;
+    constexpr int LDSN = (F & PF_DEPOSIT) ? dep_cstride<F>() * NC : 1;
+    constexpr int LDSE = use_etile<NC, F>() ? etile_nodes<F>() * 3 * lds_dual<NC>() : 1;
     __shared__ __align__(16) double lr[LDSN];
     __shared__ __align__(16) double le[LDSE];
     __shared__ __align__(16) double smap[MB_N * lds_dual<NC>()];
@@ -687,7 +744,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
         if (ci != blockIdx.x) __syncthreads();  // the previous item's flush is done with lr and smap
         if (ck.w != cur) {
             if ((F & (PF_DEPOSIT | PF_COUNT)) && cur >= 0) {
-                extent_flush(sv.cnt, e0, e1, e2, sext);
+                extent_flush_wave(sv.cnt, e0, e1, e2);
                 e0 = e1 = e2 = 0.0;
             }
             cur = ck.w;
@@ -699,12 +756,14 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
             for (int j = threadIdx.x; j < LDSN; j += PART_THREADS) lr[j] = 0.0;
         const bool use_tile = ck.x < t.nbins - 1;
         const int tx = ck.x % t.tx, ty = (ck.x / t.tx) % t.ty, tz = ck.x / (t.tx * t.ty);
-        const int ox = tx * TILE_EDGE - TILE_HALO, oy = ty * TILE_EDGE - TILE_HALO, oz = tz * TILE_EDGE - TILE_HALO_Z;
+        const int ox = tx * TILE_EDGE - TILE_HALO, oy = ty * TILE_EDGE - TILE_HALO, oz = tz * TILE_EDGE - dep_offz<F>();
+        const int oze = tz * TILE_EDGE;  // E tile: no allowance in z
         if (use_etile<NC, F>() && use_tile) {
             // E of the tile's nodes (runs of TILE_R nodes x 3 x NC doubles
             // along x in global memory) into the split layout, SB loads in
             // flight per thread before their LDS writes
-            constexpr int SN = TILE_NODES * 3 * NC, SB = STAGE_BATCH;
+            constexpr int ER = etile_r<F>(), EN = etile_nodes<F>();
+            constexpr int SN = EN * 3 * NC, SB = STAGE_BATCH;
 #pragma unroll 1
             for (int j0 = 0; j0 < SN; j0 += SB * PART_THREADS) {
                 double v[SB];
@@ -712,8 +771,8 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
                 for (int k = 0; k < SB; ++k) {
                     const int j = j0 + threadIdx.x + k * PART_THREADS;
                     const int node = j / (3 * NC), r = j - node * (3 * NC);
-                    const int lx = node % TILE_R, ly = (node / TILE_R) % TILE_R, lz = node / (TILE_R * TILE_R);
-                    const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+                    const int lx = node % ER, ly = (node / ER) % ER, lz = node / (ER * ER);
+                    const int gx = ox + etile_off<F>() + lx, gy = oy + etile_off<F>() + ly, gz = oze + lz;
                     v[k] = (j < SN && gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz)
                                ? sv.E[(((int64_t)gz * a.ny + gy) * a.nx + gx) * 3 * NC + r]
                                : 0.0;
@@ -730,14 +789,14 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
         {
             // software pipeline: a thread's loads for its next particle are
             // issued before the current one is processed (two iterations deep
-            // measured 18% slower at the c2 size)
+            // measured 18% slower with 1e6 particles on 64^3 nodes)
             RawState<LaneGroup<NC>::K> next;
             if (i0 < ck.z) next = load_raw<NC>(a, (int64_t)ck.y + i0, q);
 #pragma unroll 1
             for (int i = i0; i < ck.z; i += STRIDE) {
                 const RawState<LaneGroup<NC>::K> curst = next;
                 if (i + STRIDE < ck.z) next = load_raw<NC>(a, (int64_t)ck.y + i + STRIDE, q);
-                particle_body<NC, F, true>(a, sv, smap, stau, (int64_t)ck.y + i, q, curst, lr, le, ox, oy, oz, use_tile,
+                particle_body<NC, F, true>(a, sv, smap, stau, (int64_t)ck.y + i, q, curst, lr, le, ox, oy, oz, oze, use_tile,
                                            e0, e1, e2);
             }
         }
@@ -746,12 +805,13 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
             // node-major walk (NC consecutive lanes write one node's channels),
             // started at an item-dependent node so that items of the same tile
             // flushing at the same time hit different addresses
-            const int rot = (int)((ci * 61u) % TILE_NODES);
-            for (int j = threadIdx.x; j < TILE_NODES * NC; j += PART_THREADS) {
+            constexpr int DN = dep_nodes<F>(), CS = dep_cstride<F>();
+            const int rot = (int)((ci * 61u) % DN);
+            for (int j = threadIdx.x; j < DN * NC; j += PART_THREADS) {
                 const int ch = j % NC;
                 int node = j / NC + rot;
-                node -= node >= TILE_NODES ? TILE_NODES : 0;
-                const double v = lr[ch * TILE_CSTRIDE + node];
+                node -= node >= DN ? DN : 0;
+                const double v = lr[ch * CS + node];
                 if (v != 0.0) {
                     const int lx = node % TILE_R, ly = (node / TILE_R) % TILE_R, lz = node / (TILE_R * TILE_R);
                     const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
@@ -787,6 +847,8 @@ static int resident_nc(int flags) {
         case PF_KICK | PF_MAP: return tiled_occupancy<NC, PF_KICK | PF_MAP>();
         case PF_MAP | PF_COUNT: return tiled_occupancy<NC, PF_MAP | PF_COUNT>();
         case PF_MAP: return tiled_occupancy<NC, PF_MAP>();
+        case PF_KICK | PF_MAP | PF_DEPOSIT | PF_EHALO: return tiled_occupancy<NC, PF_KICK | PF_MAP | PF_DEPOSIT | PF_EHALO>();
+        case PF_KICK | PF_MAP | PF_EHALO: return tiled_occupancy<NC, PF_KICK | PF_MAP | PF_EHALO>();
         default: return tiled_occupancy<NC, PF_DEPOSIT>();
     }
 }
@@ -796,8 +858,8 @@ static int resident_nc(int flags) {
 // of this channel count (so that no query happens during graph capture).
 int particle_resident_blocks(dpic_ctx* cx) {
     int r = 0;
-    const int all[6] = {PF_MAP | PF_DEPOSIT, PF_KICK | PF_MAP | PF_DEPOSIT, PF_KICK | PF_MAP, PF_MAP | PF_COUNT,
-                        PF_MAP, PF_DEPOSIT};
+    const int all[8] = {PF_MAP | PF_DEPOSIT, PF_KICK | PF_MAP | PF_DEPOSIT, PF_KICK | PF_MAP, PF_MAP | PF_COUNT,
+                        PF_MAP, PF_DEPOSIT, PF_KICK | PF_MAP | PF_DEPOSIT | PF_EHALO, PF_KICK | PF_MAP | PF_EHALO};
     for (int f : all) {
         const int v = cx->NC == 1 ? resident_nc<1>(f) : (cx->NC == 8 ? resident_nc<8>(f) : resident_nc<16>(f));
         if (f == (PF_KICK | PF_MAP | PF_DEPOSIT)) r = v;
@@ -835,6 +897,14 @@ static hipError_t launch_particles_nc(dpic_ctx* cx, int flags, const PartArgs& a
         case PF_MAP | PF_COUNT: launch_one<NC, PF_MAP | PF_COUNT, TL>(cx, a, t, max_items); break;
         case PF_MAP: launch_one<NC, PF_MAP, TL>(cx, a, t, max_items); break;
         case PF_DEPOSIT: launch_one<NC, PF_DEPOSIT, TL>(cx, a, t, max_items); break;
+        case PF_KICK | PF_MAP | PF_DEPOSIT | PF_EHALO:
+            if constexpr (!TL) return hipErrorInvalidValue;
+            launch_one<NC, PF_KICK | PF_MAP | PF_DEPOSIT | PF_EHALO, TL>(cx, a, t, max_items);
+            break;
+        case PF_KICK | PF_MAP | PF_EHALO:
+            if constexpr (!TL) return hipErrorInvalidValue;
+            launch_one<NC, PF_KICK | PF_MAP | PF_EHALO, TL>(cx, a, t, max_items);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -872,6 +942,10 @@ hipError_t launch_particles(dpic_ctx* cx, int flags, int e_tau, int map_off, boo
         t.nbins = nbins;
         items = max_chunks(cx);
     }
+    // the E tile with the drift allowance while the fields of all settings
+    // fit in the caches
+    const double ebytes = (double)cx->B * cx->dims.nx * cx->dims.ny * cx->dims.nz * 3.0 * cx->NC * sizeof(double);
+    if (tiled && (flags & PF_KICK) && ebytes <= EHALO_MAX_BYTES) flags |= PF_EHALO;
     switch (cx->NC) {
         case 1: return tiled ? launch_particles_nc<1, true>(cx, flags, a, t, items) : launch_particles_nc<1, false>(cx, flags, a, t, items);
         case 8: return tiled ? launch_particles_nc<8, true>(cx, flags, a, t, items) : launch_particles_nc<8, false>(cx, flags, a, t, items);
