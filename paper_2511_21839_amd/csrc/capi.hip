@@ -91,9 +91,12 @@ struct StageTimer {
 };
 
 
-int run_particles(dpic_ctx* c, int flags, int e_tau, int map_off) {
+// keys: the launch also writes the tile keys of the positions it deposits
+// at, for the sort that follows it.
+int run_particles(dpic_ctx* c, int flags, int e_tau, int map_off, bool keys = false) {
     StageTimer tm(c, T_PART);
-    HIPCHK(c, launch_particles(c, flags, e_tau, map_off, c->sort_every > 0 && c->chunks_valid));
+    HIPCHK(c, launch_particles(c, flags, e_tau, map_off, c->sort_every > 0 && c->chunks_valid, keys));
+    c->keys_ready = keys;
     return DPIC_OK;
 }
 
@@ -263,6 +266,7 @@ int step_body(dpic_ctx* c, int n) {
     const int64_t s0 = c->steps_done, s1 = s0 + n;
     const size_t rho_n = grid_nodes(c) * c->NC * c->B;
     int r;
+    c->keys_ready = false;
     if (sc && c->sort_every > 0 && !c->chunks_valid)
         if ((r = run_sort(c)) != DPIC_OK) return r;
     if (c->adj.bound) {
@@ -288,8 +292,9 @@ int step_body(dpic_ctx* c, int n) {
             if ((r = run_solve_field(c)) != DPIC_OK) return r;
             const bool last = (s == s1 - 1);
             const int flags = PF_KICK | PF_MAP | (last ? 0 : PF_DEPOSIT);
-            if ((r = run_particles(c, flags, c->schedule[s], closing_map(c, s, last))) != DPIC_OK) return r;
-            if (c->sort_every > 0 && !last && ((s + 1) % c->sort_every) == 0)
+            const bool sort_next = c->sort_every > 0 && !last && ((s + 1) % c->sort_every) == 0;
+            if ((r = run_particles(c, flags, c->schedule[s], closing_map(c, s, last), sort_next)) != DPIC_OK) return r;
+            if (sort_next)
                 if ((r = run_sort(c)) != DPIC_OK) return r;
         }
     } else {

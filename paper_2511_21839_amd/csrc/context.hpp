@@ -170,6 +170,7 @@ struct dpic_ctx {
     int64_t chunk = dpic::TILE_CHUNK;  // particles per tiled work item
     int64_t part_blocks = 0;           // workgroups of the tiled particle kernel (0: resident capacity)
     bool chunks_valid = false;  // the tiled work list matches the stored order
+    bool keys_ready = false;    // ws.key holds every particle's tile key (written by the last particle launch)
     int stage_timing = 0;  // 0 off, 1 every stage, 2 the particle stage only
     bool use_graph = false;
     int cu_count = 0;
@@ -198,7 +199,7 @@ hipError_t launch_element_consts_into(dpic_ctx* c, int NC, int nb, const double*
 hipError_t launch_init_beam(dpic_ctx* c, const double* xi);
 // flags: PF_*; e_tau: element whose step size the kick uses; map_off: map
 // block to apply (ec_offset) when PF_MAP is set.
-hipError_t launch_particles(dpic_ctx* c, int flags, int e_tau, int map_off, bool tiled);
+hipError_t launch_particles(dpic_ctx* c, int flags, int e_tau, int map_off, bool tiled, bool write_keys = false);
 hipError_t launch_canonical_state(dpic_ctx* c);  // st -> st2 in packed original order
 int particle_resident_blocks(dpic_ctx* c);       // resident tiled-kernel workgroups on the device
 hipError_t launch_zero(dpic_ctx* c, double* p, size_t n);

@@ -347,6 +347,8 @@ struct PartArgs {
     int nx, ny, nz;
     double lo0, lo1, lo2, ih0, ih1, ih2;
     double kperp, kpar;
+    uint32_t* key_out;      // PF_KEYS: each particle's tile key for the next sort
+    int ktx, kty, knbins;   // tiles in x and y, sort bins (the last one: outside the box)
 };
 
 // the arrays and charge of one setting
@@ -624,6 +626,11 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& 
     }
     if (F & (PF_DEPOSIT | PF_COUNT)) {
         const CellPos g = cell_of(x.v, y.v, z.v, a);
+        // the sort's key of this position (the sort that follows reads it
+        // instead of the positions)
+        if ((F & PF_KEYS) && q == 0)
+            a.key_out[p] = g.inside ? (uint32_t)(((g.iz / TILE_EDGE) * a.kty + g.iy / TILE_EDGE) * a.ktx + g.ix / TILE_EDGE)
+                                    : (uint32_t)(a.knbins - 1);
         if (g.inside) {
             if (F & PF_DEPOSIT) {
                 const QD<K> fx = qd_frac(x, g.sx, g.ix, a.ih0), fy = qd_frac(y, g.sy, g.iy, a.ih1),
@@ -905,12 +912,19 @@ static hipError_t launch_particles_nc(dpic_ctx* cx, int flags, const PartArgs& a
             if constexpr (!TL) return hipErrorInvalidValue;
             launch_one<NC, PF_KICK | PF_MAP | PF_EHALO, TL>(cx, a, t, max_items);
             break;
+        case PF_KICK | PF_MAP | PF_DEPOSIT | PF_KEYS:
+            launch_one<NC, PF_KICK | PF_MAP | PF_DEPOSIT | PF_KEYS, TL>(cx, a, t, max_items);
+            break;
+        case PF_KICK | PF_MAP | PF_DEPOSIT | PF_EHALO | PF_KEYS:
+            if constexpr (!TL) return hipErrorInvalidValue;
+            launch_one<NC, PF_KICK | PF_MAP | PF_DEPOSIT | PF_EHALO | PF_KEYS, TL>(cx, a, t, max_items);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_particles(dpic_ctx* cx, int flags, int e_tau, int map_off, bool tiled) {
+hipError_t launch_particles(dpic_ctx* cx, int flags, int e_tau, int map_off, bool tiled, bool write_keys) {
     PartArgs a;
     a.st = cx->ws.st;
     a.cap = cx->dims.n_particles;
@@ -930,6 +944,17 @@ hipError_t launch_particles(dpic_ctx* cx, int flags, int e_tau, int map_off, boo
     a.ih2 = 1.0 / cx->h[2];
     a.kperp = cx->kperp;
     a.kpar = cx->kpar;
+    a.key_out = nullptr;
+    a.ktx = a.kty = a.knbins = 0;
+    if (write_keys && (flags & PF_DEPOSIT)) {
+        int tk[3], nb = 0;
+        if (!sort_geometry(cx, tk, &nb)) return hipErrorInvalidValue;
+        a.key_out = cx->ws.key;
+        a.ktx = tk[0];
+        a.kty = tk[1];
+        a.knbins = nb;
+        flags |= PF_KEYS;
+    }
     TiledArgs t{};
     size_t items = 0;
     if (tiled) {

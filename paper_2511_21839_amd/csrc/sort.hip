@@ -70,7 +70,9 @@ __device__ __forceinline__ SegInfo seg_info(const SettingDev* set, const int32_t
     return r;
 }
 
-template <int NC>
+// FROM_KEYS: the keys were written by the particle launch that produced
+// these positions; only the histogram is built.
+template <int NC, bool FROM_KEYS>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_count(const double* __restrict__ st, int64_t cap,
                                                              const SettingDev* __restrict__ set,
                                                              const int32_t* __restrict__ owner, SortGeom g,
@@ -83,8 +85,13 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_count(const double* __res
     for (int i = threadIdx.x; i < SORT_PB; i += SORT_THREADS) {
         const int64_t p = si.lo + i;
         if (p < si.hi) {
-            const uint32_t k = tile_key(st[p * NC], st[2 * cs + p * NC], st[4 * cs + p * NC], g);
-            key[p] = k;
+            uint32_t k;
+            if (FROM_KEYS) {
+                k = key[p];
+            } else {
+                k = tile_key(st[p * NC], st[2 * cs + p * NC], st[4 * cs + p * NC], g);
+                key[p] = k;
+            }
             atomicAdd(&h[k], 1u);
         }
     }
@@ -277,10 +284,15 @@ hipError_t launch_sort(dpic_ctx* cx) {
     const int64_t m = (int64_t)g.nbins * nsegs;
     const int nscan = (int)((m + SCAN_SEG - 1) / SCAN_SEG);
     if (nsegs > 0) {
-        switch (cx->NC) {
-            case 1: hipLaunchKernelGGL(k_sort_count<1>, dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, w.counts); break;
-            case 8: hipLaunchKernelGGL(k_sort_count<8>, dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, w.counts); break;
-            default: hipLaunchKernelGGL(k_sort_count<16>, dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, w.counts); break;
+        if (cx->keys_ready) {
+            hipLaunchKernelGGL((k_sort_count<1, true>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key,
+                               w.counts);
+        } else {
+            switch (cx->NC) {
+                case 1: hipLaunchKernelGGL((k_sort_count<1, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, w.counts); break;
+                case 8: hipLaunchKernelGGL((k_sort_count<8, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, w.counts); break;
+                default: hipLaunchKernelGGL((k_sort_count<16, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, w.counts); break;
+            }
         }
         hipLaunchKernelGGL(k_scan_seg_sums, dim3(nscan), dim3(1024), 0, s, w.counts, m, w.seg);
         hipLaunchKernelGGL(k_scan_seg_offsets, dim3(1), dim3(1024), 0, s, w.seg, nscan);
@@ -301,6 +313,7 @@ hipError_t launch_sort(dpic_ctx* cx) {
         cx->swapped = !cx->swapped;
     }
     cx->chunks_valid = true;
+    cx->keys_ready = false;
     return hipSuccess;
 }
 
