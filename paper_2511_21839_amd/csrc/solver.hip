@@ -61,7 +61,7 @@ struct ColCfg {
     static constexpr int R1 = M >= 128 ? 16 : (M >= 32 ? 8 : 4);
     static constexpr int R2 = M / R1;
     static constexpr int NG = R1 / R2;    // stage-B groups per thread
-    static constexpr int BC = 2048 / M;   // columns per block
+    static constexpr int BC = (M >= 128 ? 4096 : 2048) / M;   // columns per block
     static constexpr int NT = BC * R2;    // threads per block
 };
 
