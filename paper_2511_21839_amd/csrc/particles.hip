@@ -364,6 +364,8 @@ __device__ __forceinline__ SetView set_view(const SettingDev& sd) { return SetVi
 struct TiledArgs {
     const int4* chunks;
     const uint32_t* nchunks;
+    const double* E0;  // field of setting b at E0 + b * estride
+    int64_t estride;
     int tx, ty, nbins;
 };
 
@@ -765,7 +767,13 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
         const int tx = ck.x % t.tx, ty = (ck.x / t.tx) % t.ty, tz = ck.x / (t.tx * t.ty);
         const int ox = tx * TILE_EDGE - TILE_HALO, oy = ty * TILE_EDGE - TILE_HALO, oz = tz * TILE_EDGE - dep_offz<F>();
         const int oze = tz * TILE_EDGE;  // E tile: no allowance in z
+        // first particle's loads, in flight during the staging below
+        RawState<LaneGroup<NC>::K> next;
+        if (i0 < ck.z) next = load_raw<NC>(a, (int64_t)ck.y + i0, q);
         if (use_etile<NC, F>() && use_tile) {
+            // the setting's field from its index: the staging need not wait
+            // for the setting record
+            const double* __restrict__ Eb = t.E0 + (int64_t)ck.w * t.estride;
             // E of the tile's nodes (runs of TILE_R nodes x 3 x NC doubles
             // along x in global memory) into the split layout, SB loads in
             // flight per thread before their LDS writes
@@ -781,7 +789,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
                     const int lx = node % ER, ly = (node / ER) % ER, lz = node / (ER * ER);
                     const int gx = ox + etile_off<F>() + lx, gy = oy + etile_off<F>() + ly, gz = oze + lz;
                     v[k] = (j < SN && gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz)
-                               ? sv.E[(((int64_t)gz * a.ny + gy) * a.nx + gx) * 3 * NC + r]
+                               ? Eb[(((int64_t)gz * a.ny + gy) * a.nx + gx) * 3 * NC + r]
                                : 0.0;
                 }
 #pragma unroll
@@ -797,8 +805,6 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
             // software pipeline: a thread's loads for its next particle are
             // issued before the current one is processed (two iterations deep
             // measured 18% slower with 1e6 particles on 64^3 nodes)
-            RawState<LaneGroup<NC>::K> next;
-            if (i0 < ck.z) next = load_raw<NC>(a, (int64_t)ck.y + i0, q);
 #pragma unroll 1
             for (int i = i0; i < ck.z; i += STRIDE) {
                 const RawState<LaneGroup<NC>::K> curst = next;
@@ -962,6 +968,8 @@ hipError_t launch_particles(dpic_ctx* cx, int flags, int e_tau, int map_off, boo
         if (!cx->chunks_valid || !sort_geometry(cx, tiles, &nbins)) return hipErrorInvalidValue;
         t.chunks = cx->ws.chunks;
         t.nchunks = cx->ws.nchunks;
+        t.E0 = cx->ws.E;
+        t.estride = (int64_t)cx->dims.nx * cx->dims.ny * cx->dims.nz * 3 * cx->NC;
         t.tx = tiles[0];
         t.ty = tiles[1];
         t.nbins = nbins;
