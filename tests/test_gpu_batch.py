@@ -91,6 +91,29 @@ def _check_against_oracle(sim, batch, nsteps=None):
         assert oob[b] == ref.out_of_box
 
 
+def test_batch_with_streamed_fields_matches_oracle():
+    """24 settings on 32^3 grids: their fields (151 MB) are more than the
+    particle kernel expects to stay in the caches, so it stages E on each
+    tile's own nodes and deposits with the drift allowance in z (the other
+    tests run the cached-field geometry). Sampled settings against their own
+    oracle runs, every setting's out-of-box count against zero."""
+    ns = [400 + 50 * k for k in range(24)]
+    batch = _batch(ns, grid=32)
+    w0 = batch.base
+    assert len(ns) * w0.grid[0] * w0.grid[1] * w0.grid[2] * 3 * (w0.ntan + 1) * 8 > 128 * 2**20
+    sim = _make(batch, sort_every=2)
+    sim.step(w0.total_steps())
+    parts = _split(sim.particles(), batch.ns)
+    emit = sim.emittance()
+    assert np.all(sim.batch_counters() == 0)
+    for b in (0, 11, 23):
+        w = batch.setting(b)
+        ref = pic.simulate_workload(w)
+        assert ref.out_of_box == 0
+        assert_particles_close(parts[b], ref.particles)
+        assert_outputs_close(emit[b], ref.emittance, what=f"emittance of setting {b}")
+
+
 @pytest.mark.parametrize("sort_every", [None, 0, 4])
 def test_batch_settings_match_their_own_oracle_runs(sort_every):
     # ragged counts: one below a segment, one empty, one spanning three segments
