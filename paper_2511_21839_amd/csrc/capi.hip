@@ -442,9 +442,7 @@ size_t workspace_layout(const dpic_dims& d, char* base, Workspace* ws) {
     for (size_t nd : {nx, ny, nz}) nbins *= (nd - 1 + TILE_EDGE - 1) / TILE_EDGE;
     nbins += 1;
     const size_t segs = (cap + SEG - 1) / SEG;
-    const size_t ncount = nbins * segs;
-    w.counts = (uint32_t*)take(ncount * sizeof(uint32_t));
-    w.seg = (uint32_t*)take(((ncount + 1023) / 1024 + 1) * sizeof(uint32_t));
+    w.bins = (uint32_t*)take((2 * B * nbins + 2) * sizeof(uint32_t));
     w.chunks = (int4*)take((std::min(B * nbins, cap) + cap / CHUNK_MIN + 1) * sizeof(int4));
     w.nchunks = (uint32_t*)take(sizeof(uint32_t));
     w.set = (SettingDev*)take(B * sizeof(SettingDev));

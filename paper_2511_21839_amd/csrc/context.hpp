@@ -42,8 +42,7 @@ struct Workspace {
     int32_t* pid = nullptr;    // packed original row of each stored particle
     int32_t* pid2 = nullptr;
     uint32_t* key = nullptr;     // sort keys
-    uint32_t* counts = nullptr;  // per (setting, bin, segment) counts, then offsets
-    uint32_t* seg = nullptr;     // scan segment sums
+    uint32_t* bins = nullptr;    // sort: [B][nbins] bin totals, then first slots; [B][nbins] claim cursors
     int4* chunks = nullptr;      // tiled work list (tile, first, count, setting)
     uint32_t* nchunks = nullptr;
     SettingDev* set = nullptr;   // [B]

@@ -6,13 +6,15 @@
 // tile's nodes and flush it once. Key = tile index of the particle's cell;
 // particles outside the box go to a final bin.
 //
-// Counting sort over nbins keys:
-//   count:   each block of SORT_PB particles builds an LDS histogram and writes
-//            its column counts[bin][block];
-//   scan:    exclusive scan of counts in bin-major order (three kernels);
-//   scatter: each block claims slots from its column offsets with LDS atomics
-//            and moves the particles (all channels) into the second buffer.
-// The order inside one bin of one block is not fixed. The original particle
+// Counting sort over nbins keys per setting:
+//   count:   each block of SORT_PB particles builds an LDS histogram and adds
+//            it into the setting's bin totals;
+//   starts:  an exclusive scan of each setting's totals gives every bin's
+//            first storage slot;
+//   scatter: each block claims a run of slots per bin (global atomics), then
+//            its particles take slots in it (LDS atomics) and move with all
+//            channels into the second buffer.
+// The order of particles inside a bin is not fixed. The original particle
 // index travels with the state so read-back stays in the original order.
 //
 // Batches: each setting is sorted within its own storage range (see
@@ -45,42 +47,34 @@ __device__ __forceinline__ uint32_t tile_key(double x, double y, double z, const
 constexpr int SORT_THREADS = 1024;
 
 // Sort block k covers storage segment k, which belongs to setting
-// b = owner[k]. Its column of counts sits at
-// nbins * seg0_b + bin * nseg_b + (k - seg0_b) (seg0_b = off_b / SEG, nseg_b
-// the setting's segments): the array is ordered [setting][bin][segment], so
-// one exclusive scan over it gives every particle's packed destination.
+// b = owner[k]; its particles occupy slots [lo, hi).
 struct SegInfo {
     int b;
-    int64_t lo, hi;       // slots of this segment holding particles
-    int64_t col, nseg;    // counts index of (bin 0, this segment), segments of the setting
-    int64_t delta;
+    int64_t lo, hi;
 };
 
-__device__ __forceinline__ SegInfo seg_info(const SettingDev* set, const int32_t* owner, int nbins, int64_t k) {
+__device__ __forceinline__ SegInfo seg_info(const SettingDev* set, const int32_t* owner, int64_t k) {
     SegInfo r;
     r.b = owner[k];
     const SettingDev sd = set[r.b];
-    const int64_t seg0 = sd.off / SEG;
-    r.nseg = (sd.n + SEG - 1) / SEG;
     r.lo = k * SEG;
     const int64_t end = sd.off + sd.n;
     r.hi = (k + 1) * SEG < end ? (k + 1) * SEG : end;
-    r.col = (int64_t)nbins * seg0 + (k - seg0);
-    r.delta = sd.delta;
     return r;
 }
 
-// FROM_KEYS: the keys were written by the particle launch that produced
-// these positions; only the histogram is built.
+// Count: the block's histogram over the bins, added into the setting's
+// totals tot[b][bin] (non-empty bins only). FROM_KEYS: the keys were
+// written by the particle launch that produced these positions.
 template <int NC, bool FROM_KEYS>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_count(const double* __restrict__ st, int64_t cap,
                                                              const SettingDev* __restrict__ set,
                                                              const int32_t* __restrict__ owner, SortGeom g,
-                                                             uint32_t* __restrict__ key, uint32_t* __restrict__ counts) {
+                                                             uint32_t* __restrict__ key, uint32_t* __restrict__ tot) {
     __shared__ uint32_t h[NUM_TILE_BINS_MAX + 1];
     for (int b = threadIdx.x; b < g.nbins; b += SORT_THREADS) h[b] = 0u;
     __syncthreads();
-    const SegInfo si = seg_info(set, owner, g.nbins, blockIdx.x);
+    const SegInfo si = seg_info(set, owner, blockIdx.x);
     const int64_t cs = cap * NC;
     for (int i = threadIdx.x; i < SORT_PB; i += SORT_THREADS) {
         const int64_t p = si.lo + i;
@@ -96,24 +90,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_count(const double* __res
         }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < g.nbins; b += SORT_THREADS) counts[si.col + (int64_t)b * si.nseg] = h[b];
-}
-
-// Exclusive scan of m values in place: per-segment sums, scan of the sums in
-// one block, then each segment re-scanned with its offset.
-constexpr int SCAN_SEG = 1024;
-
-__global__ __launch_bounds__(1024) void k_scan_seg_sums(const uint32_t* __restrict__ v, int64_t m,
-                                                        uint32_t* __restrict__ seg) {
-    __shared__ uint32_t red[1024];
-    const int64_t i = (int64_t)blockIdx.x * SCAN_SEG + threadIdx.x;
-    red[threadIdx.x] = i < m ? v[i] : 0u;
-    __syncthreads();
-    for (int off = 512; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) seg[blockIdx.x] = red[0];
+    uint32_t* tb = tot + (int64_t)si.b * g.nbins;
+    for (int b = threadIdx.x; b < g.nbins; b += SORT_THREADS)
+        if (h[b] != 0u) atomicAdd(tb + b, h[b]);
 }
 
 __device__ __forceinline__ uint32_t block_excl_scan_1024(uint32_t x, uint32_t* sh, uint32_t* total) {
@@ -131,45 +110,56 @@ __device__ __forceinline__ uint32_t block_excl_scan_1024(uint32_t x, uint32_t* s
     return incl - x;
 }
 
-// one block: exclusive scan of nseg segment sums (any count), in place
-__global__ __launch_bounds__(1024) void k_scan_seg_offsets(uint32_t* __restrict__ seg, int nseg) {
+// Starts: one block per setting; its bin totals become the first storage
+// slot of every bin (exclusive scan plus the setting's offset), in tot (for
+// the work list) and cur (the slots the scatter claims).
+__global__ __launch_bounds__(1024) void k_sort_starts(const SettingDev* __restrict__ set, int nbins,
+                                                      uint32_t* __restrict__ tot, uint32_t* __restrict__ cur) {
     __shared__ uint32_t sh[1024];
-    const int per = (nseg + 1023) / 1024;
-    const int b0 = threadIdx.x * per;
+    const int b = blockIdx.x;
+    const int64_t off = set[b].off;
+    uint32_t* tb = tot + (int64_t)b * nbins;
+    uint32_t* cb = cur + (int64_t)b * nbins;
+    const int per = (nbins + 1023) / 1024;
+    const int f0 = threadIdx.x * per;
     uint32_t s = 0;
     for (int i = 0; i < per; ++i)
-        if (b0 + i < nseg) s += seg[b0 + i];
-    uint32_t run = block_excl_scan_1024(s, sh, nullptr);
+        if (f0 + i < nbins) s += tb[f0 + i];
+    uint32_t run = (uint32_t)off + block_excl_scan_1024(s, sh, nullptr);
     for (int i = 0; i < per; ++i) {
-        const int b = b0 + i;
-        if (b < nseg) {
-            const uint32_t c = seg[b];
-            seg[b] = run;
+        const int f = f0 + i;
+        if (f < nbins) {
+            const uint32_t c = tb[f];
+            tb[f] = run;
+            cb[f] = run;
             run += c;
         }
     }
 }
 
-__global__ __launch_bounds__(1024) void k_scan_apply(uint32_t* __restrict__ v, int64_t m,
-                                                     const uint32_t* __restrict__ seg) {
-    __shared__ uint32_t sh[1024];
-    const int64_t i = (int64_t)blockIdx.x * SCAN_SEG + threadIdx.x;
-    const uint32_t x = i < m ? v[i] : 0u;
-    const uint32_t ex = block_excl_scan_1024(x, sh, nullptr);
-    if (i < m) v[i] = ex + seg[blockIdx.x];
-}
-
+// Scatter: the block recounts its bins, claims a run of slots per non-empty
+// bin from cur, then every particle takes the next slot of its bin (LDS
+// atomics) and moves there with all channels.
 template <int NC>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(const double* __restrict__ st,
                                                                const int32_t* __restrict__ pid, int64_t cap,
                                                                const SettingDev* __restrict__ set,
                                                                const int32_t* __restrict__ owner,
                                                                const uint32_t* __restrict__ key,
-                                                               const uint32_t* __restrict__ offs, int nbins,
+                                                               uint32_t* __restrict__ cur, int nbins,
                                                                double* __restrict__ st2, int32_t* __restrict__ pid2) {
-    __shared__ uint32_t cur[NUM_TILE_BINS_MAX + 1];
-    const SegInfo si = seg_info(set, owner, nbins, blockIdx.x);
-    for (int b = threadIdx.x; b < nbins; b += SORT_THREADS) cur[b] = offs[si.col + (int64_t)b * si.nseg];
+    __shared__ uint32_t h[NUM_TILE_BINS_MAX + 1];
+    for (int b = threadIdx.x; b < nbins; b += SORT_THREADS) h[b] = 0u;
+    __syncthreads();
+    const SegInfo si = seg_info(set, owner, blockIdx.x);
+    for (int i = threadIdx.x; i < SORT_PB; i += SORT_THREADS) {
+        const int64_t p = si.lo + i;
+        if (p < si.hi) atomicAdd(&h[key[p]], 1u);
+    }
+    __syncthreads();
+    uint32_t* cb = cur + (int64_t)si.b * nbins;
+    for (int b = threadIdx.x; b < nbins; b += SORT_THREADS)
+        if (h[b] != 0u) h[b] = atomicAdd(cb + b, h[b]);
     __syncthreads();
     const int64_t cs = cap * NC;
     // lanes in groups of NC: the group leader claims the slot, every lane copies its channel
@@ -178,10 +168,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(const double* __r
         const int c = i % NC;
         const bool valid = p < si.hi;
         uint32_t dst = 0;
-        if (valid && c == 0) dst = atomicAdd(&cur[key[p]], 1u);
+        if (valid && c == 0) dst = atomicAdd(&h[key[p]], 1u);
         dst = __shfl(dst, (int)(threadIdx.x & 63) & ~(NC - 1), 64);
         if (valid) {
-            const int64_t d = (int64_t)dst + si.delta;  // packed position -> storage slot
+            const int64_t d = (int64_t)dst;
 #pragma unroll
             for (int j = 0; j < 6; ++j) st2[j * cs + d * NC + c] = st[j * cs + p * NC + c];
             if (c == 0) pid2[d] = pid[p];
@@ -193,22 +183,20 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(const double* __r
 // f = b * nbins + bin holds slots [start(b, bin), start(b, bin + 1)), the
 // last bin ending at off_b + n_b; each range is cut into items of at most
 // `chunk` particles: (tile, first slot, count, setting).
-__device__ __forceinline__ void bin_range(const SettingDev* set, const uint32_t* offs, int nbins, int f, int64_t* a,
+__device__ __forceinline__ void bin_range(const SettingDev* set, const uint32_t* starts, int nbins, int f, int64_t* a,
                                           int64_t* e) {
     const int b = f / nbins, bin = f - b * nbins;
     const SettingDev sd = set[b];
-    const int64_t nseg = (sd.n + SEG - 1) / SEG;
-    if (nseg == 0) {
+    if (sd.n == 0) {
         *a = *e = 0;
         return;
     }
-    const int64_t base = (int64_t)nbins * (sd.off / SEG);
-    *a = (int64_t)offs[base + (int64_t)bin * nseg] + sd.delta;
-    *e = bin + 1 < nbins ? (int64_t)offs[base + (int64_t)(bin + 1) * nseg] + sd.delta : sd.off + sd.n;
+    *a = (int64_t)starts[f];
+    *e = bin + 1 < nbins ? (int64_t)starts[f + 1] : sd.off + sd.n;
 }
 
 __global__ __launch_bounds__(1024) void k_build_chunks(const SettingDev* __restrict__ set,
-                                                       const uint32_t* __restrict__ offs, int nbins, int nb,
+                                                       const uint32_t* __restrict__ starts, int nbins, int nb,
                                                        int chunk, int4* __restrict__ chunks,
                                                        uint32_t* __restrict__ nchunks) {
     __shared__ uint32_t sh[1024];
@@ -220,7 +208,7 @@ __global__ __launch_bounds__(1024) void k_build_chunks(const SettingDev* __restr
         const int f = f0 + i;
         if (f < nf) {
             int64_t a, e;
-            bin_range(set, offs, nbins, f, &a, &e);
+            bin_range(set, starts, nbins, f, &a, &e);
             s += (uint32_t)((e - a + chunk - 1) / chunk);
         }
     }
@@ -230,7 +218,7 @@ __global__ __launch_bounds__(1024) void k_build_chunks(const SettingDev* __restr
         const int f = f0 + i;
         if (f < nf) {
             int64_t a, e;
-            bin_range(set, offs, nbins, f, &a, &e);
+            bin_range(set, starts, nbins, f, &a, &e);
             const int b = f / nbins;
             for (int64_t q = a; q < e; q += chunk) {
                 const int64_t cnt = (e - q) < chunk ? (e - q) : chunk;
@@ -281,29 +269,30 @@ hipError_t launch_sort(dpic_ctx* cx) {
     const int64_t cap = cx->dims.n_particles;
     const Workspace& w = cx->ws;
     const int nsegs = (int)((cx->used + SEG - 1) / SEG);
-    const int64_t m = (int64_t)g.nbins * nsegs;
-    const int nscan = (int)((m + SCAN_SEG - 1) / SCAN_SEG);
+    const int64_t nbt = (int64_t)cx->B * g.nbins;
+    uint32_t* tot = w.bins;
+    uint32_t* cur = w.bins + nbt;
     if (nsegs > 0) {
+        hipError_t ez = launch_zero(cx, (double*)tot, (size_t)(nbt + 1) / 2);
+        if (ez != hipSuccess) return ez;
         if (cx->keys_ready) {
             hipLaunchKernelGGL((k_sort_count<1, true>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key,
-                               w.counts);
+                               tot);
         } else {
             switch (cx->NC) {
-                case 1: hipLaunchKernelGGL((k_sort_count<1, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, w.counts); break;
-                case 8: hipLaunchKernelGGL((k_sort_count<8, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, w.counts); break;
-                default: hipLaunchKernelGGL((k_sort_count<16, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, w.counts); break;
+                case 1: hipLaunchKernelGGL((k_sort_count<1, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, tot); break;
+                case 8: hipLaunchKernelGGL((k_sort_count<8, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, tot); break;
+                default: hipLaunchKernelGGL((k_sort_count<16, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, tot); break;
             }
         }
-        hipLaunchKernelGGL(k_scan_seg_sums, dim3(nscan), dim3(1024), 0, s, w.counts, m, w.seg);
-        hipLaunchKernelGGL(k_scan_seg_offsets, dim3(1), dim3(1024), 0, s, w.seg, nscan);
-        hipLaunchKernelGGL(k_scan_apply, dim3(nscan), dim3(1024), 0, s, w.counts, m, w.seg);
+        hipLaunchKernelGGL(k_sort_starts, dim3(cx->B), dim3(1024), 0, s, w.set, g.nbins, tot, cur);
         switch (cx->NC) {
-            case 1: hipLaunchKernelGGL(k_sort_scatter<1>, dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, w.pid, cap, w.set, w.owner, w.key, w.counts, g.nbins, w.st2, w.pid2); break;
-            case 8: hipLaunchKernelGGL(k_sort_scatter<8>, dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, w.pid, cap, w.set, w.owner, w.key, w.counts, g.nbins, w.st2, w.pid2); break;
-            default: hipLaunchKernelGGL(k_sort_scatter<16>, dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, w.pid, cap, w.set, w.owner, w.key, w.counts, g.nbins, w.st2, w.pid2); break;
+            case 1: hipLaunchKernelGGL(k_sort_scatter<1>, dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, w.pid, cap, w.set, w.owner, w.key, cur, g.nbins, w.st2, w.pid2); break;
+            case 8: hipLaunchKernelGGL(k_sort_scatter<8>, dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, w.pid, cap, w.set, w.owner, w.key, cur, g.nbins, w.st2, w.pid2); break;
+            default: hipLaunchKernelGGL(k_sort_scatter<16>, dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, w.pid, cap, w.set, w.owner, w.key, cur, g.nbins, w.st2, w.pid2); break;
         }
     }
-    hipLaunchKernelGGL(k_build_chunks, dim3(1), dim3(1024), 0, s, w.set, w.counts, g.nbins, cx->B, (int)cx->chunk,
+    hipLaunchKernelGGL(k_build_chunks, dim3(1), dim3(1024), 0, s, w.set, tot, g.nbins, cx->B, (int)cx->chunk,
                        w.chunks, w.nchunks);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
