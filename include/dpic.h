@@ -221,15 +221,16 @@ int dpic_load_state(dpic_ctx* ctx, const void* dev_buf);
 /*
  * Options:
  *  DPIC_OPT_SORT_EVERY = re-sort particles by grid tile every k steps (0 = never,
- *    default 12);
+ *    default 10);
  *  DPIC_OPT_STAGE_TIMING = 1 records HIP events around every stage launch of
  *    dpic_step, 2 around the particle stage only (fewer event records in the
  *    stream: each leaves the GPU idle for a few microseconds); read with
  *    dpic_stage_times; other values are EINVAL;
  *  DPIC_OPT_CHUNK = particles per work item of the tiled particle kernel
- *    (a multiple of 64 in 128..8192, default 1024);
+ *    (a multiple of 64 in 128..8192, default 768);
  *  DPIC_OPT_PART_BLOCKS = workgroups of the persistent tiled particle kernel
- *    (0 = twice the device's resident capacity for it, the default);
+ *    (0 = four times the device's resident capacity for it, the default;
+ *    never more than the work list can hold);
  *  DPIC_OPT_GRAPH = 1 captures each distinct dpic_step(n) call (same start
  *    step, same n, same batch layout) in a HIP graph on first use and replays
  *    it afterwards, and likewise the adjoint sweep of dpic_adjoint_backward

@@ -1003,7 +1003,7 @@ int dpic_autotune(dpic_ctx* c, void* scratch, size_t scratch_bytes, int trial_st
     const int64_t resident = particle_resident_blocks(c);
     r = trial(se, ch, pb, &t);  // warm-up, then the incumbent
     if (r == DPIC_OK) r = trial(se, ch, pb, &bms);
-    for (int64_t v : {256, 512, 1024, 2048}) {
+    for (int64_t v : {256, 512, 768, 1024, 2048}) {
         if (r != DPIC_OK || v == ch) continue;
         if ((r = trial(se, v, pb, &t)) == DPIC_OK && t < bms) {
             bms = t;

@@ -74,7 +74,7 @@ constexpr int TILE_EDGE = 4;                             // cells per tile edge
 constexpr int TILE_HALO = 1;                             // drift allowance (cells)
 constexpr int TILE_R = TILE_EDGE + 2 * TILE_HALO + 1;    // deposit tile nodes per dimension
 constexpr int TILE_RZ_E = TILE_EDGE + 1;                 // E tile nodes in z
-constexpr int TILE_CHUNK = 1024;                         // default particles per tiled work item
+constexpr int TILE_CHUNK = 768;                          // default particles per tiled work item
 constexpr int CHUNK_MIN = 128;                           // smallest work item (sizes the work list)
 constexpr int CHUNK_MAX = 8192;
 constexpr int SORT_PB = SEG;                             // particles per sort block
@@ -165,7 +165,7 @@ struct dpic_ctx {
     int64_t steps_done = 0;
     bool swapped = false;             // ws.st holds the second state buffer
     // options
-    int64_t sort_every = 12;
+    int64_t sort_every = 10;
     int64_t chunk = dpic::TILE_CHUNK;  // particles per tiled work item
     int64_t part_blocks = 0;           // workgroups of the tiled particle kernel (0: resident capacity)
     bool chunks_valid = false;  // the tiled work list matches the stored order

@@ -885,11 +885,13 @@ static void launch_one(dpic_ctx* cx, const PartArgs& a, const TiledArgs& t, size
     constexpr int G = LaneGroup<NC>::G;
     dim3 block(PART_THREADS);
     if (TL) {
-        // default: twice the resident workgroups, so that the hardware
-        // dispatcher refills CUs whose items finish early
+        // default: four times the resident workgroups as the runtime reports
+        // them, more than the work items at the default item size, so that
+        // every item gets a workgroup of its own and the hardware dispatcher
+        // balances them (a workgroup that found two items set the time)
         size_t g = cx->part_blocks > 0
                        ? (size_t)cx->part_blocks
-                       : 2 * (size_t)tiled_occupancy<NC, FL>() * (size_t)(cx->cu_count > 0 ? cx->cu_count : 256);
+                       : 4 * (size_t)tiled_occupancy<NC, FL>() * (size_t)(cx->cu_count > 0 ? cx->cu_count : 256);
         if (g > max_items) g = max_items;
         if (g < 1) g = 1;
         hipLaunchKernelGGL((k_particles_tiled<NC, FL>), dim3((unsigned)g), block, 0, cx->stream, a, t);

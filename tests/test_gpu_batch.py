@@ -278,7 +278,7 @@ def test_autotune_keeps_the_state_and_picks_a_candidate():
     T = batch.base.total_steps()
     sim.step(3)
     res = sim.autotune(trial_steps=8)
-    assert res["chunk"] in (256, 512, 1024, 2048)
+    assert res["chunk"] in (256, 512, 768, 1024, 2048)
     assert res["sort_every"] in (5, 10, 12, 20, 40)
     assert res["part_blocks"] >= 0 and res["ms"] > 0
     assert sim.get_option(dpic.OPT_CHUNK) == res["chunk"]
