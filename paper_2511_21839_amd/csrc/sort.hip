@@ -172,8 +172,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(const double* __r
         dst = __shfl(dst, (int)(threadIdx.x & 63) & ~(NC - 1), 64);
         if (valid) {
             const int64_t d = (int64_t)dst;
+            // the state streams through once: nontemporal, like the particle kernel's accesses
 #pragma unroll
-            for (int j = 0; j < 6; ++j) st2[j * cs + d * NC + c] = st[j * cs + p * NC + c];
+            for (int j = 0; j < 6; ++j)
+                __builtin_nontemporal_store(__builtin_nontemporal_load(st + j * cs + p * NC + c), st2 + j * cs + d * NC + c);
             if (c == 0) pid2[d] = pid[p];
         }
     }
