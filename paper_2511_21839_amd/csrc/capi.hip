@@ -66,7 +66,8 @@ struct StageTimer {
     dpic_ctx* c;
     int stage;
     hipEvent_t end = nullptr;
-    StageTimer(dpic_ctx* c_, int s) : c(c_), stage(s) {
+    bool counted;  // adds to the stage's launch count (false: a part of a stage that is counted elsewhere)
+    StageTimer(dpic_ctx* c_, int s, bool counted_ = true) : c(c_), stage(s), counted(counted_) {
         if (c->stage_timing == 0 || (c->stage_timing == 2 && stage != T_PART)) return;
         auto& pool = c->ev_pool[stage];
         const size_t i = c->ev_used[stage];
@@ -86,16 +87,16 @@ struct StageTimer {
     ~StageTimer() {
         if (!end) return;
         (void)hipEventRecord(end, c->stream);
-        c->stage_launches[stage]++;
+        if (counted) c->stage_launches[stage]++;
     }
 };
 
 
 // keys: the launch also writes the tile keys of the positions it deposits
 // at, for the sort that follows it.
-int run_particles(dpic_ctx* c, int flags, int e_tau, int map_off, bool keys = false) {
+int run_particles(dpic_ctx* c, int flags, int e_tau, int map_off, bool keys = false, bool scatter = false) {
     StageTimer tm(c, T_PART);
-    HIPCHK(c, launch_particles(c, flags, e_tau, map_off, c->sort_every > 0 && c->chunks_valid, keys));
+    HIPCHK(c, launch_particles(c, flags, e_tau, map_off, c->sort_every > 0 && c->chunks_valid, keys, scatter));
     c->keys_ready = keys;
     return DPIC_OK;
 }
@@ -142,6 +143,21 @@ int run_solve_field(dpic_ctx* c) {
 int run_sort(dpic_ctx* c) {
     StageTimer tm(c, T_SORT);
     HIPCHK(c, launch_sort(c));
+    return DPIC_OK;
+}
+
+// A re-sort split around the particle launch that stores the state in sorted
+// order: the counts after the launch that wrote the keys (timed with the
+// sort, counted once with the finish).
+int run_sort_counts(dpic_ctx* c) {
+    StageTimer tm(c, T_SORT, false);
+    HIPCHK(c, launch_sort_counts(c));
+    return DPIC_OK;
+}
+
+int run_sort_finish(dpic_ctx* c) {
+    StageTimer tm(c, T_SORT);
+    HIPCHK(c, launch_sort_finish(c, true));
     return DPIC_OK;
 }
 
@@ -288,14 +304,35 @@ int step_body(dpic_ctx* c, int n) {
         HIPCHK(c, launch_zero(c, c->ws.rho, rho_n));
         if ((r = run_particles(c, PF_MAP | PF_DEPOSIT, c->schedule[s0], ec_offset(c, c->schedule[s0], EC_HALF))) != DPIC_OK)
             return r;
+        // Re-sort after step s when (s + 1) is a multiple of the cadence R.
+        // With R >= 2 and room in this call, the launch one step earlier
+        // writes the tile keys and the bins are counted from them; the sort
+        // step's launch then stores every particle in its sorted slot, which
+        // replaces the scatter's full pass over the state (the order lags the
+        // positions by one step, well inside the tiles' drift allowance).
+        // Otherwise the sort step's launch writes the keys and a plain sort
+        // follows it.
+        const int64_t R = c->sort_every;
+        bool counted = false;
         for (int64_t s = s0; s < s1; ++s) {
             if ((r = run_solve_field(c)) != DPIC_OK) return r;
             const bool last = (s == s1 - 1);
             const int flags = PF_KICK | PF_MAP | (last ? 0 : PF_DEPOSIT);
-            const bool sort_next = c->sort_every > 0 && !last && ((s + 1) % c->sort_every) == 0;
-            if ((r = run_particles(c, flags, c->schedule[s], closing_map(c, s, last), sort_next)) != DPIC_OK) return r;
-            if (sort_next)
+            const bool sort_next = R > 0 && !last && ((s + 1) % R) == 0;
+            const bool scatter = sort_next && counted;
+            const bool early_keys = R >= 2 && s + 2 < s1 && ((s + 2) % R) == 0;
+            const bool keys = (sort_next && !scatter) || early_keys;
+            if ((r = run_particles(c, flags, c->schedule[s], closing_map(c, s, last), keys, scatter)) != DPIC_OK)
+                return r;
+            if (scatter) {
+                if ((r = run_sort_finish(c)) != DPIC_OK) return r;
+                counted = false;
+            } else if (sort_next) {
                 if ((r = run_sort(c)) != DPIC_OK) return r;
+            } else if (early_keys) {
+                if ((r = run_sort_counts(c)) != DPIC_OK) return r;
+                counted = true;
+            }
         }
     } else {
         if ((r = run_particles(c, PF_MAP | PF_COUNT, c->schedule[s0], ec_offset(c, c->schedule[s0], EC_HALF))) != DPIC_OK)

@@ -111,7 +111,8 @@ enum PartFlags {
     PF_DEPOSIT = 4,  // CIC deposit at the resulting position (implies counting)
     PF_COUNT = 8,    // count out-of-box particles and track the extent
     PF_EHALO = 16,   // tiled kernel: E tile with the transverse drift allowance (see particles.hip)
-    PF_KEYS = 32     // with PF_DEPOSIT: write each particle's tile key for the sort that follows
+    PF_KEYS = 32,    // with PF_DEPOSIT: write each particle's tile key for the sort that follows
+    PF_SCATTER = 64  // tiled kernel: store each particle in its sorted slot of the second state buffer
 };
 
 enum CounterSlot { CNT_OUTSIDE = 0, CNT_EXT_X = 1, CNT_EXT_Y = 2, CNT_EXT_Z = 3, CNT_N = 8 };

@@ -198,7 +198,11 @@ hipError_t launch_element_consts_into(dpic_ctx* c, int NC, int nb, const double*
 hipError_t launch_init_beam(dpic_ctx* c, const double* xi);
 // flags: PF_*; e_tau: element whose step size the kick uses; map_off: map
 // block to apply (ec_offset) when PF_MAP is set.
-hipError_t launch_particles(dpic_ctx* c, int flags, int e_tau, int map_off, bool tiled, bool write_keys = false);
+// write_keys: also write each particle's tile key (PF_KEYS); scatter: store
+// each particle in its sorted slot of the second buffer (PF_SCATTER, after
+// launch_sort_counts over the previous launch's keys).
+hipError_t launch_particles(dpic_ctx* c, int flags, int e_tau, int map_off, bool tiled, bool write_keys = false,
+                            bool scatter = false);
 hipError_t launch_canonical_state(dpic_ctx* c);  // st -> st2 in packed original order
 int particle_resident_blocks(dpic_ctx* c);       // resident tiled-kernel workgroups on the device
 hipError_t launch_zero(dpic_ctx* c, double* p, size_t n);
@@ -207,6 +211,11 @@ hipError_t launch_zero(dpic_ctx* c, double* p, size_t n);
 bool sort_geometry(const dpic_ctx* c, int* tiles, int* nbins);
 size_t max_chunks(const dpic_ctx* c);
 hipError_t launch_sort(dpic_ctx* c);  // also rebuilds the tiled work list
+// The sort in two parts around a particle launch that stores the state in
+// sorted order itself: bin totals and first slots from the stored keys, then
+// (after that launch) the work list and the buffer swap.
+hipError_t launch_sort_counts(dpic_ctx* c);
+hipError_t launch_sort_finish(dpic_ctx* c, bool scattered);
 
 // ---- launchers (solver.hip)
 hipError_t launch_green(dpic_ctx* c);

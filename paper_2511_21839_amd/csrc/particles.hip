@@ -357,6 +357,9 @@ struct PartArgs {
     double kperp, kpar;
     uint32_t* key_out;      // PF_KEYS: each particle's tile key for the next sort
     int ktx, kty, knbins;   // tiles in x and y, sort bins (the last one: outside the box)
+    double* st_out;         // PF_SCATTER: second state buffer, sorted order
+    const int32_t* pid_in;  // PF_SCATTER: original rows, stored order
+    int32_t* pid_out;       //             and sorted order
 };
 
 // the arrays and charge of one setting
@@ -375,7 +378,19 @@ struct TiledArgs {
     const double* E0;  // field of setting b at E0 + b * estride
     int64_t estride;
     int tx, ty, nbins;
+    const uint32_t* key_in;  // PF_SCATTER: tile keys, stored order (counted into the bin starts)
+    uint32_t* cur;           // PF_SCATTER: [setting][bin] next free sorted slot
 };
+
+// PF_SCATTER: position of tile key k among the 27 tiles around (tx, ty, tz),
+// or -1 (farther, or outside the box)
+__device__ __forceinline__ int near_tile(uint32_t k, int tx, int ty, int tz, const TiledArgs& t) {
+    if ((int)k >= t.nbins - 1) return -1;
+    const int kx = (int)k % t.tx, ky = ((int)k / t.tx) % t.ty, kz = (int)k / (t.tx * t.ty);
+    const int dx = kx - tx + 1, dy = ky - ty + 1, dz = kz - tz + 1;
+    if ((unsigned)dx > 2u || (unsigned)dy > 2u || (unsigned)dz > 2u) return -1;
+    return (dz * 3 + dy) * 3 + dx;
+}
 
 // LDS copy of the deposit tile: the nodes [o, o + TILE_R)^2 x [oz, oz +
 // dep_rz) around the grid tile, channel-major with a channel stride of 1 mod
@@ -551,14 +566,13 @@ __device__ __forceinline__ QD<K> raw_to_qd(const double* r, int q) {
     return x;
 }
 
-template <int NC, int F, bool TILED>
+template <int NC, int F, bool TILED, class Dest>
 __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& sv, const double* __restrict__ smap,
-                                              const double* __restrict__ stau, int64_t p, int q,
+                                              const double* __restrict__ stau, int64_t p, Dest dest, int q,
                                               const RawState<LaneGroup<NC>::K>& raw, double* lr, const double* le, int ox,
                                               int oy, int oz, int oze, bool use_tile, double& e0, double& e1, double& e2) {
     constexpr int G = LaneGroup<NC>::G, K = LaneGroup<NC>::K;
     const int64_t cs = a.cap * NC;
-    double* sp = a.st + p * NC;
     QD<K> x = raw_to_qd<K, G>(raw.r[0], q), px = raw_to_qd<K, G>(raw.r[1], q), y = raw_to_qd<K, G>(raw.r[2], q);
     QD<K> py = raw_to_qd<K, G>(raw.r[3], q), z = raw_to_qd<K, G>(raw.r[4], q), d = raw_to_qd<K, G>(raw.r[5], q);
     const int64_t sxy = (int64_t)a.nx * a.ny;
@@ -691,6 +705,8 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& 
         e1 = fmax(e1, fabs(y.v));
         e2 = fmax(e2, fabs(z.v));
     }
+    // the slot the state goes to: p, or with PF_SCATTER its sorted slot
+    double* sp = ((F & PF_SCATTER) ? a.st_out : a.st) + dest() * NC;
     qd_store(sp, x, q);
     qd_store(sp + cs, px, q);
     qd_store(sp + 2 * cs, y, q);
@@ -728,9 +744,26 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles(PartArgs a) {
     double e0 = 0.0, e1 = 0.0, e2 = 0.0;
     if (p - sd.off < sd.n) {
         const RawState<LaneGroup<NC>::K> raw = load_raw<NC>(a, p, q);
-        particle_body<NC, F, false>(a, sv, smap, stau, p, q, raw, nullptr, nullptr, 0, 0, 0, 0, false, e0, e1, e2);
+        particle_body<NC, F, false>(a, sv, smap, stau, p, [p]() { return p; }, q, raw, nullptr, nullptr, 0, 0, 0, 0, false, e0, e1, e2);
     }
     if (F & (PF_DEPOSIT | PF_COUNT)) extent_flush(sv.cnt, e0, e1, e2, sext);
+}
+
+// PF_SCATTER: the sorted slot of a particle with tile key k and original row
+// `row` (both loaded by the group's first lane with its state), claimed by
+// that lane from its tile's run (sclaim) or singly from the bin's cursor; the
+// lane also moves the original row.
+template <int G>
+__device__ __forceinline__ int64_t scatter_slot(const PartArgs& a, const TiledArgs& t, int q, uint32_t k, int32_t row,
+                                                uint32_t* sclaim, int setting, int tx, int ty, int tz, bool use_tile) {
+    uint32_t slot = 0u;
+    if (q == 0) {
+        const int l = use_tile ? near_tile(k, tx, ty, tz, t) : -1;
+        slot = l >= 0 ? atomicAdd(&sclaim[l], 1u) : atomicAdd(t.cur + (int64_t)setting * t.nbins + k, 1u);
+        a.pid_out[slot] = row;
+    }
+    if constexpr (G > 1) slot = (uint32_t)group_bcast_u32<G>((int)slot);
+    return (int64_t)slot;
 }
 
 // Tiled kernel, persistent: each workgroup walks the work list with a grid
@@ -739,7 +772,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles(PartArgs a) {
 // TILE_HALO-cell halo (particles drift between re-sorts) and is flushed once:
 // only nodes that received charge issue global atomics.
 template <int NC, int F>
-__global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, TiledArgs t) {
+__device__ __forceinline__ void tiled_body(const PartArgs& a, const TiledArgs& t) {
     constexpr int G = LaneGroup<NC>::G;
     constexpr int LDSN = (F & PF_DEPOSIT) ? dep_cstride<F>() * NC : 1;
     constexpr int LDSE = use_etile<NC, F>() ? etile_nodes<F>() * 3 * lds_dual<NC>() : 1;
@@ -748,6 +781,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
     __shared__ __align__(16) double smap[MB_N * lds_dual<NC>()];
     __shared__ __align__(16) double stau[lds_dual<NC>()];
     __shared__ double sext[PART_THREADS / 64][3];
+    __shared__ uint32_t sclaim[(F & PF_SCATTER) ? 27 : 1];  // PF_SCATTER: per nearby tile, next sorted slot
     const uint32_t nck = *t.nchunks;
     const int q = threadIdx.x % G;
     constexpr int STRIDE = PART_THREADS / G;
@@ -775,9 +809,37 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
         const int tx = ck.x % t.tx, ty = (ck.x / t.tx) % t.ty, tz = ck.x / (t.tx * t.ty);
         const int ox = tx * TILE_EDGE - TILE_HALO, oy = ty * TILE_EDGE - TILE_HALO, oz = tz * TILE_EDGE - dep_offz<F>();
         const int oze = tz * TILE_EDGE;  // E tile: no allowance in z
+        if (F & PF_SCATTER) {
+            // the item's particles by destination bin: one run of sorted
+            // slots claimed per tile around the item's own, single slots for
+            // particles farther away (LDS cleared after the previous item's
+            // last use at the barrier that opened this one)
+            if (threadIdx.x < 27) sclaim[threadIdx.x] = 0u;
+            __syncthreads();
+            if (use_tile)
+                for (int j = threadIdx.x; j < ck.z; j += PART_THREADS) {
+                    const int l = near_tile(t.key_in[(int64_t)ck.y + j], tx, ty, tz, t);
+                    if (l >= 0) atomicAdd(&sclaim[l], 1u);
+                }
+            __syncthreads();
+            if (threadIdx.x < 27 && sclaim[threadIdx.x] != 0u) {
+                const int l = threadIdx.x;
+                const int key = ((tz + l / 9 - 1) * t.ty + (ty + (l / 3) % 3 - 1)) * t.tx + (tx + l % 3 - 1);
+                sclaim[l] = atomicAdd(t.cur + (int64_t)ck.w * t.nbins + key, sclaim[l]);
+            }
+            // ordered before the particle loop by the barrier after the E staging
+        }
         // first particle's loads, in flight during the staging below
         RawState<LaneGroup<NC>::K> next;
-        if (i0 < ck.z) next = load_raw<NC>(a, (int64_t)ck.y + i0, q);
+        uint32_t knext = 0u;  // PF_SCATTER: the next particle's tile key and original row (first lane),
+        int32_t rnext = 0;    // loaded with its state
+        if (i0 < ck.z) {
+            next = load_raw<NC>(a, (int64_t)ck.y + i0, q);
+            if ((F & PF_SCATTER) && q == 0) {
+                knext = t.key_in[(int64_t)ck.y + i0];
+                rnext = a.pid_in[(int64_t)ck.y + i0];
+            }
+        }
         if (use_etile<NC, F>() && use_tile) {
             // the setting's field from its index: the staging need not wait
             // for the setting record
@@ -816,8 +878,24 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
 #pragma unroll 1
             for (int i = i0; i < ck.z; i += STRIDE) {
                 const RawState<LaneGroup<NC>::K> curst = next;
-                if (i + STRIDE < ck.z) next = load_raw<NC>(a, (int64_t)ck.y + i + STRIDE, q);
-                particle_body<NC, F, true>(a, sv, smap, stau, (int64_t)ck.y + i, q, curst, lr, le, ox, oy, oz, oze, use_tile,
+                const uint32_t kin = knext;
+                const int32_t rin = rnext;
+                if (i + STRIDE < ck.z) {
+                    next = load_raw<NC>(a, (int64_t)ck.y + i + STRIDE, q);
+                    if ((F & PF_SCATTER) && q == 0) {
+                        knext = t.key_in[(int64_t)ck.y + i + STRIDE];
+                        rnext = a.pid_in[(int64_t)ck.y + i + STRIDE];
+                    }
+                }
+                const int64_t p = (int64_t)ck.y + i;
+                // PF_SCATTER: the sorted slot is claimed just before the stores
+                auto dest = [&]() -> int64_t {
+                    if constexpr ((F & PF_SCATTER) != 0)
+                        return scatter_slot<G>(a, t, q, kin, rin, sclaim, ck.w, tx, ty, tz, use_tile);
+                    else
+                        return p;
+                };
+                particle_body<NC, F, true>(a, sv, smap, stau, p, dest, q, curst, lr, le, ox, oy, oz, oze, use_tile,
                                            e0, e1, e2);
             }
         }
@@ -845,16 +923,33 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, Ti
     if ((F & (PF_DEPOSIT | PF_COUNT)) && cur >= 0) extent_flush(sv.cnt, e0, e1, e2, sext);
 }
 
+template <int NC, int F>
+__global__ __launch_bounds__(PART_THREADS) void k_particles_tiled(PartArgs a, TiledArgs t) {
+    static_assert((F & PF_SCATTER) == 0, "sorted stores: k_particles_sorted");
+    tiled_body<NC, F>(a, t);
+}
+
+// The same kernel storing the state in sorted order (PF_SCATTER), held to
+// two waves per SIMD: the slot claims add registers, which would otherwise
+// leave room for one.
+template <int NC, int F>
+__global__ __launch_bounds__(PART_THREADS, 2) void k_particles_sorted(PartArgs a, TiledArgs t) {
+    static_assert((F & PF_SCATTER) != 0, "unsorted stores: k_particles_tiled");
+    tiled_body<NC, F>(a, t);
+}
+
 // Resident workgroups per CU of one tiled-kernel instance (queried once).
 template <int NC, int FL>
 static int tiled_occupancy() {
     static int occ = 0;
     if (occ == 0) {
         int v = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_particles_tiled<NC, FL>, PART_THREADS, 0) !=
-                hipSuccess ||
-            v < 1)
-            v = 1;
+        hipError_t e;
+        if constexpr ((FL & PF_SCATTER) != 0)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_particles_sorted<NC, FL>, PART_THREADS, 0);
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_particles_tiled<NC, FL>, PART_THREADS, 0);
+        if (e != hipSuccess || v < 1) v = 1;
         occ = v;
     }
     return occ;
@@ -902,7 +997,10 @@ static void launch_one(dpic_ctx* cx, const PartArgs& a, const TiledArgs& t, size
                        : 4 * (size_t)tiled_occupancy<NC, FL>() * (size_t)(cx->cu_count > 0 ? cx->cu_count : 256);
         if (g > max_items) g = max_items;
         if (g < 1) g = 1;
-        hipLaunchKernelGGL((k_particles_tiled<NC, FL>), dim3((unsigned)g), block, 0, cx->stream, a, t);
+        if constexpr ((FL & PF_SCATTER) != 0)
+            hipLaunchKernelGGL((k_particles_sorted<NC, FL>), dim3((unsigned)g), block, 0, cx->stream, a, t);
+        else
+            hipLaunchKernelGGL((k_particles_tiled<NC, FL>), dim3((unsigned)g), block, 0, cx->stream, a, t);
     } else {
         const int64_t blocks = (a.used * G + PART_THREADS - 1) / PART_THREADS;
         hipLaunchKernelGGL((k_particles<NC, FL>), dim3((unsigned)blocks), block, 0, cx->stream, a);
@@ -935,12 +1033,21 @@ static hipError_t launch_particles_nc(dpic_ctx* cx, int flags, const PartArgs& a
             if constexpr (!TL) return hipErrorInvalidValue;
             launch_one<NC, PF_KICK | PF_MAP | PF_DEPOSIT | PF_EHALO | PF_KEYS, TL>(cx, a, t, max_items);
             break;
+        case PF_KICK | PF_MAP | PF_DEPOSIT | PF_SCATTER:
+            if constexpr (!TL) return hipErrorInvalidValue;
+            launch_one<NC, PF_KICK | PF_MAP | PF_DEPOSIT | PF_SCATTER, TL>(cx, a, t, max_items);
+            break;
+        case PF_KICK | PF_MAP | PF_DEPOSIT | PF_EHALO | PF_SCATTER:
+            if constexpr (!TL) return hipErrorInvalidValue;
+            launch_one<NC, PF_KICK | PF_MAP | PF_DEPOSIT | PF_EHALO | PF_SCATTER, TL>(cx, a, t, max_items);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_particles(dpic_ctx* cx, int flags, int e_tau, int map_off, bool tiled, bool write_keys) {
+hipError_t launch_particles(dpic_ctx* cx, int flags, int e_tau, int map_off, bool tiled, bool write_keys,
+                            bool scatter) {
     PartArgs a;
     a.st = cx->ws.st;
     a.cap = cx->dims.n_particles;
@@ -962,6 +1069,9 @@ hipError_t launch_particles(dpic_ctx* cx, int flags, int e_tau, int map_off, boo
     a.kpar = cx->kpar;
     a.key_out = nullptr;
     a.ktx = a.kty = a.knbins = 0;
+    a.st_out = nullptr;
+    a.pid_in = nullptr;
+    a.pid_out = nullptr;
     if (write_keys && (flags & PF_DEPOSIT)) {
         int tk[3], nb = 0;
         if (!sort_geometry(cx, tk, &nb)) return hipErrorInvalidValue;
@@ -984,6 +1094,17 @@ hipError_t launch_particles(dpic_ctx* cx, int flags, int e_tau, int map_off, boo
         t.ty = tiles[1];
         t.nbins = nbins;
         items = max_chunks(cx);
+    }
+    if (scatter) {
+        // the bin starts and cursors come from the keys of the previous
+        // launch (launch_sort_counts); keys and scatter never share a launch
+        if (!tiled || (flags & PF_KEYS) || !(flags & PF_KICK) || !(flags & PF_DEPOSIT)) return hipErrorInvalidValue;
+        a.st_out = cx->ws.st2;
+        a.pid_in = cx->ws.pid;
+        a.pid_out = cx->ws.pid2;
+        t.key_in = cx->ws.key;
+        t.cur = cx->ws.bins + (size_t)cx->B * t.nbins;
+        flags |= PF_SCATTER;
     }
     // the E tile with the drift allowance while the fields of all settings
     // fit in the caches

@@ -251,22 +251,29 @@ size_t max_chunks(const dpic_ctx* cx) {
     return bins + (size_t)(cx->n / cx->chunk) + 1;
 }
 
-hipError_t launch_sort(dpic_ctx* cx) {
-    SortGeom g;
+static bool sort_geom(const dpic_ctx* cx, SortGeom* g) {
     int t[3];
-    if (!sort_geometry(cx, t, &g.nbins)) return hipErrorInvalidValue;
-    g.lo0 = cx->lo[0];
-    g.lo1 = cx->lo[1];
-    g.lo2 = cx->lo[2];
-    g.ih0 = 1.0 / cx->h[0];
-    g.ih1 = 1.0 / cx->h[1];
-    g.ih2 = 1.0 / cx->h[2];
-    g.nx = cx->dims.nx;
-    g.ny = cx->dims.ny;
-    g.nz = cx->dims.nz;
-    g.tx = t[0];
-    g.ty = t[1];
-    g.tz = t[2];
+    if (!sort_geometry(cx, t, &g->nbins)) return false;
+    g->lo0 = cx->lo[0];
+    g->lo1 = cx->lo[1];
+    g->lo2 = cx->lo[2];
+    g->ih0 = 1.0 / cx->h[0];
+    g->ih1 = 1.0 / cx->h[1];
+    g->ih2 = 1.0 / cx->h[2];
+    g->nx = cx->dims.nx;
+    g->ny = cx->dims.ny;
+    g->nz = cx->dims.nz;
+    g->tx = t[0];
+    g->ty = t[1];
+    g->tz = t[2];
+    return true;
+}
+
+// bin totals of every setting (from the stored keys when the last particle
+// launch wrote them, else from the positions), then first slots into tot and cur
+hipError_t launch_sort_counts(dpic_ctx* cx) {
+    SortGeom g;
+    if (!sort_geom(cx, &g)) return hipErrorInvalidValue;
     hipStream_t s = cx->stream;
     const int64_t cap = cx->dims.n_particles;
     const Workspace& w = cx->ws;
@@ -274,20 +281,35 @@ hipError_t launch_sort(dpic_ctx* cx) {
     const int64_t nbt = (int64_t)cx->B * g.nbins;
     uint32_t* tot = w.bins;
     uint32_t* cur = w.bins + nbt;
-    if (nsegs > 0) {
-        hipError_t ez = launch_zero(cx, (double*)tot, (size_t)(nbt + 1) / 2);
-        if (ez != hipSuccess) return ez;
-        if (cx->keys_ready) {
-            hipLaunchKernelGGL((k_sort_count<1, true>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key,
-                               tot);
-        } else {
-            switch (cx->NC) {
-                case 1: hipLaunchKernelGGL((k_sort_count<1, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, tot); break;
-                case 8: hipLaunchKernelGGL((k_sort_count<8, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, tot); break;
-                default: hipLaunchKernelGGL((k_sort_count<16, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, tot); break;
-            }
+    if (nsegs == 0) return hipSuccess;
+    hipError_t ez = launch_zero(cx, (double*)tot, (size_t)(nbt + 1) / 2);
+    if (ez != hipSuccess) return ez;
+    if (cx->keys_ready) {
+        hipLaunchKernelGGL((k_sort_count<1, true>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key,
+                           tot);
+    } else {
+        switch (cx->NC) {
+            case 1: hipLaunchKernelGGL((k_sort_count<1, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, tot); break;
+            case 8: hipLaunchKernelGGL((k_sort_count<8, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, tot); break;
+            default: hipLaunchKernelGGL((k_sort_count<16, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, tot); break;
         }
-        hipLaunchKernelGGL(k_sort_starts, dim3(cx->B), dim3(1024), 0, s, w.set, g.nbins, tot, cur);
+    }
+    hipLaunchKernelGGL(k_sort_starts, dim3(cx->B), dim3(1024), 0, s, w.set, g.nbins, tot, cur);
+    return hipGetLastError();
+}
+
+// scattered: a particle launch has already stored the state in sorted order
+// in the second buffers; otherwise the scatter kernel moves it there.
+hipError_t launch_sort_finish(dpic_ctx* cx, bool scattered) {
+    SortGeom g;
+    if (!sort_geom(cx, &g)) return hipErrorInvalidValue;
+    hipStream_t s = cx->stream;
+    const int64_t cap = cx->dims.n_particles;
+    const Workspace& w = cx->ws;
+    const int nsegs = (int)((cx->used + SEG - 1) / SEG);
+    uint32_t* tot = w.bins;
+    uint32_t* cur = w.bins + (int64_t)cx->B * g.nbins;
+    if (nsegs > 0 && !scattered) {
         switch (cx->NC) {
             case 1: hipLaunchKernelGGL(k_sort_scatter<1>, dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, w.pid, cap, w.set, w.owner, w.key, cur, g.nbins, w.st2, w.pid2); break;
             case 8: hipLaunchKernelGGL(k_sort_scatter<8>, dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, w.pid, cap, w.set, w.owner, w.key, cur, g.nbins, w.st2, w.pid2); break;
@@ -306,6 +328,12 @@ hipError_t launch_sort(dpic_ctx* cx) {
     cx->chunks_valid = true;
     cx->keys_ready = false;
     return hipSuccess;
+}
+
+hipError_t launch_sort(dpic_ctx* cx) {
+    hipError_t e = launch_sort_counts(cx);
+    if (e != hipSuccess) return e;
+    return launch_sort_finish(cx, false);
 }
 
 }  // namespace dpic
