@@ -490,10 +490,11 @@ def main(argv=None):
     torch.cuda.synchronize()
 
     # timed: K steps from the start of the schedule, beam resident in HBM,
-    # with HIP events around the particle launches only (mode 2: every event
-    # record idles the GPU for a few microseconds)
+    # with HIP events around the plain particle launches only (mode 3: every
+    # event record idles the GPU for a few microseconds; the launches that
+    # also write sort keys or store in sorted order are other kernels)
     sim.init_beam(xi, w.sigma, w.sigma_seed())
-    sim.set_option(dpic.OPT_STAGE_TIMING, 2)
+    sim.set_option(dpic.OPT_STAGE_TIMING, 3)
     sim.stage_times()  # reset the stage timers
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -547,7 +548,8 @@ def main(argv=None):
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": _recorded_traffic(),
-            "kernel": "k_particles (gather, kick, two half-maps, deposit)",
+            "kernel": "k_particles_tiled (gather, kick, two half-maps, deposit)",
+            "timed_launches": int(launches[0]),
             "avg_launch_us": part_avg_s * 1e6,
         },
         "stages_ms": {n: float(sms[i]) for i, n in enumerate(dpic.STAGE_TIMER_NAMES)},

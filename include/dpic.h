@@ -224,7 +224,9 @@ int dpic_load_state(dpic_ctx* ctx, const void* dev_buf);
  *    default 10);
  *  DPIC_OPT_STAGE_TIMING = 1 records HIP events around every stage launch of
  *    dpic_step, 2 around the particle stage only (fewer event records in the
- *    stream: each leaves the GPU idle for a few microseconds); read with
+ *    stream: each leaves the GPU idle for a few microseconds), 3 around the
+ *    plain particle launches only (not the launch that also writes the sort
+ *    keys nor the one that stores the particles in sorted order); read with
  *    dpic_stage_times; other values are EINVAL;
  *  DPIC_OPT_CHUNK = particles per work item of the tiled particle kernel
  *    (a multiple of 64 in 128..8192, default 768);

@@ -67,8 +67,11 @@ struct StageTimer {
     int stage;
     hipEvent_t end = nullptr;
     bool counted;  // adds to the stage's launch count (false: a part of a stage that is counted elsewhere)
-    StageTimer(dpic_ctx* c_, int s, bool counted_ = true) : c(c_), stage(s), counted(counted_) {
-        if (c->stage_timing == 0 || (c->stage_timing == 2 && stage != T_PART)) return;
+    // plain: a particle launch that neither writes sort keys nor stores in
+    // sorted order (the only launches mode 3 times)
+    StageTimer(dpic_ctx* c_, int s, bool counted_ = true, bool plain = false) : c(c_), stage(s), counted(counted_) {
+        if (c->stage_timing == 0 || (c->stage_timing >= 2 && stage != T_PART)) return;
+        if (c->stage_timing == 3 && !plain) return;
         auto& pool = c->ev_pool[stage];
         const size_t i = c->ev_used[stage];
         if (i >= pool.size()) {
@@ -95,7 +98,7 @@ struct StageTimer {
 // keys: the launch also writes the tile keys of the positions it deposits
 // at, for the sort that follows it.
 int run_particles(dpic_ctx* c, int flags, int e_tau, int map_off, bool keys = false, bool scatter = false) {
-    StageTimer tm(c, T_PART);
+    StageTimer tm(c, T_PART, true, !keys && !scatter);
     HIPCHK(c, launch_particles(c, flags, e_tau, map_off, c->sort_every > 0 && c->chunks_valid, keys, scatter));
     c->keys_ready = keys;
     return DPIC_OK;
@@ -942,7 +945,7 @@ int dpic_set_option(dpic_ctx* c, int option, int64_t value) {
             c->sort_every = value;
             return DPIC_OK;
         case DPIC_OPT_STAGE_TIMING:
-            if (value < 0 || value > 2) return fail(c, DPIC_EINVAL, "stage timing: 0, 1 or 2");
+            if (value < 0 || value > 3) return fail(c, DPIC_EINVAL, "stage timing: 0, 1, 2 or 3");
             c->stage_timing = (int)value;
             return DPIC_OK;
         case DPIC_OPT_CHUNK:

@@ -266,8 +266,18 @@ def test_stage_timing_counts_launches_and_keeps_results():
     ms3, launches3 = part.stage_times()
     assert list(launches3) == [T + len(calls), 0, 0, 0] and ms3[0] > 0.0
     assert_outputs_close(part.emittance(), plain.emittance(), vtol=1e-11, dtol=1e-9)
+    # mode 3 times the plain particle launches only: with a re-sort every 5
+    # steps some launches write keys or store in sorted order
+    plain3 = make_sim(w, sort_every=5)
+    plain3.set_option(dpic.OPT_STAGE_TIMING, 3)
+    plain3.stage_times()
+    for c in calls:
+        plain3.step(c)
+    ms4, launches4 = plain3.stage_times()
+    assert 0 < launches4[0] < T + len(calls) and list(launches4[1:]) == [0, 0, 0] and ms4[0] > 0.0
+    assert_outputs_close(plain3.emittance(), plain.emittance(), vtol=1e-11, dtol=1e-9)
     with pytest.raises(dpic.DpicError):
-        part.set_option(dpic.OPT_STAGE_TIMING, 3)
+        part.set_option(dpic.OPT_STAGE_TIMING, 4)
 
 
 def test_autotune_keeps_the_state_and_picks_a_candidate():
