@@ -221,7 +221,7 @@ int dpic_load_state(dpic_ctx* ctx, const void* dev_buf);
 /*
  * Options:
  *  DPIC_OPT_SORT_EVERY = re-sort particles by grid tile every k steps (0 = never,
- *    default 10);
+ *    default 5);
  *  DPIC_OPT_STAGE_TIMING = 1 records HIP events around every stage launch of
  *    dpic_step, 2 around the particle stage only (fewer event records in the
  *    stream: each leaves the GPU idle for a few microseconds), 3 around the

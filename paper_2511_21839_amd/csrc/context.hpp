@@ -165,7 +165,7 @@ struct dpic_ctx {
     int64_t steps_done = 0;
     bool swapped = false;             // ws.st holds the second state buffer
     // options
-    int64_t sort_every = 10;
+    int64_t sort_every = 5;
     int64_t chunk = dpic::TILE_CHUNK;  // particles per tiled work item
     int64_t part_blocks = 0;           // workgroups of the tiled particle kernel (0: resident capacity)
     bool chunks_valid = false;  // the tiled work list matches the stored order

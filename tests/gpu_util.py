@@ -17,7 +17,7 @@ DERIV_RTOL = 1e-9
 
 def make_sim(w, capacity=None, sort_every=None, n_particles=None, xi=None):
     """sort_every None keeps the library default (tiled deposit, re-sort every
-    10 steps); 0 selects the storage-order kernel with global atomics."""
+    5 steps); 0 selects the storage-order kernel with global atomics."""
     from paper_2511_21839_amd import dpic
 
     sim = dpic.Simulation(capacity or w.n_particles, w.ntan, w.grid)

@@ -1,6 +1,6 @@
 """Parity at the benchmark's full size: the 1e6-particle, 64^3-grid workload
 with 7 tangents, in the launch configuration the benchmark times (tiled
-persistent particle kernel, re-sort every 10 steps, default work items).
+persistent particle kernel, re-sort every 5 steps, default work items).
 
 What the oracle can compute at this size is compared element by element:
 each stage on the whole beam, and two whole steps (which run the fused
@@ -48,7 +48,7 @@ def _to_gpu_grid(a):
 
 def _bench_sim(w, xi):
     sim = make_sim(w, xi=xi)
-    return sim  # library defaults: tiled kernel, re-sort every 10 steps
+    return sim  # library defaults: tiled kernel, re-sort every 5 steps
 
 
 def test_c2_stages_match_oracle(c2):
