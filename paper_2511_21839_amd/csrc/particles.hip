@@ -14,6 +14,9 @@
 // workgroup takes one chunk of particles sorted into one grid tile and
 // accumulates the deposit in LDS over the tile's nodes plus a halo, flushing
 // it once.
+// On the step before a re-sort the tiled kernel can store every particle in
+// its sorted slot of the second state buffer (k_particles_sorted), from tile
+// keys written one launch earlier: the sort then needs no pass over the state.
 #include "context.hpp"
 
 namespace dpic {

@@ -14,6 +14,11 @@
 //   scatter: each block claims a run of slots per bin (global atomics), then
 //            its particles take slots in it (LDS atomics) and move with all
 //            channels into the second buffer.
+// In a run of steps the scatter is usually not a pass of its own: the bins
+// are counted (launch_sort_counts) after the particle launch that wrote the
+// keys, and the next particle launch stores every particle in its sorted
+// slot itself (PF_SCATTER in particles.hip); launch_sort_finish then builds
+// the work list and swaps the buffers.
 // The order of particles inside a bin is not fixed. The original particle
 // index travels with the state so read-back stays in the original order.
 //
