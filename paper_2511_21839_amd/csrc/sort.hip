@@ -125,19 +125,26 @@ __global__ __launch_bounds__(1024) void k_sort_starts(const SettingDev* __restri
     const int64_t off = set[b].off;
     uint32_t* tb = tot + (int64_t)b * nbins;
     uint32_t* cb = cur + (int64_t)b * nbins;
+    // at most PS bins per thread; their totals are loaded together (unrolled)
+    // and kept in registers for the second loop
+    constexpr int PS = (NUM_TILE_BINS_MAX + 1 + 1023) / 1024;
     const int per = (nbins + 1023) / 1024;
     const int f0 = threadIdx.x * per;
+    uint32_t v[PS];
     uint32_t s = 0;
-    for (int i = 0; i < per; ++i)
-        if (f0 + i < nbins) s += tb[f0 + i];
+#pragma unroll
+    for (int i = 0; i < PS; ++i) {
+        v[i] = (i < per && f0 + i < nbins) ? tb[f0 + i] : 0u;
+        s += v[i];
+    }
     uint32_t run = (uint32_t)off + block_excl_scan_1024(s, sh, nullptr);
-    for (int i = 0; i < per; ++i) {
+#pragma unroll
+    for (int i = 0; i < PS; ++i) {
         const int f = f0 + i;
-        if (f < nbins) {
-            const uint32_t c = tb[f];
+        if (i < per && f < nbins) {
             tb[f] = run;
             cb[f] = run;
-            run += c;
+            run += v[i];
         }
     }
 }
@@ -210,6 +217,34 @@ __global__ __launch_bounds__(1024) void k_build_chunks(const SettingDev* __restr
     const int nf = nbins * nb;
     const int per = (nf + 1023) / 1024;
     const int f0 = threadIdx.x * per;
+    constexpr int PMAX = 8;
+    if (per <= PMAX) {
+        // up to PMAX bins per thread (every single-setting grid): their
+        // ranges are loaded once, all in flight together, and kept in
+        // registers for the writes
+        int64_t ba[PMAX], be[PMAX];
+        uint32_t s = 0;
+#pragma unroll
+        for (int i = 0; i < PMAX; ++i) {
+            ba[i] = be[i] = 0;
+            if (i < per && f0 + i < nf) bin_range(set, starts, nbins, f0 + i, &ba[i], &be[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < PMAX; ++i) s += (uint32_t)((be[i] - ba[i] + chunk - 1) / chunk);
+        uint32_t total = 0;
+        uint32_t run = block_excl_scan_1024(s, sh, &total);
+#pragma unroll
+        for (int i = 0; i < PMAX; ++i) {
+            const int f = f0 + i;
+            const int b = f / nbins;
+            for (int64_t q = ba[i]; q < be[i]; q += chunk) {
+                const int64_t cnt = (be[i] - q) < chunk ? (be[i] - q) : chunk;
+                chunks[run++] = make_int4(f - b * nbins, (int)q, (int)cnt, b);
+            }
+        }
+        if (threadIdx.x == 0) *nchunks = total;
+        return;
+    }
     uint32_t s = 0;
     for (int i = 0; i < per; ++i) {
         const int f = f0 + i;
