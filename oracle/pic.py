@@ -34,11 +34,20 @@ The convolution is evaluated with scipy.signal.fftconvolve of the node
 charges with G tabulated on every offset -n..n (a library routine for the
 plain aperiodic sum), then sliced to targets -1..n.
 
-Pins: tests/test_oracle_pic.py and tests/test_oracle_invariants.py (brute-force
-convolution on tiny grids, charge conservation, zero total space-charge
-momentum for value and every derivative, zero self-force, mirror symmetry,
-pairwise Coulomb fields of sparse beams, zero-current closed forms, central
-finite differences of the full run).
+This module is test infrastructure: only the tests, the smoke check and the
+benchmark's CPU-baseline leg use it; the HIP library never does.
+
+Pins: tests/test_oracle_pic.py (brute-force convolution on tiny grids, charge
+conservation, zero total space-charge momentum for value and every
+derivative, zero self-force, mirror symmetry, pairwise Coulomb fields of
+sparse beams); tests/test_oracle_kick.py (the kick as the step applies it:
+one whole step of sparse charges and of a Gaussian bunch against the
+lab-frame Lorentz force of the moving charges, which fixes the coefficient of
+each momentum, the full step tau, the sign and the step-size tangent; the
+centred emittance against numpy's covariance determinant, shift invariance
+and the raw form of a zero-mean beam); tests/test_oracle_lattice.py
+(zero-current closed forms); tests/test_oracle_fd.py (central finite
+differences of the full run).
 """
 from __future__ import annotations
 

@@ -48,6 +48,8 @@ def _compare_run(w, sim, ref):
     assert_particles_close(sim.particles(), ref.particles)
     assert_moments_close(sim.moments(), ref.moments, ref.particles)
     assert_outputs_close(sim.emittance(), ref.emittance, what="emittance")
+    assert_outputs_close(sim.emittance(centred=True), pic.emittance(ref.moments, centred=True),
+                         what="centred emittance")
     oob, steps, ext = sim.counters()
     assert oob == ref.out_of_box
     assert steps == ref.steps
@@ -231,3 +233,22 @@ def test_c1_full_run_matches_oracle():
     sim = make_sim(w, sort_every=10)
     sim.step(w.total_steps())
     _compare_run(w, sim, _oracle(w))
+
+
+def test_off_centre_beam_centred_emittance():
+    """A beam displaced by half a sigma in x and y (and by 0.2 sigma in the
+    momenta): the centred emittance differs from the raw one, and both
+    match the oracle."""
+    w = synth.tiny(n_particles=2500, grid=16, steps_per_element=4)
+    w = w.with_(bunch_charge_C=w.bunch_charge_C * 5)
+    xi = w.xi()
+    xi[:, 0] += 0.5
+    xi[:, 2] -= 0.5
+    xi[:, 1] += 0.2
+    xi[:, 3] += 0.2
+    sim = make_sim(w, xi=xi)
+    sim.step(w.total_steps())
+    ref = pic.simulate_workload(w, xi=xi)
+    _compare_run(w, sim, ref)
+    raw, cen = pic.emittance(ref.moments), pic.emittance(ref.moments, centred=True)
+    assert np.abs(raw[:2, 0] - cen[:2, 0]).min() > 1e-2 * cen[:2, 0].min()

@@ -1,4 +1,5 @@
-"""Pins of the oracle's PIC stages: deposit, solve, field, gather, kick.
+"""Pins of the oracle's PIC stages: deposit, solve, field, gather (the kick as
+the step applies it is pinned in test_oracle_kick.py).
 
 Every check below is fixed by mathematics independent of the code under test:
 brute-force sums, exactness of linear interpolation and of central
