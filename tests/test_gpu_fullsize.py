@@ -3,9 +3,13 @@ with 7 tangents, in the launch configuration the benchmark times (tiled
 persistent particle kernel, re-sort every 5 steps, default work items).
 
 What the oracle can compute at this size is compared element by element:
-each stage on the whole beam, and two whole steps (which run the fused
-gather/kick/map/deposit kernel) for every particle. The full 2000-step run
-is checked through properties that hold at any size:
+each stage on the whole beam, and the first 20 whole steps for every
+particle. Those 20 steps run every particle launch the benchmark times: the
+plain fused gather/kick/map/deposit launch, the launch that also writes the
+next sort's tile keys, the launch that stores the state in sorted order
+(three folded re-sorts, after steps 5, 10 and 15) and the first sort's
+scatter. The full 2000-step run is checked through properties that hold at
+any size:
   - the space-charge forces sum to zero for the value and every tangent
     (the gather uses the deposit's weights and the convolution kernel is
     even), so the beam centroid follows the zero-current linear transport
@@ -17,8 +21,9 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import green, physics, pic
-from gpu_util import assert_outputs_close, assert_particles_close, make_sim, normwise_err
+from oracle import green, lattice, physics, pic
+from gpu_util import (assert_moments_close, assert_outputs_close, assert_particles_close, make_sim,
+                      normwise_err)
 
 pytestmark = pytest.mark.gpu
 
@@ -95,15 +100,36 @@ def test_c2_stages_match_oracle(c2):
     assert normwise_err(E, want_E) <= 1e-13
 
 
-def test_c2_two_steps_match_oracle(c2):
+@pytest.mark.timeout(900)
+def test_c2_twenty_steps_match_oracle(c2):
+    """Every particle, the moments and both emittances after 20 steps in the
+    benchmark's launch configuration (the oracle takes ~4 s per step here)."""
     w, xi = c2
     sim = _bench_sim(w, xi)
-    sim.step(2)
-    ref = pic.simulate_workload(w, nsteps=2, xi=xi)
-    assert_particles_close(sim.particles(), ref.particles)
-    assert_outputs_close(sim.emittance(), ref.emittance, what="c2 emittance after 2 steps")
+    sim.step(20)
+    got = sim.particles()
+    print("c2: 20 GPU steps done, running the oracle", flush=True)
+    ref = pic.simulate_workload(w, nsteps=20, xi=xi)
+    assert_particles_close(got, ref.particles)
+    assert_moments_close(sim.moments(), ref.moments, ref.particles)
+    assert_outputs_close(sim.emittance(), ref.emittance, what="c2 emittance after 20 steps")
+    assert_outputs_close(sim.emittance(centred=True), pic.emittance(ref.moments, centred=True),
+                         what="c2 centred emittance after 20 steps")
     oob, steps, _ = sim.counters()
-    assert oob == ref.out_of_box == 0 and steps == 2
+    assert oob == ref.out_of_box == 0 and steps == 20
+
+
+def _centroid_transport(w, xi_mean):
+    """Zero-current transport of the beam's initial centroid (value and
+    tangents) over the whole schedule, by the oracle's own maps."""
+    g0, _ = physics.gamma_beta(w.kinetic_eV, w.rest_eV)
+    ps = np.asarray(w.param_seed(), dtype=np.float64)
+    maps = lattice.build_maps(w.lattice, w.params, ps, g0)
+    st = pic.initial_state(np.asarray(xi_mean, dtype=np.float64)[None, :], w.sigma, w.sigma_seed(), w.ntan)
+    for e in lattice.schedule(w.lattice):
+        pic.half_map(st, maps[e])
+        pic.half_map(st, maps[e])
+    return pic.state_array(st)[0]  # (6, 1+ntan)
 
 
 def test_c2_full_run_centroid_follows_linear_transport(c2):
@@ -116,11 +142,7 @@ def test_c2_full_run_centroid_follows_linear_transport(c2):
     oob, steps, _ = sim.counters()
     assert oob == 0 and steps == w.total_steps()
     mom = sim.moments()  # [plane][<u^2>, <u p>, <p^2>, <u>, <p>][channel]
-    point = pic.simulate(xi=xi.mean(axis=0)[None, :], sigma=w.sigma, sigma_seed=w.sigma_seed(),
-                         params=w.params, param_seed=w.param_seed(), lat=w.lattice, grid_n=w.grid, lo=w.lo,
-                         hi=w.hi, kinetic_eV=w.kinetic_eV, rest_eV=w.rest_eV, charge_e=w.charge_e,
-                         bunch_charge_C=0.0, ntan=w.ntan)
-    want = point.particles[0]  # (6, 1+ntan): x, px, y, py, z, delta
+    want = _centroid_transport(w, xi.mean(axis=0))  # (6, 1+ntan): x, px, y, py, z, delta
     for pl in range(3):
         for m, coord in ((3, 2 * pl), (4, 2 * pl + 1)):
             got = mom[pl, m]
@@ -214,11 +236,7 @@ def test_c4_full_batch_sampled_settings():
         one.step(T)
         assert_outputs_close(eb[b], one.emittance(), vtol=1e-10, dtol=1e-9, what=f"setting {b}")
         one.close()
-        point = pic.simulate(xi=ws.xi().mean(axis=0)[None, :], sigma=ws.sigma, sigma_seed=ws.sigma_seed(),
-                             params=ws.params, param_seed=ws.param_seed(), lat=ws.lattice, grid_n=ws.grid,
-                             lo=ws.lo, hi=ws.hi, kinetic_eV=ws.kinetic_eV, rest_eV=ws.rest_eV,
-                             charge_e=ws.charge_e, bunch_charge_C=0.0, ntan=ws.ntan)
-        want = point.particles[0]
+        want = _centroid_transport(ws, ws.xi().mean(axis=0))
         for pl in range(3):
             for m, coord in ((3, 2 * pl), (4, 2 * pl + 1)):
                 second = mb[b, pl, 0] if m == 3 else mb[b, pl, 2]
