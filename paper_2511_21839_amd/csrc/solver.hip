@@ -72,10 +72,69 @@ constexpr int bitrev(int i, int bits) {
     return r;
 }
 
+// cos and sin of 2 pi j / 16: the twiddles inside the register DFTs (R <= 16)
+// are compile-time constants, so they cost neither LDS reads nor registers.
+struct Tw16 {
+    static constexpr double c[16] = {1.0,  0.9238795325112867,  0.7071067811865476,  0.3826834323650898,
+                                     0.0,  -0.3826834323650898, -0.7071067811865476, -0.9238795325112867,
+                                     -1.0, -0.9238795325112867, -0.7071067811865476, -0.3826834323650898,
+                                     0.0,  0.3826834323650898,  0.7071067811865476,  0.9238795325112867};
+    static constexpr double s[16] = {0.0,  0.3826834323650898,  0.7071067811865476,  0.9238795325112867,
+                                     1.0,  0.9238795325112867,  0.7071067811865476,  0.3826834323650898,
+                                     0.0,  -0.3826834323650898, -0.7071067811865476, -0.9238795325112867,
+                                     -1.0, -0.9238795325112867, -0.7071067811865476, -0.3826834323650898};
+};
+
+// (vr, vi) *= exp(-2 pi i J / 16), conjugated for INV; J = 4 (a quarter turn)
+// is a swap with a sign
+template <int J, bool INV>
+__device__ __forceinline__ void mul_w16(double& vr, double& vi) {
+    if constexpr (J == 0) {
+        return;
+    } else if constexpr (J == 4) {
+        const double t = vr;
+        if constexpr (INV) {
+            vr = -vi;
+            vi = t;
+        } else {
+            vr = vi;
+            vi = -t;
+        }
+    } else {
+        constexpr double wr = Tw16::c[J], wi = INV ? Tw16::s[J] : -Tw16::s[J];
+        const double tr = vr * wr - vi * wi;
+        vi = vr * wi + vi * wr;
+        vr = tr;
+    }
+}
+
 // R-point DFT in registers (radix-2 decimation in time, bit-reversed input
-// order, natural output order); W_R^j = tw[j M / R], conjugated for INV.
+// order, natural output order), R in {2, 4, 8, 16}; the butterfly twiddle
+// of stage len, index j is W_len^j = W_16^(16 j / len).
+template <int R, bool INV, int LEN, int J>
+__device__ __forceinline__ void butterflies(double (&ar)[R], double (&ai)[R], int s0) {
+    constexpr int half = LEN / 2;
+    double vr = ar[s0 + J + half], vi = ai[s0 + J + half];
+    mul_w16<J * (16 / LEN), INV>(vr, vi);
+    ar[s0 + J + half] = ar[s0 + J] - vr;
+    ai[s0 + J + half] = ai[s0 + J] - vi;
+    ar[s0 + J] += vr;
+    ai[s0 + J] += vi;
+    if constexpr (J + 1 < half) butterflies<R, INV, LEN, J + 1>(ar, ai, s0);
+}
+
+template <int R, bool INV, int LEN = 2>
+__device__ __forceinline__ void dft_stages(double (&ar)[R], double (&ai)[R]) {
+    if constexpr (LEN <= R) {
+#pragma unroll
+        for (int s0 = 0; s0 < R; s0 += LEN) butterflies<R, INV, LEN, 0>(ar, ai, s0);
+        dft_stages<R, INV, LEN * 2>(ar, ai);
+    }
+}
+
 template <int M, int R, bool INV>
-__device__ __forceinline__ void dft_reg(double (&re)[R], double (&im)[R], const double* twr, const double* twi) {
+__device__ __forceinline__ void dft_reg(double (&re)[R], double (&im)[R]) {
+    static_assert(R == 2 || R == 4 || R == 8 || R == 16, "register DFT of 2, 4, 8 or 16 points");
     constexpr int LOG = ilog2c(R);
     double ar[R], ai[R];
 #pragma unroll
@@ -83,28 +142,7 @@ __device__ __forceinline__ void dft_reg(double (&re)[R], double (&im)[R], const 
         ar[bitrev(i, LOG)] = re[i];
         ai[bitrev(i, LOG)] = im[i];
     }
-#pragma unroll
-    for (int len = 2; len <= R; len <<= 1) {
-        const int half = len >> 1;
-#pragma unroll
-        for (int s = 0; s < R; s += len) {
-#pragma unroll
-            for (int j = 0; j < half; ++j) {
-                double vr = ar[s + j + half], vi = ai[s + j + half];
-                if (j != 0) {
-                    const int m = j * (M / len);
-                    const double wr = twr[m], wi = INV ? -twi[m] : twi[m];
-                    const double tr = vr * wr - vi * wi;
-                    vi = vr * wi + vi * wr;
-                    vr = tr;
-                }
-                ar[s + j + half] = ar[s + j] - vr;
-                ai[s + j + half] = ai[s + j] - vi;
-                ar[s + j] += vr;
-                ai[s + j] += vi;
-            }
-        }
-    }
+    dft_stages<R, INV>(ar, ai);
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         re[i] = ar[i];
@@ -172,7 +210,7 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_cols(const double2* __res
             xi[n1] = v.y;
         }
         __syncthreads();  // twiddle table
-        dft_reg<M, R1, false>(xr, xi, twr, twi);
+        dft_reg<M, R1, false>(xr, xi);
 #pragma unroll
         for (int k1 = 1; k1 < R1; ++k1) twiddle<M, false>(xr[k1], xi[k1], r * k1, twr, twi);
 #pragma unroll
@@ -190,7 +228,7 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_cols(const double2* __res
         for (int g = 0; g < NG; ++g) {
 #pragma unroll
             for (int n2 = 0; n2 < R2; ++n2) hi[g][n2] = ex[((r + R2 * g) * R2 + n2) * BC + b];
-            dft_reg<M, R2, false>(hr[g], hi[g], twr, twi);
+            dft_reg<M, R2, false>(hr[g], hi[g]);
         }
         if (MODE == 0) {
 #pragma unroll
@@ -230,7 +268,7 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_cols(const double2* __res
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
         const int k1 = r + R2 * g;
-        dft_reg<M, R2, true>(hr[g], hi[g], twr, twi);
+        dft_reg<M, R2, true>(hr[g], hi[g]);
 #pragma unroll
         for (int n2 = 0; n2 < R2; ++n2) {
             twiddle<M, true>(hr[g][n2], hi[g][n2], n2 * k1, twr, twi);
@@ -249,7 +287,7 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_cols(const double2* __res
     __syncthreads();
 #pragma unroll
     for (int k1 = 0; k1 < R1; ++k1) xi[k1] = ex[(r * R1 + k1) * BC + b];
-    dft_reg<M, R1, true>(xr, xi, twr, twi);
+    dft_reg<M, R1, true>(xr, xi);
 #pragma unroll
     for (int n1 = 0; n1 < R1; ++n1) {
         const int t = (r + R2 * n1 + a.out_shift) & (M - 1);
@@ -298,7 +336,7 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_rows_fwd(double* __restri
         }
     }
     __syncthreads();  // twiddle table
-    dft_reg<M, R1, false>(xr, xi, twr, twi);
+    dft_reg<M, R1, false>(xr, xi);
 #pragma unroll
     for (int k1 = 1; k1 < R1; ++k1) twiddle<M, false>(xr[k1], xi[k1], r * k1, twr, twi);
     double hr[NG][R2], hi[NG][R2];
@@ -317,7 +355,7 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_rows_fwd(double* __restri
     for (int g = 0; g < NG; ++g) {
 #pragma unroll
         for (int n2 = 0; n2 < R2; ++n2) hi[g][n2] = ex[((r + R2 * g) * R2 + n2) * BC + b];
-        dft_reg<M, R2, false>(hr[g], hi[g], twr, twi);
+        dft_reg<M, R2, false>(hr[g], hi[g]);
     }
     if (!valid) return;
     double2* dst = out + row * M * NCC + j;
@@ -363,7 +401,7 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_rows_inv(const double2* _
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
         const int k1 = r + R2 * g;
-        dft_reg<M, R2, true>(hr[g], hi[g], twr, twi);
+        dft_reg<M, R2, true>(hr[g], hi[g]);
 #pragma unroll
         for (int n2 = 0; n2 < R2; ++n2) {
             twiddle<M, true>(hr[g][n2], hi[g][n2], n2 * k1, twr, twi);
@@ -382,7 +420,7 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_rows_inv(const double2* _
     __syncthreads();
 #pragma unroll
     for (int k1 = 0; k1 < R1; ++k1) xi[k1] = ex[(r * R1 + k1) * BC + b];
-    dft_reg<M, R1, true>(xr, xi, twr, twi);
+    dft_reg<M, R1, true>(xr, xi);
     if (!valid) return;
     double* dst = phi + row * nxo * NC + j;
 #pragma unroll
