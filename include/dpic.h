@@ -212,7 +212,9 @@ int dpic_write_grid(dpic_ctx* ctx, int which, const double* in);
 /*
  * Checkpoint: bytes needed, then copy the particle state, particle order,
  * per-setting particle counts and step counter to / from caller device
- * memory (synchronous).
+ * memory (synchronous). The buffer ends with the particle state in storage
+ * order, [6][capacity][NC] doubles (coordinate, storage slot, channel); the
+ * header and the particle order come before it.
  */
 int dpic_state_bytes(const dpic_ctx* ctx, size_t* bytes);
 int dpic_save_state(dpic_ctx* ctx, void* dev_buf);
@@ -241,13 +243,21 @@ int dpic_load_state(dpic_ctx* ctx, const void* dev_buf);
  *    memory); changing the beam, grid, lattice, particle counts or the
  *    adjoint binding, or loading a state, drops the captured graphs. The
  *    stream bound at dpic_create may be the null stream: capture runs on a
- *    stream the context creates.
+ *    stream the context creates;
+ *  DPIC_OPT_CHECK_FINITE = 1 makes dpic_step synchronise at its end and
+ *    return DPIC_ENONFINITE when any particle launch since dpic_init_beam
+ *    stored a NaN or Inf in the state of any setting (the message names the
+ *    first such step); every particle launch records that step in device
+ *    memory whatever the option, and dpic_read_moments and
+ *    dpic_read_emittance return DPIC_ENONFINITE from it too (after writing
+ *    their output). Default 0: dpic_step stays asynchronous.
  */
 #define DPIC_OPT_SORT_EVERY 1
 #define DPIC_OPT_STAGE_TIMING 2
 #define DPIC_OPT_CHUNK 3
 #define DPIC_OPT_PART_BLOCKS 4
 #define DPIC_OPT_GRAPH 5
+#define DPIC_OPT_CHECK_FINITE 6
 int dpic_set_option(dpic_ctx* ctx, int option, int64_t value);
 int dpic_get_option(const dpic_ctx* ctx, int option, int64_t* value);
 

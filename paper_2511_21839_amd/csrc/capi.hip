@@ -119,6 +119,7 @@ int run_solve_field(dpic_ctx* c);
 // When e_store is given, the step's field is copied there (adjoint replay, B = 1).
 int single_step(dpic_ctx* c, int64_t s, double* e_store) {
     const int e = c->schedule[s];
+    c->cur_step = s;
     const int half = ec_offset(c, e, EC_HALF);
     int r;
     if (c->bunch_charge != 0.0) {
@@ -223,6 +224,22 @@ bool all_finite(const double* v, size_t n) {
     return true;
 }
 
+// DPIC_ENONFINITE when a particle launch of any setting stored a NaN or Inf
+// (the counters record the first such step); synchronises the stream.
+int check_nonfinite(dpic_ctx* c, const char* what) {
+    std::vector<unsigned long long> h((size_t)c->B * CNT_N);
+    HIPCHK(c, hipMemcpyAsync(h.data(), c->ws.counters, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int b = 0; b < c->B; ++b) {
+        const unsigned long long v = h[(size_t)b * CNT_N + CNT_NONFINITE];
+        if (v != 0ull)
+            return fail(c, DPIC_ENONFINITE, "%s: setting %d holds a non-finite value since step %lld", what, b,
+                        (long long)(NONFINITE_BASE - v));
+    }
+    return DPIC_OK;
+}
+
 void clear_graphs(dpic_ctx* c) {
     for (auto& g : c->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -303,6 +320,7 @@ int step_body(dpic_ctx* c, int n) {
         c->steps_done = s1;
         return DPIC_OK;
     }
+    c->cur_step = s0;
     if (sc) {
         HIPCHK(c, launch_zero(c, c->ws.rho, rho_n));
         if ((r = run_particles(c, PF_MAP | PF_DEPOSIT, c->schedule[s0], ec_offset(c, c->schedule[s0], EC_HALF))) != DPIC_OK)
@@ -318,6 +336,7 @@ int step_body(dpic_ctx* c, int n) {
         const int64_t R = c->sort_every;
         bool counted = false;
         for (int64_t s = s0; s < s1; ++s) {
+            c->cur_step = s;
             if ((r = run_solve_field(c)) != DPIC_OK) return r;
             const bool last = (s == s1 - 1);
             const int flags = PF_KICK | PF_MAP | (last ? 0 : PF_DEPOSIT);
@@ -341,6 +360,7 @@ int step_body(dpic_ctx* c, int n) {
         if ((r = run_particles(c, PF_MAP | PF_COUNT, c->schedule[s0], ec_offset(c, c->schedule[s0], EC_HALF))) != DPIC_OK)
             return r;
         for (int64_t s = s0; s < s1; ++s) {
+            c->cur_step = s;
             const bool last = (s == s1 - 1);
             const int flags = PF_MAP | (last ? 0 : PF_COUNT);
             if ((r = run_particles(c, flags, c->schedule[s], closing_map(c, s, last))) != DPIC_OK) return r;
@@ -449,6 +469,12 @@ int init_beams(dpic_ctx* c, const std::vector<int64_t>& nb, const double* xi_dev
     c->steps_done = 0;
     c->beam_init = true;
     c->chunks_valid = false;
+    c->keys_ready = false;
+    // the beam is stored sorted by grid tile from the start (the order the
+    // tiled particle kernel needs), so that the first dpic_step does not
+    // begin with a full sort pass
+    if (c->bunch_charge != 0.0 && c->sort_every > 0 && c->grid_set)
+        if ((r = run_sort(c)) != DPIC_OK) return r;
     return DPIC_OK;
 }
 
@@ -734,8 +760,9 @@ int dpic_step(dpic_ctx* c, int n) {
                     c->schedule.size());
     if (c->adj.bound && c->steps_done + n > c->adj.nmax)
         return fail(c, DPIC_EINVAL, "step: the adjoint workspace covers %d steps", c->adj.nmax);
-    if (c->use_graph && !c->stage_timing) return step_graph(c, n);
-    return step_body(c, n);
+    const int r = (c->use_graph && !c->stage_timing) ? step_graph(c, n) : step_body(c, n);
+    if (r != DPIC_OK || !c->check_finite) return r;
+    return check_nonfinite(c, "step");
 }
 
 int dpic_read_moments(dpic_ctx* c, double* out) {
@@ -746,6 +773,8 @@ int dpic_read_moments(dpic_ctx* c, double* out) {
     HIPCHK(c, hipMemcpyAsync(h.data(), c->ws.mom, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     repack_out(h.data(), (size_t)c->B * MOM_N, c->NC, c->ntan, out);
+    int rc;
+    if ((rc = check_nonfinite(c, "read_moments")) != DPIC_OK) return rc;
     if (!all_finite(out, (size_t)c->B * MOM_N * (c->ntan + 1))) return fail(c, DPIC_ENONFINITE, "read_moments: non-finite moment");
     return DPIC_OK;
 }
@@ -758,6 +787,8 @@ int dpic_read_emittance(dpic_ctx* c, int centred, double* out) {
     std::vector<double> h((size_t)c->B * 6 * NC);
     HIPCHK(c, hipMemcpyAsync(h.data(), c->ws.emit, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    int rc;
+    if ((rc = check_nonfinite(c, "read_emittance")) != DPIC_OK) return rc;
     const size_t per = (size_t)3 * (c->ntan + 1);
     for (int b = 0; b < c->B; ++b) {
         double* o = out + (size_t)b * per;
@@ -966,6 +997,9 @@ int dpic_set_option(dpic_ctx* c, int option, int64_t value) {
             c->use_graph = value != 0;
             if (!c->use_graph) clear_graphs(c);
             return DPIC_OK;
+        case DPIC_OPT_CHECK_FINITE:
+            c->check_finite = value != 0;
+            return DPIC_OK;
         default:
             return fail(c, DPIC_EINVAL, "unknown option %d", option);
     }
@@ -979,6 +1013,7 @@ int dpic_get_option(const dpic_ctx* c, int option, int64_t* value) {
         case DPIC_OPT_CHUNK: *value = c->chunk; return DPIC_OK;
         case DPIC_OPT_PART_BLOCKS: *value = c->part_blocks; return DPIC_OK;
         case DPIC_OPT_GRAPH: *value = c->use_graph; return DPIC_OK;
+        case DPIC_OPT_CHECK_FINITE: *value = c->check_finite; return DPIC_OK;
         default: return DPIC_EINVAL;
     }
 }

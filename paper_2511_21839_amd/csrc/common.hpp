@@ -115,7 +115,10 @@ enum PartFlags {
     PF_SCATTER = 64  // tiled kernel: store each particle in its sorted slot of the second state buffer
 };
 
-enum CounterSlot { CNT_OUTSIDE = 0, CNT_EXT_X = 1, CNT_EXT_Y = 2, CNT_EXT_Z = 3, CNT_N = 8 };
+// CNT_NONFINITE: 0 while every stored state value is finite, else
+// NONFINITE_BASE - (first step whose particle launch stored a NaN or Inf)
+enum CounterSlot { CNT_OUTSIDE = 0, CNT_EXT_X = 1, CNT_EXT_Y = 2, CNT_EXT_Z = 3, CNT_NONFINITE = 4, CNT_N = 8 };
+constexpr unsigned long long NONFINITE_BASE = 1ull << 62;
 
 constexpr int MOM_N = 15;  // 3 planes x 5 moments
 

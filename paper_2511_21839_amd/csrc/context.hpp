@@ -163,6 +163,7 @@ struct dpic_ctx {
     int64_t used = 0;                 // storage slots in use (off + n of the last setting)
     std::vector<int64_t> nb, off;     // per setting
     int64_t steps_done = 0;
+    int64_t cur_step = 0;             // schedule step of the particle launch being enqueued
     bool swapped = false;             // ws.st holds the second state buffer
     // options
     int64_t sort_every = 5;
@@ -172,6 +173,7 @@ struct dpic_ctx {
     bool keys_ready = false;    // ws.key holds every particle's tile key (written by the last particle launch)
     int stage_timing = 0;  // 0 off, 1 every stage, 2 the particle stage only
     bool use_graph = false;
+    bool check_finite = false;  // dpic_step synchronises and reports non-finite state values
     int cu_count = 0;
     dpic::AdjointWs adj;
     // captured runs

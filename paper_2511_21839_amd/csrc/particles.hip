@@ -363,6 +363,7 @@ struct PartArgs {
     double* st_out;         // PF_SCATTER: second state buffer, sorted order
     const int32_t* pid_in;  // PF_SCATTER: original rows, stored order
     int32_t* pid_out;       //             and sorted order
+    int64_t step;           // schedule step of this launch (for the non-finite record)
 };
 
 // the arrays and charge of one setting
@@ -501,6 +502,22 @@ __device__ __forceinline__ void extent_flush(unsigned long long* cnt, double e0,
     __syncthreads();  // sext is reused
 }
 
+// Record the launch's step in the setting's non-finite counter when any lane
+// of the wave stored a NaN or Inf (all 64 lanes take part).
+__device__ __forceinline__ void nonfinite_flush_wave(unsigned long long* cnt, bool nf, int64_t step) {
+    const unsigned long long m = __ballot(nf);
+    if (m != 0ull && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)m) - 1))
+        atomicMax(cnt + CNT_NONFINITE, NONFINITE_BASE - (unsigned long long)step);
+}
+
+template <int K>
+__device__ __forceinline__ bool qd_nonfinite(const QD<K>& x) {
+    bool bad = !__builtin_isfinite(x.v);
+#pragma unroll
+    for (int k = 0; k < K; ++k) bad |= !__builtin_isfinite(x.t[k]);
+    return bad;
+}
+
 struct CellPos {
     double sx, sy, sz;
     int ix, iy, iz;
@@ -573,7 +590,8 @@ template <int NC, int F, bool TILED, class Dest>
 __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& sv, const double* __restrict__ smap,
                                               const double* __restrict__ stau, int64_t p, Dest dest, int q,
                                               const RawState<LaneGroup<NC>::K>& raw, double* lr, const double* le, int ox,
-                                              int oy, int oz, int oze, bool use_tile, double& e0, double& e1, double& e2) {
+                                              int oy, int oz, int oze, bool use_tile, double& e0, double& e1, double& e2,
+                                              bool& nf) {
     constexpr int G = LaneGroup<NC>::G, K = LaneGroup<NC>::K;
     const int64_t cs = a.cap * NC;
     QD<K> x = raw_to_qd<K, G>(raw.r[0], q), px = raw_to_qd<K, G>(raw.r[1], q), y = raw_to_qd<K, G>(raw.r[2], q);
@@ -708,6 +726,7 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& 
         e1 = fmax(e1, fabs(y.v));
         e2 = fmax(e2, fabs(z.v));
     }
+    nf |= qd_nonfinite(x) | qd_nonfinite(px) | qd_nonfinite(y) | qd_nonfinite(py) | qd_nonfinite(z) | qd_nonfinite(d);
     // the slot the state goes to: p, or with PF_SCATTER its sorted slot
     double* sp = ((F & PF_SCATTER) ? a.st_out : a.st) + dest() * NC;
     qd_store(sp, x, q);
@@ -745,10 +764,13 @@ __global__ __launch_bounds__(PART_THREADS) void k_particles(PartArgs a) {
     const int64_t p = p0 + threadIdx.x / G;
     const int q = (int)(threadIdx.x % G);
     double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+    bool nf = false;
     if (p - sd.off < sd.n) {
         const RawState<LaneGroup<NC>::K> raw = load_raw<NC>(a, p, q);
-        particle_body<NC, F, false>(a, sv, smap, stau, p, [p]() { return p; }, q, raw, nullptr, nullptr, 0, 0, 0, 0, false, e0, e1, e2);
+        particle_body<NC, F, false>(a, sv, smap, stau, p, [p]() { return p; }, q, raw, nullptr, nullptr, 0, 0, 0, 0, false, e0, e1, e2,
+                                    nf);
     }
+    nonfinite_flush_wave(sv.cnt, nf, a.step);
     if (F & (PF_DEPOSIT | PF_COUNT)) extent_flush(sv.cnt, e0, e1, e2, sext);
 }
 
@@ -792,11 +814,16 @@ __device__ __forceinline__ void tiled_body(const PartArgs& a, const TiledArgs& t
     SetView sv{nullptr, nullptr, nullptr, 0.0};
     const int i0 = threadIdx.x / G;
     double e0 = 0.0, e1 = 0.0, e2 = 0.0;  // this thread's extents in the current setting
+    bool nf = false;                      // and whether it stored a non-finite value there
 #pragma unroll 1
     for (uint32_t ci = blockIdx.x; ci < nck; ci += gridDim.x) {
         const int4 ck = t.chunks[ci];
         if (ci != blockIdx.x) __syncthreads();  // the previous item's flush is done with lr and smap
         if (ck.w != cur) {
+            if (cur >= 0) {
+                nonfinite_flush_wave(sv.cnt, nf, a.step);
+                nf = false;
+            }
             if ((F & (PF_DEPOSIT | PF_COUNT)) && cur >= 0) {
                 extent_flush_wave(sv.cnt, e0, e1, e2);
                 e0 = e1 = e2 = 0.0;
@@ -899,7 +926,7 @@ __device__ __forceinline__ void tiled_body(const PartArgs& a, const TiledArgs& t
                         return p;
                 };
                 particle_body<NC, F, true>(a, sv, smap, stau, p, dest, q, curst, lr, le, ox, oy, oz, oze, use_tile,
-                                           e0, e1, e2);
+                                           e0, e1, e2, nf);
             }
         }
         if (F & PF_DEPOSIT) {
@@ -923,6 +950,7 @@ __device__ __forceinline__ void tiled_body(const PartArgs& a, const TiledArgs& t
             }
         }
     }
+    if (cur >= 0) nonfinite_flush_wave(sv.cnt, nf, a.step);
     if ((F & (PF_DEPOSIT | PF_COUNT)) && cur >= 0) extent_flush(sv.cnt, e0, e1, e2, sext);
 }
 
@@ -1052,6 +1080,7 @@ static hipError_t launch_particles_nc(dpic_ctx* cx, int flags, const PartArgs& a
 hipError_t launch_particles(dpic_ctx* cx, int flags, int e_tau, int map_off, bool tiled, bool write_keys,
                             bool scatter) {
     PartArgs a;
+    a.step = cx->cur_step;
     a.st = cx->ws.st;
     a.cap = cx->dims.n_particles;
     a.used = cx->used;

@@ -222,10 +222,10 @@ def test_single_setting_graph_matches_eager():
 
 
 def _expected_sorts(calls, sort_every):
-    """Re-sorts of dpic_step calls of the given lengths from a fresh beam:
-    one on entry while the work list is stale (only the first call), and one
-    after every step s with (s + 1) % sort_every == 0 except a call's last."""
-    n, s0 = 1, 0
+    """Re-sorts of dpic_step calls of the given lengths from a fresh beam
+    (dpic_init_beam already stored it sorted): one after every step s with
+    (s + 1) % sort_every == 0 except a call's last."""
+    n, s0 = 0, 0
     for c in calls:
         n += sum(1 for s in range(s0, s0 + c - 1) if (s + 1) % sort_every == 0)
         s0 += c
