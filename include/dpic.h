@@ -179,6 +179,23 @@ int dpic_read_moments(dpic_ctx* ctx, double* out);
 int dpic_read_emittance(dpic_ctx* ctx, int centred, double* out);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): the emittances
+ * of dpic_read_emittance, written to caller device memory
+ * out_dev[B][3][1+ntan] (raw when centred == 0, central moments otherwise;
+ * zeros for an empty setting) and enqueued asynchronously on the bound
+ * stream: no host transfer and no synchronisation. The moment partial sums,
+ * moments and emittance duals go to a static device array of the library
+ * (4 MiB per device, held until the process ends) instead of the context
+ * workspace; nothing is allocated. Contexts that need more than 4 MiB
+ * (B * NC * (15 * blocks + 21) doubles, blocks <= 512 partial-sum blocks per
+ * setting, at most 4096 / B) get DPIC_EINVAL. Every call on one GPU shares
+ * that array: calls that overlap on one GPU (other streams, other threads)
+ * race. No non-finite check (that needs the host; dpic_read_emittance does it).
+ */
+int dpic_read_emittance_noalloc(dpic_ctx* ctx, int centred, double* out_dev);
+
+/*
  * Particle state in the original particle order, host out[n][6][1+ntan]
  * (settings back to back in the packed order of dpic_init_beam_batch).
  * Synchronises the stream.

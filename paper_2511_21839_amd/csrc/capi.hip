@@ -593,6 +593,7 @@ int dpic_create(const dpic_dims* dims, void* workspace_dev, size_t workspace_byt
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         c->cu_count = 0;
+    c->device = dev;
     (void)particle_resident_blocks(c);  // occupancy queries happen here, never under capture
     *out = c;
     return DPIC_OK;

@@ -175,6 +175,7 @@ struct dpic_ctx {
     bool use_graph = false;
     bool check_finite = false;  // dpic_step synchronises and reports non-finite state values
     int cu_count = 0;
+    int device = 0;  // the device current at dpic_create
     dpic::AdjointWs adj;
     // captured runs
     uint64_t layout_gen = 1;

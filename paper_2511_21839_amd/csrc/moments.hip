@@ -8,6 +8,10 @@
 // Pass 2: one block adds the partial rows in a fixed order (the result is
 // bitwise reproducible for a given particle order), divides by N and forms
 // the raw and the centred emittances with the dual rules.
+#include <stdio.h>
+
+#include <mutex>
+
 #include "context.hpp"
 
 namespace dpic {
@@ -95,31 +99,128 @@ __global__ void k_moments_final(const double* __restrict__ part, int nblocks, co
     }
 }
 
-hipError_t launch_moments(dpic_ctx* cx) {
+// partial-sum blocks per setting for the context's current beams
+static int moment_blocks(const dpic_ctx* cx) {
     int64_t nmax = 0;
     for (int b = 0; b < cx->B; ++b) nmax = nmax > cx->nb[b] ? nmax : cx->nb[b];
     const int64_t want = (nmax * cx->NC + MOM_THREADS - 1) / MOM_THREADS;
     const int cap_blocks = mom_blocks_for(cx->B);
-    const int nblocks = (int)(want < cap_blocks ? (want < 1 ? 1 : want) : cap_blocks);
+    return (int)(want < cap_blocks ? (want < 1 ? 1 : want) : cap_blocks);
+}
+
+// partials [B][nblocks][MOM_N][NC], moments [B][MOM_N][NC], emittances [B][2][3][NC]
+static hipError_t launch_moments_into(dpic_ctx* cx, int nblocks, double* part, double* mom, double* emit) {
     hipStream_t s = cx->stream;
     const Workspace& w = cx->ws;
     const int64_t cap = cx->dims.n_particles;
     const dim3 g1(nblocks, cx->B), g2(cx->B);
     switch (cx->NC) {
         case 1:
-            hipLaunchKernelGGL(k_moments_partial<1>, g1, dim3(MOM_THREADS), 0, s, w.st, cap, w.set, w.mom_part);
-            hipLaunchKernelGGL(k_moments_final<1>, g2, dim3(256), 0, s, w.mom_part, nblocks, w.set, w.mom, w.emit);
+            hipLaunchKernelGGL(k_moments_partial<1>, g1, dim3(MOM_THREADS), 0, s, w.st, cap, w.set, part);
+            hipLaunchKernelGGL(k_moments_final<1>, g2, dim3(256), 0, s, part, nblocks, w.set, mom, emit);
             break;
         case 8:
-            hipLaunchKernelGGL(k_moments_partial<8>, g1, dim3(MOM_THREADS), 0, s, w.st, cap, w.set, w.mom_part);
-            hipLaunchKernelGGL(k_moments_final<8>, g2, dim3(256), 0, s, w.mom_part, nblocks, w.set, w.mom, w.emit);
+            hipLaunchKernelGGL(k_moments_partial<8>, g1, dim3(MOM_THREADS), 0, s, w.st, cap, w.set, part);
+            hipLaunchKernelGGL(k_moments_final<8>, g2, dim3(256), 0, s, part, nblocks, w.set, mom, emit);
             break;
         default:
-            hipLaunchKernelGGL(k_moments_partial<16>, g1, dim3(MOM_THREADS), 0, s, w.st, cap, w.set, w.mom_part);
-            hipLaunchKernelGGL(k_moments_final<16>, g2, dim3(256), 0, s, w.mom_part, nblocks, w.set, w.mom, w.emit);
+            hipLaunchKernelGGL(k_moments_partial<16>, g1, dim3(MOM_THREADS), 0, s, w.st, cap, w.set, part);
+            hipLaunchKernelGGL(k_moments_final<16>, g2, dim3(256), 0, s, part, nblocks, w.set, mom, emit);
             break;
     }
     return hipGetLastError();
 }
 
+hipError_t launch_moments(dpic_ctx* cx) {
+    return launch_moments_into(cx, moment_blocks(cx), cx->ws.mom_part, cx->ws.mom, cx->ws.emit);
+}
+
+// ---------------------------------------------------------------- allocation-free read-back
+// The emittance read-back of dpic_read_emittance_noalloc stages its partial
+// sums, moments and emittance duals in this array (one copy per device,
+// held until the process ends) instead of the context workspace, and writes
+// its result to caller device memory. Host code never uses the array's name
+// as an address: it takes the device address from hipGetSymbolAddress, once
+// per device, with that device current.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)4 << 20;
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[NOALLOC_MAX_DEVICES];
+
+// emit [B][2][3][NC] -> out [B][3][1 + ntan] (raw or centred), zeros for an
+// empty setting; one block per setting
+template <int NC>
+__global__ void k_emittance_out(const double* __restrict__ emit, const SettingDev* __restrict__ set, int ntan,
+                                int centred, double* __restrict__ out) {
+    const int b = blockIdx.x;
+    const bool empty = set[b].n == 0;
+    const double* e = emit + ((size_t)b * 6 + (centred ? 3 : 0)) * NC;
+    double* o = out + (size_t)b * 3 * (ntan + 1);
+    for (int i = threadIdx.x; i < 3 * (ntan + 1); i += blockDim.x) {
+        const int pl = i / (ntan + 1), ch = i % (ntan + 1);
+        o[i] = empty ? 0.0 : e[pl * NC + ch];
+    }
+}
+
 }  // namespace dpic
+
+using namespace dpic;
+
+extern "C" int dpic_read_emittance_noalloc(dpic_ctx* c, int centred, double* out_dev) {
+    if (!c || !out_dev) return DPIC_EINVAL;
+    if (!c->beam_init) {
+        c->err = "read_emittance_noalloc: no beam";
+        return DPIC_ESTATE;
+    }
+    if (c->device < 0 || c->device >= NOALLOC_MAX_DEVICES) {
+        c->err = "read_emittance_noalloc: device index beyond the library's table";
+        return DPIC_EUNSUPPORTED;
+    }
+    const int nblocks = moment_blocks(c);
+    const size_t per = (size_t)c->B * c->NC;
+    const size_t need = (per * nblocks * MOM_N + per * MOM_N + per * 6) * sizeof(double);
+    if (need > NOALLOC_SCRATCH_BYTES) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "read_emittance_noalloc: needs %zu bytes of scratch, the static array holds %zu",
+                 need, NOALLOC_SCRATCH_BYTES);
+        c->err = buf;
+        return DPIC_EINVAL;
+    }
+    double* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_dev[c->device]) {
+            int cur = 0;
+            hipError_t e = hipGetDevice(&cur);
+            if (e == hipSuccess && cur != c->device) e = hipSetDevice(c->device);
+            void* p = nullptr;
+            if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (cur != c->device) (void)hipSetDevice(cur);
+            if (e != hipSuccess || !p) {
+                c->err = std::string("read_emittance_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e);
+                return DPIC_EHIP;
+            }
+            g_scratch_dev[c->device] = (double*)p;
+        }
+        base = g_scratch_dev[c->device];
+    }
+    double* part = base;
+    double* mom = part + per * nblocks * MOM_N;
+    double* emit = mom + per * MOM_N;
+    hipError_t e = launch_moments_into(c, nblocks, part, mom, emit);
+    if (e == hipSuccess) {
+        switch (c->NC) {
+            case 1: hipLaunchKernelGGL(k_emittance_out<1>, dim3(c->B), dim3(64), 0, c->stream, emit, c->ws.set, c->ntan, centred, out_dev); break;
+            case 8: hipLaunchKernelGGL(k_emittance_out<8>, dim3(c->B), dim3(64), 0, c->stream, emit, c->ws.set, c->ntan, centred, out_dev); break;
+            default: hipLaunchKernelGGL(k_emittance_out<16>, dim3(c->B), dim3(64), 0, c->stream, emit, c->ws.set, c->ntan, centred, out_dev); break;
+        }
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) {
+        c->err = std::string("read_emittance_noalloc: ") + hipGetErrorString(e);
+        return DPIC_EHIP;
+    }
+    return DPIC_OK;
+}

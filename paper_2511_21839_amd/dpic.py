@@ -40,7 +40,7 @@ SYMBOLS = (
     "dpic_version", "dpic_query_workspace", "dpic_create", "dpic_destroy", "dpic_last_error",
     "dpic_set_beam", "dpic_set_grid", "dpic_set_lattice", "dpic_set_params", "dpic_set_params_batch",
     "dpic_init_beam", "dpic_init_beam_batch", "dpic_step", "dpic_read_moments", "dpic_read_emittance",
-    "dpic_read_particles", "dpic_counters", "dpic_batch_counters", "dpic_stage", "dpic_read_grid",
+    "dpic_read_emittance_noalloc", "dpic_read_particles", "dpic_counters", "dpic_batch_counters", "dpic_stage", "dpic_read_grid",
     "dpic_write_grid", "dpic_state_bytes", "dpic_save_state", "dpic_load_state", "dpic_set_option",
     "dpic_get_option", "dpic_autotune", "dpic_stage_times",
     "dpic_adjoint_query", "dpic_adjoint_bind", "dpic_adjoint_backward",
@@ -95,6 +95,7 @@ _SIGS = {
     "dpic_get_option": ([_P, ctypes.c_int, _I64], ctypes.c_int),
     "dpic_autotune": ([_P, _P, ctypes.c_size_t, ctypes.c_int, _I64, _D], ctypes.c_int),
     "dpic_stage_times": ([_P, _D, _I64], ctypes.c_int),
+    "dpic_read_emittance_noalloc": ([_P, ctypes.c_int, _P], ctypes.c_int),
     "dpic_adjoint_query": ([ctypes.POINTER(dpic_dims), ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
                            ctypes.c_int),
     "dpic_adjoint_bind": ([_P, _P, ctypes.c_size_t, ctypes.c_int, ctypes.c_int], ctypes.c_int),
@@ -249,6 +250,12 @@ def dpic_read_emittance(ctx, ntan: int, centred: bool = False, nbatch: int = 1) 
     out = np.empty((nbatch, 3, ntan + 1))
     _check(ctx, lib().dpic_read_emittance(ctx, int(bool(centred)), _dp(out)))
     return out
+
+
+def dpic_read_emittance_noalloc(ctx, centred: bool, out_dev_ptr: int):
+    """Emittances into caller device memory [B][3][1+ntan] (float64),
+    asynchronous, with no allocation (the library's static scratch)."""
+    _check(ctx, lib().dpic_read_emittance_noalloc(ctx, int(bool(centred)), _P(out_dev_ptr)))
 
 
 def dpic_read_particles(ctx, n: int, ntan: int) -> np.ndarray:
