@@ -3,8 +3,7 @@
  * of a line of drifts and hard-edge quadrupoles and their derivatives with
  * respect to lattice parameters (dual numbers, Sec. 2), and the paper's
  * matching example (Sec. 3): quadrupole strengths that carry given Twiss
- * parameters into target ones, minimised by BFGS (using the derivatives)
- * or by the derivative-free Nelder-Mead simplex.
+ * parameters into target ones, minimised by BFGS using the derivatives.
  *
  * Twiss transport with the plane's transfer matrix m (Sec. 3):
  *   beta1 = m11^2 beta0 - 2 m11 m12 alpha0 + m12^2 gamma0,
@@ -31,9 +30,6 @@
 extern "C" {
 #endif
 
-#define DTWISS_BFGS 0
-#define DTWISS_NELDER_MEAD 1
-
 /* Device workspace bytes for evaluations of up to nb parameter vectors. */
 int dtwiss_query_workspace(int nb, size_t* bytes);
 
@@ -50,15 +46,15 @@ int dtwiss_eval(void* workspace_dev, size_t bytes, void* hip_stream, int n_elem,
 
 /*
  * Minimise the matching objective over the np parameters from p0 [np] with
- * BFGS (backtracking Armijo line search, inverse-Hessian update) or
- * Nelder-Mead (initial simplex steps `step`), until f < tol or max_eval
+ * BFGS on the objective and its dual-number gradient (backtracking Armijo
+ * line search, inverse-Hessian update), until f < tol or max_eval
  * evaluations. Writes p_out [np], f_out, the evaluation count and, if not
  * NULL, history [max_eval] (f after every evaluation). Synchronous.
  */
-int dtwiss_match(void* workspace_dev, size_t bytes, void* hip_stream, int method, int n_elem, const int* kind,
-                 const double* L, const double* k, const int* L_param, const int* k_param, int np, const double* p0,
-                 const double* twiss0, const double* target, double step, double tol, int max_eval, double* p_out,
-                 double* f_out, int* n_eval, double* history);
+int dtwiss_match(void* workspace_dev, size_t bytes, void* hip_stream, int n_elem, const int* kind, const double* L,
+                 const double* k, const int* L_param, const int* k_param, int np, const double* p0,
+                 const double* twiss0, const double* target, double tol, int max_eval, double* p_out, double* f_out,
+                 int* n_eval, double* history);
 
 #ifdef __cplusplus
 }

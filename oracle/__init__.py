@@ -20,7 +20,7 @@ Modules
   pipe2d   -- the paper's own 2D PIC: rectangular conducting pipe, sine-series
               Poisson solver, bilinear deposit, perveance kick (Sec. 4)
   twiss    -- single-particle Twiss transport, matched Twiss of a cell, the
-              matching objective and the BFGS / Nelder-Mead optimisers (Sec. 3)
+              matching objective and its BFGS optimiser (Sec. 3)
   mlp      -- the emittance surrogate: MLP with its input Jacobian, the
               Sobolev loss and its weight gradient (exact, and with the
               rounding points of a BF16 matrix-core implementation)

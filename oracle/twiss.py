@@ -1,7 +1,7 @@
 """Single-particle linear optics: transfer matrices of a lattice, Twiss
 parameters and their derivatives with respect to lattice parameters, and
 the matching objective of the paper's third example (Sec. 3), minimised by
-BFGS and by the Nelder-Mead simplex.
+BFGS.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -17,15 +17,14 @@ Matching objective (Sec. 3):
     f(k) = (beta_x - beta_xt)^2 / beta_xt^2 + (alpha_x - alpha_xt)^2
          + (beta_y - beta_yt)^2 / beta_yt^2 + (alpha_y - alpha_yt)^2.
 
-The optimisers are the textbook algorithms: BFGS with the inverse-Hessian
-update H <- (I - r s y^T) H (I - r y s^T) + r s s^T, r = 1/(y^T s), and a
-backtracking Armijo line search; Nelder-Mead with reflection 1, expansion 2,
-contraction 1/2 and shrink 1/2.
+The optimiser is textbook BFGS with the inverse-Hessian update
+H <- (I - r s y^T) H (I - r y s^T) + r s s^T, r = 1/(y^T s), and a
+backtracking Armijo line search.
 
 Pins (tests/test_oracle_twiss.py): Twiss transport against sigma-matrix
 transport M Sigma M^T (a different route); the matched Twiss are invariant
-over one cell; derivatives against central differences; both optimisers on
-a quadratic and on the Rosenbrock function.
+over one cell; derivatives against central differences; BFGS on a quadratic
+and on the Rosenbrock function.
 """
 from __future__ import annotations
 
@@ -124,41 +123,3 @@ def bfgs(fg: Callable[[np.ndarray], Tuple[float, np.ndarray]], x0, tol=1e-12, ma
         if f < tol:
             break
     return x, f, len(hist), hist
-
-
-def nelder_mead(fn: Callable[[np.ndarray], float], x0, step, tol=1e-12, max_eval=5000):
-    x0 = np.asarray(x0, dtype=np.float64)
-    n = x0.size
-    pts = [x0] + [x0 + step * np.eye(n)[i] for i in range(n)]
-    vals = [fn(p) for p in pts]
-    hist = list(vals)
-    while len(hist) < max_eval:
-        order = np.argsort(vals)
-        pts = [pts[i] for i in order]
-        vals = [vals[i] for i in order]
-        if vals[0] < tol:
-            break
-        c = np.mean(pts[:-1], axis=0)
-        xr = c + (c - pts[-1])
-        fr = fn(xr)
-        hist.append(fr)
-        if fr < vals[0]:
-            xe = c + 2.0 * (c - pts[-1])
-            fe = fn(xe)
-            hist.append(fe)
-            pts[-1], vals[-1] = (xe, fe) if fe < fr else (xr, fr)
-        elif fr < vals[-2]:
-            pts[-1], vals[-1] = xr, fr
-        else:
-            xc = c + 0.5 * (pts[-1] - c)
-            fc = fn(xc)
-            hist.append(fc)
-            if fc < vals[-1]:
-                pts[-1], vals[-1] = xc, fc
-            else:
-                for i in range(1, n + 1):
-                    pts[i] = pts[0] + 0.5 * (pts[i] - pts[0])
-                    vals[i] = fn(pts[i])
-                    hist.append(vals[i])
-    i = int(np.argmin(vals))
-    return pts[i], vals[i], len(hist), hist

@@ -1,6 +1,6 @@
 // Twiss parameters of a line and their parameter derivatives (dual numbers,
 // NC = 16 lanes per parameter vector), the matching objective, and the BFGS
-// and Nelder-Mead drivers of the matching example. C ABI: include/dtwiss.h.
+// driver of the matching example. C ABI: include/dtwiss.h.
 #include <math.h>
 #include <string.h>
 
@@ -182,13 +182,12 @@ int dtwiss_eval(void* ws, size_t bytes, void* stream, int n_elem, const int* kin
     return eval(ws, bytes, (hipStream_t)stream, ln, en, np, nb, p, twiss, f);
 }
 
-int dtwiss_match(void* ws, size_t bytes, void* stream, int method, int n_elem, const int* kind, const double* L,
-                 const double* k, const int* L_param, const int* k_param, int np, const double* p0, const double* twiss0,
-                 const double* target, double step, double tol, int max_eval, double* p_out, double* f_out, int* n_eval,
+int dtwiss_match(void* ws, size_t bytes, void* stream, int n_elem, const int* kind, const double* L, const double* k,
+                 const int* L_param, const int* k_param, int np, const double* p0, const double* twiss0,
+                 const double* target, double tol, int max_eval, double* p_out, double* f_out, int* n_eval,
                  double* history) {
     using namespace dtwiss;
     if (!p0 || !twiss0 || !target || !p_out || np < 1 || np > 15 || max_eval < 2) return DPIC_EINVAL;
-    if (method != DTWISS_BFGS && method != DTWISS_NELDER_MEAD) return DPIC_EINVAL;
     Line ln;
     int r = make_line(n_elem, kind, L, k, L_param, k_param, np, &ln);
     if (r != DPIC_OK) return r;
@@ -215,116 +214,55 @@ int dtwiss_match(void* ws, size_t bytes, void* stream, int method, int n_elem, c
     };
     std::vector<double> x(p0, p0 + np);
     double fx;
-    if (method == DTWISS_BFGS) {
-        std::vector<double> g(np), gn(np), d(np), xn(np), H((size_t)np * np, 0.0);
-        for (int i = 0; i < np; ++i) H[(size_t)i * np + i] = 1.0;
-        fx = fg(x, &g);
-        while (evals < max_eval && fx >= tol && err == DPIC_OK) {
-            double gd = 0.0;
-            for (int i = 0; i < np; ++i) {
-                double s = 0.0;
-                for (int j = 0; j < np; ++j) s -= H[(size_t)i * np + j] * g[j];
-                d[i] = s;
-                gd += g[i] * s;
-            }
-            if (gd >= 0) {  // not a descent direction: restart from steepest descent
-                std::fill(H.begin(), H.end(), 0.0);
-                for (int i = 0; i < np; ++i) H[(size_t)i * np + i] = 1.0, d[i] = -g[i];
-                gd = 0.0;
-                for (int i = 0; i < np; ++i) gd -= g[i] * g[i];
-            }
-            double t = 1.0, fn = fx;
-            while (evals < max_eval) {
-                for (int i = 0; i < np; ++i) xn[i] = x[i] + t * d[i];
-                fn = fg(xn, &gn);
-                if (fn <= fx + 1e-4 * t * gd || t < 1e-12) break;
-                t *= 0.5;
-            }
-            // BFGS inverse-Hessian update with s = xn - x, y = gn - g
-            std::vector<double> s(np), y(np), Hy(np);
-            double ys = 0.0;
-            for (int i = 0; i < np; ++i) {
-                s[i] = xn[i] - x[i];
-                y[i] = gn[i] - g[i];
-                ys += y[i] * s[i];
-            }
-            if (ys > 1e-300) {
-                const double rr = 1.0 / ys;
-                double yHy = 0.0;
-                for (int i = 0; i < np; ++i) {
-                    double v = 0.0;
-                    for (int j = 0; j < np; ++j) v += H[(size_t)i * np + j] * y[j];
-                    Hy[i] = v;
-                    yHy += y[i] * v;
-                }
-                // H <- H - r (Hy s^T + s (Hy)^T) + (r^2 yHy + r) s s^T  (H symmetric)
-                for (int i = 0; i < np; ++i)
-                    for (int j = 0; j < np; ++j)
-                        H[(size_t)i * np + j] += -rr * (Hy[i] * s[j] + s[i] * Hy[j]) + (rr * rr * yHy + rr) * s[i] * s[j];
-            }
-            x = xn;
-            fx = fn;
-            g = gn;
+    std::vector<double> g(np), gn(np), d(np), xn(np), H((size_t)np * np, 0.0);
+    for (int i = 0; i < np; ++i) H[(size_t)i * np + i] = 1.0;
+    fx = fg(x, &g);
+    while (evals < max_eval && fx >= tol && err == DPIC_OK) {
+        double gd = 0.0;
+        for (int i = 0; i < np; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < np; ++j) s -= H[(size_t)i * np + j] * g[j];
+            d[i] = s;
+            gd += g[i] * s;
         }
-    } else {
-        const int n = np;
-        std::vector<std::vector<double>> P(n + 1, x);
-        std::vector<double> V(n + 1);
-        for (int i = 1; i <= n; ++i) P[i][i - 1] += step;
-        for (int i = 0; i <= n && evals < max_eval; ++i) V[i] = fg(P[i], nullptr);
-        std::vector<double> c(n), xr(n), xe(n), xc(n);
-        while (evals < max_eval && err == DPIC_OK) {
-            std::vector<int> idx(n + 1);
-            for (int i = 0; i <= n; ++i) idx[i] = i;
-            std::sort(idx.begin(), idx.end(), [&](int a2, int b2) { return V[a2] < V[b2]; });
-            std::vector<std::vector<double>> P2;
-            std::vector<double> V2;
-            for (int i : idx) {
-                P2.push_back(P[i]);
-                V2.push_back(V[i]);
-            }
-            P = P2;
-            V = V2;
-            if (V[0] < tol) break;
-            for (int j = 0; j < n; ++j) {
-                double s = 0.0;
-                for (int i = 0; i < n; ++i) s += P[i][j];
-                c[j] = s / n;
-            }
-            for (int j = 0; j < n; ++j) xr[j] = c[j] + (c[j] - P[n][j]);
-            const double fr = fg(xr, nullptr);
-            if (fr < V[0]) {
-                for (int j = 0; j < n; ++j) xe[j] = c[j] + 2.0 * (c[j] - P[n][j]);
-                const double fe = evals < max_eval ? fg(xe, nullptr) : INFINITY;
-                if (fe < fr) {
-                    P[n] = xe;
-                    V[n] = fe;
-                } else {
-                    P[n] = xr;
-                    V[n] = fr;
-                }
-            } else if (fr < V[n - 1]) {
-                P[n] = xr;
-                V[n] = fr;
-            } else {
-                for (int j = 0; j < n; ++j) xc[j] = c[j] + 0.5 * (P[n][j] - c[j]);
-                const double fc = evals < max_eval ? fg(xc, nullptr) : INFINITY;
-                if (fc < V[n]) {
-                    P[n] = xc;
-                    V[n] = fc;
-                } else {
-                    for (int i = 1; i <= n && evals < max_eval; ++i) {
-                        for (int j = 0; j < n; ++j) P[i][j] = P[0][j] + 0.5 * (P[i][j] - P[0][j]);
-                        V[i] = fg(P[i], nullptr);
-                    }
-                }
-            }
+        if (gd >= 0) {  // not a descent direction: restart from steepest descent
+            std::fill(H.begin(), H.end(), 0.0);
+            for (int i = 0; i < np; ++i) H[(size_t)i * np + i] = 1.0, d[i] = -g[i];
+            gd = 0.0;
+            for (int i = 0; i < np; ++i) gd -= g[i] * g[i];
         }
-        int best = 0;
-        for (int i = 1; i <= n; ++i)
-            if (V[i] < V[best]) best = i;
-        x = P[best];
-        fx = V[best];
+        double t = 1.0, fn = fx;
+        while (evals < max_eval) {
+            for (int i = 0; i < np; ++i) xn[i] = x[i] + t * d[i];
+            fn = fg(xn, &gn);
+            if (fn <= fx + 1e-4 * t * gd || t < 1e-12) break;
+            t *= 0.5;
+        }
+        // BFGS inverse-Hessian update with s = xn - x, y = gn - g
+        std::vector<double> s(np), y(np), Hy(np);
+        double ys = 0.0;
+        for (int i = 0; i < np; ++i) {
+            s[i] = xn[i] - x[i];
+            y[i] = gn[i] - g[i];
+            ys += y[i] * s[i];
+        }
+        if (ys > 1e-300) {
+            const double rr = 1.0 / ys;
+            double yHy = 0.0;
+            for (int i = 0; i < np; ++i) {
+                double v = 0.0;
+                for (int j = 0; j < np; ++j) v += H[(size_t)i * np + j] * y[j];
+                Hy[i] = v;
+                yHy += y[i] * v;
+            }
+            // H <- H - r (Hy s^T + s (Hy)^T) + (r^2 yHy + r) s s^T  (H symmetric)
+            for (int i = 0; i < np; ++i)
+                for (int j = 0; j < np; ++j)
+                    H[(size_t)i * np + j] += -rr * (Hy[i] * s[j] + s[i] * Hy[j]) + (rr * rr * yHy + rr) * s[i] * s[j];
+        }
+        x = xn;
+        fx = fn;
+        g = gn;
     }
     if (err != DPIC_OK) return err;
     for (int j = 0; j < np; ++j) p_out[j] = x[j];

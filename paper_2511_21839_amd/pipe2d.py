@@ -18,7 +18,6 @@ _I64 = ctypes.POINTER(ctypes.c_int64)
 
 GRID_RHO, GRID_PHI, GRID_E = 0, 1, 2
 STAGE_DEPOSIT, STAGE_SOLVE, STAGE_FIELD = 0, 1, 2
-BFGS, NELDER_MEAD = 0, 1
 
 
 class dpic2d_dims(ctypes.Structure):
@@ -54,8 +53,8 @@ _SIGS = {
     "dtwiss_query_workspace": ([ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "dtwiss_eval": ([_P, ctypes.c_size_t, _P, ctypes.c_int, _I, _D, _D, _I, _I, ctypes.c_int, ctypes.c_int, _D, _D, _D,
                      _D, _D], ctypes.c_int),
-    "dtwiss_match": ([_P, ctypes.c_size_t, _P, ctypes.c_int, ctypes.c_int, _I, _D, _D, _I, _I, ctypes.c_int, _D, _D, _D,
-                      ctypes.c_double, ctypes.c_double, ctypes.c_int, _D, _D, _I, _D], ctypes.c_int),
+    "dtwiss_match": ([_P, ctypes.c_size_t, _P, ctypes.c_int, _I, _D, _D, _I, _I, ctypes.c_int, _D, _D, _D,
+                      ctypes.c_double, ctypes.c_int, _D, _D, _I, _D], ctypes.c_int),
 }
 
 _bound = False
@@ -221,13 +220,14 @@ class Twiss:
                                        npar, nb, _dp(p), _dp(t0), _dp(tg), _dp(tw), _dp(f)))
         return (tw, f) if target is not None else tw
 
-    def match(self, p0, twiss0, target, method=BFGS, step=1.0, tol=1e-12, max_eval=2000):
+    def match(self, p0, twiss0, target, tol=1e-12, max_eval=2000):
+        """BFGS on the matching objective and its dual-number gradient."""
         p0 = _d(p0)
         out = np.empty_like(p0)
         f = ctypes.c_double(0.0)
         ne = ctypes.c_int(0)
         hist = np.zeros(max_eval)
-        _check(None, lib().dtwiss_match(_P(self.ptr), self.bytes, _P(self.stream) if self.stream else None, int(method),
-                                        *self._line(), len(p0), _dp(p0), _dp(_d(twiss0)), _dp(_d(target)), step, tol,
+        _check(None, lib().dtwiss_match(_P(self.ptr), self.bytes, _P(self.stream) if self.stream else None,
+                                        *self._line(), len(p0), _dp(p0), _dp(_d(twiss0)), _dp(_d(target)), tol,
                                         int(max_eval), _dp(out), ctypes.byref(f), ctypes.byref(ne), _dp(hist)))
         return out, f.value, ne.value, hist[:ne.value]

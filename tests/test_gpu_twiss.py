@@ -87,16 +87,14 @@ def test_matching_objective_and_gradient_match_oracle():
         np.testing.assert_allclose(f[s], want, rtol=1e-11, atol=1e-12 * np.abs(want).max())
 
 
-def test_bfgs_matches_with_far_fewer_evaluations_than_nelder_mead():
+def test_bfgs_matching_reaches_the_target_and_the_oracle_optimum():
     from paper_2511_21839_amd import pipe2d as p2
 
     m, t0, tt = _matching()
     tw = p2.Twiss(m.kind, m.L, [0.0] * len(m.kind), [-1] * len(m.kind), m.k_param, nmax=1)
-    kb, fb, nb, hb = tw.match(m.k0, t0, tt, method=p2.BFGS, tol=1e-14, max_eval=500)
-    kn, fn, nn, hn = tw.match(m.k0, t0, tt, method=p2.NELDER_MEAD, step=2.0, tol=1e-14, max_eval=5000)
-    assert fb < 1e-12 and fn < 1e-12
-    assert nb * 4 < nn
-    np.testing.assert_allclose(kb, kn, rtol=1e-6)
+    kb, fb, nb, hb = tw.match(m.k0, t0, tt, tol=1e-14, max_eval=500)
+    assert fb < 1e-12 and nb < 500
+    assert hb[-1] == fb and hb[0] > 1e3 * fb
     # the oracle's BFGS reaches the same strengths
     def fg(kv):
         Mx, My = twiss.line_matrices(m.kind, m.L, [0.0] * len(m.kind), [-1] * len(m.kind), m.k_param, kv, np.eye(4))

@@ -61,21 +61,17 @@ def test_twiss_derivatives_match_central_differences():
             assert float(tw[q].d[j]) == pytest.approx(fd, rel=1e-6, abs=1e-8)
 
 
-def test_bfgs_and_nelder_mead_on_textbook_functions():
+def test_bfgs_on_textbook_functions():
     A = np.array([[3.0, 1.0], [1.0, 2.0]])
     b = np.array([1.0, -2.0])
     fq = lambda x: (0.5 * x @ A @ x - b @ x + 0.5 * b @ np.linalg.solve(A, b), A @ x - b)
     x, f, ne, _ = twiss.bfgs(fq, [4.0, -3.0], tol=1e-14)
     np.testing.assert_allclose(x, np.linalg.solve(A, b), atol=1e-6)
 
-    def rosen(x):
-        return (1 - x[0]) ** 2 + 100 * (x[1] - x[0] ** 2) ** 2
-
     def rosen_g(x):
-        return rosen(x), np.array([-2 * (1 - x[0]) - 400 * x[0] * (x[1] - x[0] ** 2), 200 * (x[1] - x[0] ** 2)])
+        f = (1 - x[0]) ** 2 + 100 * (x[1] - x[0] ** 2) ** 2
+        return f, np.array([-2 * (1 - x[0]) - 400 * x[0] * (x[1] - x[0] ** 2), 200 * (x[1] - x[0] ** 2)])
 
     x, f, ne_b, _ = twiss.bfgs(rosen_g, [-1.2, 1.0], tol=1e-14, max_iter=500)
     assert f < 1e-10
-    x2, f2, ne_n, _ = twiss.nelder_mead(rosen, [-1.2, 1.0], step=0.5, tol=1e-10, max_eval=5000)
-    assert f2 < 1e-8
-    assert ne_b < ne_n
+    np.testing.assert_allclose(x, [1.0, 1.0], atol=1e-5)
