@@ -138,6 +138,64 @@ def _adjoint_timing():
     return out
 
 
+def _c1_timing(reps=5):
+    """The 1e4-particle, 32^3-grid, 100-step workload with 7 tangents (one
+    FODO cell), each whole run (beam initialisation and 100 steps) replayed
+    from HIP graphs, and with eager launches."""
+    import synth
+    from paper_2511_21839_amd import dpic
+
+    w = synth.c1()
+    xi = w.xi()
+    out = {"workload": w.name}
+    for mode, graph in (("graph", True), ("eager", False)):
+        sim = _sim_for(w, w.n_particles)
+        sim.set_params(w.params, w.param_seed())
+        sim.set_option(dpic.OPT_GRAPH, int(graph))
+
+        def go():
+            sim.init_beam(xi, w.sigma, w.sigma_seed())
+            sim.step(w.total_steps())
+
+        ms = _median_ms(go, reps)
+        out[mode] = {"ms_per_run": ms, "ms_per_step": ms / w.total_steps(),
+                     "dual_particle_steps_per_s": w.n_particles * w.total_steps() / (ms * 1e-3)}
+        sim.close()
+    # algorithmic bytes per step: particle state read and write, plus one
+    # write and read of rho, phi and E and the Ghat octant
+    n = w.grid[0]
+    grid_bytes = 2 * 8 * 8 * (n ** 3 + (n + 2) ** 3 + 3 * n ** 3) + 8 * (n + 1) ** 3
+    step_bytes = w.n_particles * BYTES_PER_PARTICLE_STEP + grid_bytes
+    g = out["graph"]["ms_per_step"] * 1e-3
+    out["roofline"] = {"bound": "hbm", "algorithmic_bytes_per_step": step_bytes,
+                       "achieved": step_bytes / g / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": step_bytes / g / 1e9 / HBM_PEAK_GBS,
+                       "note": "whole step; at this size the step is bound by launch and latency, not bytes"}
+    return out
+
+
+def _copy_rate():
+    """Achievable streaming rate: a device-to-device copy of the particle
+    state's size (384 MiB read and written), GB/s of read + write."""
+    import torch
+
+    n = 384 * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / 20 * 1e3
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes": 2 * n * 8, "us": us, "GBps": 2 * n * 8 / (us * 1e-6) / 1e9}
+
+
 def _sim_for(w, capacity, nbatch=1):
     from paper_2511_21839_amd import dpic
 
@@ -228,8 +286,9 @@ def _batched_timing():
     import synth
 
     c4 = synth.c4()
-    r4 = _batch_vs_singles(c4, c4.base.total_steps(), autotune_steps=20)
-    r4["workload"] = c4.base.name
+    r4 = _batch_vs_singles(c4, c4.base.total_steps(), autotune_steps=20, graph=True)
+    r4["workload"] = c4.base.name + ", graph replay"
+    r4["dual_particle_steps_per_s"] = float(c4.ns.sum()) * c4.base.total_steps() / r4["t_batched_s"]
     b5 = synth.c5_batch(256, seed=7)
     r5 = _batch_vs_singles(b5, b5.base.total_steps(), graph=True)
     r5["workload"] = "256 settings of 1e4 protons, 32^3 grid, 100 steps, 13 tangents (inputs +-5%), graph replay"
@@ -443,7 +502,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--sort-every", type=int, default=5)
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extensions", action="store_true",
                     help="skip the reverse-mode and batched timings")
@@ -489,11 +548,12 @@ def main(argv=None):
     torch.cuda.synchronize()
 
     # timed: K steps from the start of the schedule, beam resident in HBM,
-    # with HIP events around the plain particle launches only (mode 3: every
-    # event record idles the GPU for a few microseconds; the launches that
-    # also write sort keys or store in sorted order are other kernels)
+    # with HIP events around every particle launch (mode 2: two event
+    # records per step; the plain launches, the one that also writes the
+    # sort keys, the one that stores in sorted order, and a call's first and
+    # last launch each move the whole state once)
     sim.init_beam(xi, w.sigma, w.sigma_seed())
-    sim.set_option(dpic.OPT_STAGE_TIMING, 3)
+    sim.set_option(dpic.OPT_STAGE_TIMING, 2)
     sim.stage_times()  # reset the stage timers
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -505,8 +565,14 @@ def main(argv=None):
     oob, steps_done, extent = sim.counters()
     emit = sim.emittance()
 
-    # stage breakdown, outside the timed region: the same steps with events
-    # around every stage
+    # outside the timed region, the same steps again: events around the
+    # plain particle launches only (mode 3), then around every stage
+    sim.init_beam(xi, w.sigma, w.sigma_seed())
+    sim.set_option(dpic.OPT_STAGE_TIMING, 3)
+    sim.stage_times()
+    sim.step(K)
+    torch.cuda.synchronize()
+    pms, plaunches = sim.stage_times()
     sim.init_beam(xi, w.sigma, w.sigma_seed())
     sim.set_option(dpic.OPT_STAGE_TIMING, 1)
     sim.stage_times()
@@ -514,9 +580,15 @@ def main(argv=None):
     torch.cuda.synchronize()
     sms, slaunches = sim.stage_times()
     sim.set_option(dpic.OPT_STAGE_TIMING, 0)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    copy = _copy_rate()
 
     part_avg_s = ms[0] / 1e3 / max(int(launches[0]), 1)
     achieved = w.n_particles * BYTES_PER_PARTICLE_STEP / part_avg_s / 1e9
+    plain_avg_s = pms[0] / 1e3 / max(int(plaunches[0]), 1)
+    plain_achieved = w.n_particles * BYTES_PER_PARTICLE_STEP / plain_avg_s / 1e9
     line = {
         "metric": "dual particle-steps/s (7 tangents)",
         "value": w.n_particles * K / dt,
@@ -547,9 +619,15 @@ def main(argv=None):
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": _recorded_traffic(),
-            "kernel": "k_particles_tiled (gather, kick, two half-maps, deposit)",
+            "kernel": "fused particle kernel (gather, kick, half-maps, deposit): every launch of the timed steps",
             "timed_launches": int(launches[0]),
             "avg_launch_us": part_avg_s * 1e6,
+            "plain_launches_only": {"kernel": "k_particles_tiled<8, 23>", "launches": int(plaunches[0]),
+                                    "avg_launch_us": plain_avg_s * 1e6, "achieved": plain_achieved,
+                                    "frac": plain_achieved / HBM_PEAK_GBS},
+            "copy_ceiling": {"what": "device-to-device copy, 384 MiB each way", "GBps": copy["GBps"],
+                             "frac_of_peak": copy["GBps"] / HBM_PEAK_GBS,
+                             "kernel_over_copy": achieved / copy["GBps"]},
         },
         "stages_ms": {n: float(sms[i]) for i, n in enumerate(dpic.STAGE_TIMER_NAMES)},
         "stage_launches": {n: int(slaunches[i]) for i, n in enumerate(dpic.STAGE_TIMER_NAMES)},
@@ -559,6 +637,8 @@ def main(argv=None):
     }
     _log(f"c2: {K} steps in {dt:.3f} s")
     if not args.no_extensions:
+        line["c1"] = _c1_timing()
+        _log("1e4-particle workload timed")
         line["adjoint"] = _adjoint_timing()
         _log("reverse mode timed")
         line["batched"] = _batched_timing()
