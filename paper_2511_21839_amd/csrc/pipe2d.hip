@@ -4,10 +4,13 @@
 //
 // Lanes: NC consecutive lanes per particle (or grid node), lane c holding
 // the value and channel c of every dual (the LD rules of common.hpp).
-// Solve: the sine projection and its inverse are dense products with the
-// (symmetric) sine matrices, four passes over the interior nodes:
+// Solve: the sine projection and its inverse, four passes over the interior
+// nodes:
 //   T = Sx rho, C = (4/(nx ny)) T Sy / (eps0 (alpha_l^2 + beta_m^2)),
-//   U = Sx C,   phi = U Sy.
+//   U = Sx C,   phi = U Sy,
+// with S the (symmetric) sine matrices. On power-of-two grids each pass is
+// the O(n log n) sine transform (an FFT of the odd extension, as the
+// spectral solver of Sec. 4 has it); otherwise a dense product with S.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -210,6 +213,80 @@ __global__ void k2_pass(const double* __restrict__ in, int in_ld, int in_off, co
         if (scale) acc *= scale[(int64_t)r * cols + q];
     }
     out[((int64_t)(r + out_off) * out_ld + q + out_off) * NC + c] = acc;
+}
+
+// Type-I discrete sine transform along one axis, O(n log n): the line
+// z_i (i = 1..n-1; z_0 = z_n = 0) is extended to the odd sequence of length
+// M = 2n (y_t = z_t, y_{M-t} = -z_t), whose M-point FFT is
+// Y_l = -2i sum_i z_i sin(pi l i / n); so X_l = sum_i z_i sin(pi l i / n) =
+// i Y_l / 2 for l = 1..n-1. The real channels c and c + NC/2 travel as one
+// complex line (the transform is real-linear), so one FFT gives both. One
+// workgroup of n threads per (line, channel pair); radix-2 in LDS, n a
+// power of two. Element (line, i) sits at
+// ((line * ls + i * es + off) * NC + channel) on either side; the output is
+// multiplied by scale[line * sls + (l - 1)] when scale is given.
+struct DstArgs {
+    const double* in;
+    int64_t in_ls, in_es, in_off;
+    double* out;
+    int64_t out_ls, out_es, out_off;
+    const double* scale;
+    int64_t sls;
+    int n, log2m;
+};
+
+template <int NC>
+__global__ void k2_dst(DstArgs a) {
+    constexpr int NCH = NC == 1 ? 1 : NC / 2;  // complex channels
+    __shared__ double yr[512], yi[512];
+    const int M = 2 * a.n;
+    const int64_t line = blockIdx.x / NCH;
+    const int c = (int)(blockIdx.x % NCH);
+    // odd extension, stored at bit-reversed positions
+    for (int t = threadIdx.x; t < M; t += blockDim.x) {
+        double vr = 0.0, vi = 0.0;
+        const int i = t < a.n ? t : M - t;  // 1..n-1 for the nonzero entries
+        if (i != 0 && t != a.n) {
+            const int64_t e = (line * a.in_ls + i * a.in_es + a.in_off) * NC;
+            vr = a.in[e + c];
+            if (NC > 1) vi = a.in[e + c + NCH];
+            if (t > a.n) {
+                vr = -vr;
+                vi = -vi;
+            }
+        }
+        const int rt = (int)(__brev((unsigned)t) >> (32 - a.log2m));
+        yr[rt] = vr;
+        yi[rt] = vi;
+    }
+    __syncthreads();
+    for (int len = 2; len <= M; len <<= 1) {
+        const int half = len >> 1;
+        for (int k = threadIdx.x; k < M / 2; k += blockDim.x) {
+            const int j = k % half, base = (k / half) * len;
+            double sn, cs;
+            sincospi(-2.0 * (double)j / (double)len, &sn, &cs);
+            const double ur = yr[base + j], ui = yi[base + j];
+            const double xr = yr[base + j + half], xi = yi[base + j + half];
+            const double tr = xr * cs - xi * sn, ti = xr * sn + xi * cs;
+            yr[base + j] = ur + tr;
+            yi[base + j] = ui + ti;
+            yr[base + j + half] = ur - tr;
+            yi[base + j + half] = ui - ti;
+        }
+        __syncthreads();
+    }
+    for (int l = 1 + threadIdx.x; l < a.n; l += blockDim.x) {
+        double xr = -0.5 * yi[l], xi = 0.5 * yr[l];  // X = i Y / 2
+        if (a.scale) {
+            const double s = a.scale[line * a.sls + (l - 1)];
+            xr *= s;
+            xi *= s;
+        }
+        const int64_t e = (line * a.out_ls + l * a.out_es + a.out_off) * NC;
+        a.out[e + c] = xr;
+        if (NC > 1) a.out[e + c + NCH] = xi;
+    }
 }
 
 template <int NC>
@@ -464,8 +541,36 @@ hipError_t push(dpic2d_ctx* c, int flags, int e) {
     return hipGetLastError();
 }
 
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2i(int v) {
+    int r = 0;
+    while ((1 << r) < v) ++r;
+    return r;
+}
+
+// One sine-transform pass over nlines lines of interior length n - 1.
+hipError_t dst_pass(dpic2d_ctx* c, int n, int64_t nlines, const double* in, int64_t in_ls, int64_t in_es,
+                    int64_t in_off, double* out, int64_t out_ls, int64_t out_es, int64_t out_off, const double* scale,
+                    int64_t sls) {
+    DstArgs a{in, in_ls, in_es, in_off, out, out_ls, out_es, out_off, scale, sls, n, ilog2i(2 * n)};
+    const int nch = c->NC == 1 ? 1 : c->NC / 2;
+    const dim3 grid((unsigned)(nlines * nch)), block((unsigned)std::min(n, 256));
+    NC_SWITCH(c, hipLaunchKernelGGL((k2_dst<NC>), grid, block, 0, c->stream, a));
+    return hipGetLastError();
+}
+
 hipError_t solve(dpic2d_ctx* c) {
     const int nx1 = c->nx - 1, ny1 = c->ny - 1, ly = c->ny + 1;
+    if (pow2(c->nx) && pow2(c->ny)) {
+        // rho[i][j] (nodes, i = x) -> T[l][q]: sine transform along x of the
+        // interior rows q (node j = q + 1); T -> U[l][m] along y, scaled by
+        // ginv; U -> T along x; T -> phi (interior nodes) along y
+        hipError_t e;
+        if ((e = dst_pass(c, c->nx, ny1, c->rho, 1, ly, 1, c->T, 1, ny1, -ny1, nullptr, 0)) != hipSuccess) return e;
+        if ((e = dst_pass(c, c->ny, nx1, c->T, ny1, 1, -1, c->U, ny1, 1, -1, c->ginv, ny1)) != hipSuccess) return e;
+        if ((e = dst_pass(c, c->nx, ny1, c->U, 1, ny1, -ny1, c->T, 1, ny1, -ny1, nullptr, 0)) != hipSuccess) return e;
+        return dst_pass(c, c->ny, nx1, c->T, ny1, 1, -1, c->phi, ly, 1, ly, nullptr, 0);
+    }
     const int64_t inner = (int64_t)nx1 * ny1 * c->NC;
     const dim3 grid((unsigned)((inner + 255) / 256)), block(256);
     NC_SWITCH(c, {

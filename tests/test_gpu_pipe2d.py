@@ -119,12 +119,15 @@ def test_channel_counts_and_small_grids_match_oracle(ntan, nx, ny):
     assert sim.counters() == (ref.lost, w.total_steps())
 
 
-def test_solve_and_field_at_the_largest_grid():
-    """256 x 256 cells (255^2 interior nodes, the ABI's maximum): the dense
-    sine passes against the oracle's sine sums on a random charge."""
+@pytest.mark.parametrize("nx,ny", [(256, 256), (64, 32), (48, 40)])
+def test_solve_and_field_at_the_largest_grid(nx, ny):
+    """256 x 256 cells (255^2 interior nodes, the ABI's maximum) and the
+    benchmark-like 64 x 32 take the O(n log n) sine transform (power-of-two
+    cell counts), 48 x 40 the dense sine products: against the oracle's
+    explicit sine sums on a random charge."""
     from paper_2511_21839_amd import pipe2d as p2
 
-    w = synth.pipe2d(n_particles=10, cells=256)
+    w = synth.pipe2d(n_particles=10, cells=nx).with_(ny=ny)
     sim = _make(w)
     pipe = pipe2d.Pipe(w.a, w.b, w.nx, w.ny)
     r = np.random.default_rng(8).normal(size=(w.nx + 1, w.ny + 1, w.ntan + 1)) * 1e-9
