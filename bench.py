@@ -196,6 +196,64 @@ def _copy_rate():
     return {"bytes": 2 * n * 8, "us": us, "GBps": 2 * n * 8 / (us * 1e-6) / 1e9}
 
 
+def _adjoint_scale_timing(steps=100):
+    """Reverse mode where the state streams from HBM: the 1e6-particle, 64^3
+    beam over its first `steps` steps, J = eps_x + eps_y, gradients w.r.t.
+    the 7 lattice parameters and the 6 beam sizes, checkpoint every 50
+    steps; against forward mode with 13 tangents and the value-only run
+    (both fused, re-sorted every 5 steps), and the gradients against the
+    13-tangent forward mode."""
+    import numpy as np
+    import synth
+    from paper_2511_21839_amd import dpic
+    from paper_2511_21839_amd.autograd import AdjointRun
+
+    w = synth.c2(ntan=13, sigma_tangents=True)
+    L = w.lattice
+    xi = w.xi()
+    out = {"workload": f"1e6 protons, 64^3 grid, first {steps} steps of the 2000-step schedule, J = eps_x + eps_y, "
+                       "13 gradient components", "checkpoint_every": 50}
+
+    def forward(ntan):
+        sim = _sim_for(w.with_(ntan=ntan), w.n_particles)
+        sim.set_params(w.params, w.param_seed() if ntan else None)
+        ss = w.sigma_seed() if ntan else None
+
+        def go():
+            sim.init_beam(xi, w.sigma, ss)
+            sim.step(steps)
+        return go, sim
+
+    go13, s13 = forward(13)
+    t13 = _median_ms(go13, 3)
+    e13 = s13.emittance()
+    s13.close()
+    del s13
+    go0, s0 = forward(0)
+    t0 = _median_ms(go0, 3)
+    s0.close()
+    del s0
+    run = AdjointRun(w.n_particles, w.grid, w.lo, w.hi, (w.kinetic_eV, w.rest_eV, w.charge_e, w.bunch_charge_C),
+                     (L.kind, L.n_steps, L.L, L.k, L.L_param, L.k_param, L.n_periods), xi, steps, checkpoint_every=50)
+    grads = []
+
+    def adj():
+        run.forward(w.params, w.sigma)
+        grads.append(run.backward([1.0, 1.0, 0.0]))
+
+    ta = _median_ms(adj, 3)
+    tf = _median_ms(lambda: run.forward(w.params, w.sigma), 3)
+    gp, gs = grads[-1]
+    g_adj = np.concatenate([gp, gs])
+    g_fwd = e13[0, 1:] + e13[1, 1:]
+    run.sim.close()
+    out.update({"t_forward_13_tangents_ms": t13, "t_value_only_ms": t0, "t_adjoint_ms": ta,
+                "t_adjoint_forward_part_ms": tf,
+                "adjoint_over_forward_13": ta / t13, "adjoint_over_value_only": ta / t0,
+                "grad_rel_err_vs_forward_13": float(np.abs(g_adj - g_fwd).max() / np.abs(g_fwd).max())})
+    return out
+
+
 def _sim_for(w, capacity, nbatch=1):
     from paper_2511_21839_amd import dpic
 
@@ -640,6 +698,7 @@ def main(argv=None):
         line["c1"] = _c1_timing()
         _log("1e4-particle workload timed")
         line["adjoint"] = _adjoint_timing()
+        line["adjoint"]["at_1e6_particles"] = _adjoint_scale_timing()
         _log("reverse mode timed")
         line["batched"] = _batched_timing()
         _log("batched runs timed")

@@ -19,6 +19,8 @@
 // parameters (the element constants evaluated with dual numbers).
 //
 // Particles are processed one lane each (value-only state, NC = 1).
+#include <algorithm>
+
 #include "context.hpp"
 
 namespace dpic {
@@ -121,77 +123,131 @@ __device__ __forceinline__ void map_adjoint(St6& l, const St6& zin, const double
     l.py = lpy;
 }
 
-// Second half of the step backward, the kick's adjoint, the direct position
-// term and the deposit of the adjoint field.
+// Second half of the step backward for particle p, the kick's adjoint, the
+// direct position term and the deposit of the adjoint field: into the LDS
+// tile lt (nodes [o, o + TILE_R)^3 around a work item's grid tile, three
+// components per node) when all 8 corners fall inside it, else by global
+// atomics.
+__device__ __forceinline__ void adj_kick_particle(const AdjArgs& a, int64_t p, double* lt, int ox, int oy, int oz,
+                                                  double (&g)[10]) {
+    double m[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) m[k] = a.map[k];
+    const double tau = a.tau[0];
+    const St6 z0 = load6(a.st0, p, a.cap);
+    St6 z2 = apply_map(z0, m);
+    const Pos c = pos_of(z2.x, z2.y, z2.z, a);
+    double ex = 0.0, ey = 0.0, ez = 0.0;
+    const int64_t sxy = (int64_t)a.nx * a.ny;
+    const int64_t n0 = ((int64_t)c.iz * a.ny + c.iy) * a.nx + c.ix;
+    if (c.inside) {
+#pragma unroll
+        for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+            for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+                for (int kx = 0; kx < 2; ++kx) {
+                    const double w = (kx ? c.fx : 1.0 - c.fx) * (ky ? c.fy : 1.0 - c.fy) * (kz ? c.fz : 1.0 - c.fz);
+                    const double* e = a.E + (n0 + kx + ky * a.nx + kz * sxy) * 3;
+                    ex += w * e[0];
+                    ey += w * e[1];
+                    ez += w * e[2];
+                }
+        z2.px += tau * (ex * a.kperp);
+        z2.py += tau * (ey * a.kperp);
+        z2.d += tau * (ez * a.kpar);
+    }
+    St6 l = load6(a.lam, p, a.cap);
+    map_adjoint(l, z2, m, g);
+    if (c.inside) {
+        g[9] += l.px * a.kperp * ex + l.py * a.kperp * ey + l.d * a.kpar * ez;
+        const double ax = tau * a.kperp * l.px, ay = tau * a.kperp * l.py, az = tau * a.kpar * l.d;
+        const int lx = c.ix - ox, ly = c.iy - oy, lz = c.iz - oz;
+        const bool local = lt && lx >= 0 && lx <= TILE_R - 2 && ly >= 0 && ly <= TILE_R - 2 && lz >= 0 &&
+                           lz <= TILE_R - 2;
+        const int l0 = (lz * TILE_R + ly) * TILE_R + lx;
+        double dx = 0.0, dy = 0.0, dz = 0.0;
+#pragma unroll
+        for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+            for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+                for (int kx = 0; kx < 2; ++kx) {
+                    const double wx = kx ? c.fx : 1.0 - c.fx, wy = ky ? c.fy : 1.0 - c.fy, wz = kz ? c.fz : 1.0 - c.fz;
+                    const double gx = (kx ? a.ih0 : -a.ih0), gy = (ky ? a.ih1 : -a.ih1), gz = (kz ? a.ih2 : -a.ih2);
+                    const int64_t node = n0 + kx + ky * a.nx + kz * sxy;
+                    const double* e = a.E + node * 3;
+                    const double s = ax * e[0] + ay * e[1] + az * e[2];
+                    dx += gx * wy * wz * s;
+                    dy += wx * gy * wz * s;
+                    dz += wx * wy * gz * s;
+                    const double w = wx * wy * wz;
+                    double* ab = local ? lt + (l0 + kx + ky * TILE_R + kz * TILE_R * TILE_R) * 3 : a.abar + node * 3;
+                    unsafeAtomicAdd(ab + 0, w * ax);
+                    unsafeAtomicAdd(ab + 1, w * ay);
+                    unsafeAtomicAdd(ab + 2, w * az);
+                }
+        l.x += dx;
+        l.y += dy;
+        l.z += dz;
+    }
+    a.lam[p] = l.x;
+    a.lam[a.cap + p] = l.px;
+    a.lam[2 * a.cap + p] = l.y;
+    a.lam[3 * a.cap + p] = l.py;
+    a.lam[4 * a.cap + p] = l.z;
+    a.lam[5 * a.cap + p] = l.d;
+}
+
 __global__ __launch_bounds__(ADJ_THREADS) void k_adj_kick(AdjArgs a) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double g[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k) g[k] = 0.0;
-    if (p < a.n) {
-        double m[9];
+    if (p < a.n) adj_kick_particle(a, p, nullptr, 0, 0, 0, g);
+    block_accumulate<10>(g, a.gacc);
+}
+
+// The same over the tiled work list (items of particles sorted into one grid
+// tile): each item accumulates its adjoint-field deposit in an LDS tile and
+// flushes the nonzero nodes by global atomics. With the particles sorted by
+// tile, consecutive threads otherwise hit the same nodes with global
+// atomics: 6.3 ms per step at 1e6 particles on 64^3 nodes.
+struct AdjTiles {
+    const int4* chunks;
+    const uint32_t* nchunks;
+    int tx, ty, nbins;
+};
+
+__global__ __launch_bounds__(ADJ_THREADS) void k_adj_kick_tiled(AdjArgs a, AdjTiles t) {
+    constexpr int TN = TILE_R * TILE_R * TILE_R;
+    __shared__ double lt[TN * 3];
+    double g[10];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) m[k] = a.map[k];
-        const double tau = a.tau[0];
-        const St6 z0 = load6(a.st0, p, a.cap);
-        St6 z2 = apply_map(z0, m);
-        const Pos c = pos_of(z2.x, z2.y, z2.z, a);
-        double ex = 0.0, ey = 0.0, ez = 0.0;
-        const int64_t sxy = (int64_t)a.nx * a.ny;
-        const int64_t n0 = ((int64_t)c.iz * a.ny + c.iy) * a.nx + c.ix;
-        if (c.inside) {
-#pragma unroll
-            for (int kz = 0; kz < 2; ++kz)
-#pragma unroll
-                for (int ky = 0; ky < 2; ++ky)
-#pragma unroll
-                    for (int kx = 0; kx < 2; ++kx) {
-                        const double w = (kx ? c.fx : 1.0 - c.fx) * (ky ? c.fy : 1.0 - c.fy) * (kz ? c.fz : 1.0 - c.fz);
-                        const double* e = a.E + (n0 + kx + ky * a.nx + kz * sxy) * 3;
-                        ex += w * e[0];
-                        ey += w * e[1];
-                        ez += w * e[2];
-                    }
-            z2.px += tau * (ex * a.kperp);
-            z2.py += tau * (ey * a.kperp);
-            z2.d += tau * (ez * a.kpar);
+    for (int k = 0; k < 10; ++k) g[k] = 0.0;
+    const uint32_t nck = *t.nchunks;
+#pragma unroll 1
+    for (uint32_t ci = blockIdx.x; ci < nck; ci += gridDim.x) {
+        const int4 ck = t.chunks[ci];
+        if (ci != blockIdx.x) __syncthreads();  // the previous item's flush is done with lt
+        for (int j = threadIdx.x; j < TN * 3; j += ADJ_THREADS) lt[j] = 0.0;
+        const bool use_tile = ck.x < t.nbins - 1;
+        const int tx = ck.x % t.tx, ty = (ck.x / t.tx) % t.ty, tz = ck.x / (t.tx * t.ty);
+        const int ox = tx * TILE_EDGE - TILE_HALO, oy = ty * TILE_EDGE - TILE_HALO, oz = tz * TILE_EDGE - TILE_HALO;
+        __syncthreads();
+        for (int i = threadIdx.x; i < ck.z; i += ADJ_THREADS)
+            adj_kick_particle(a, (int64_t)ck.y + i, use_tile ? lt : nullptr, ox, oy, oz, g);
+        __syncthreads();
+        if (use_tile) {
+            for (int j = threadIdx.x; j < TN * 3; j += ADJ_THREADS) {
+                const double v = lt[j];
+                if (v == 0.0) continue;
+                const int node = j / 3, comp = j - node * 3;
+                const int gx = ox + node % TILE_R, gy = oy + (node / TILE_R) % TILE_R, gz = oz + node / (TILE_R * TILE_R);
+                if (gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz)
+                    unsafeAtomicAdd(a.abar + (((int64_t)gz * a.ny + gy) * a.nx + gx) * 3 + comp, v);
+            }
         }
-        St6 l = load6(a.lam, p, a.cap);
-        map_adjoint(l, z2, m, g);
-        if (c.inside) {
-            g[9] += l.px * a.kperp * ex + l.py * a.kperp * ey + l.d * a.kpar * ez;
-            const double ax = tau * a.kperp * l.px, ay = tau * a.kperp * l.py, az = tau * a.kpar * l.d;
-            double dx = 0.0, dy = 0.0, dz = 0.0;
-#pragma unroll
-            for (int kz = 0; kz < 2; ++kz)
-#pragma unroll
-                for (int ky = 0; ky < 2; ++ky)
-#pragma unroll
-                    for (int kx = 0; kx < 2; ++kx) {
-                        const double wx = kx ? c.fx : 1.0 - c.fx, wy = ky ? c.fy : 1.0 - c.fy, wz = kz ? c.fz : 1.0 - c.fz;
-                        const double gx = (kx ? a.ih0 : -a.ih0), gy = (ky ? a.ih1 : -a.ih1), gz = (kz ? a.ih2 : -a.ih2);
-                        const int64_t node = n0 + kx + ky * a.nx + kz * sxy;
-                        const double* e = a.E + node * 3;
-                        const double s = ax * e[0] + ay * e[1] + az * e[2];
-                        dx += gx * wy * wz * s;
-                        dy += wx * gy * wz * s;
-                        dz += wx * wy * gz * s;
-                        const double w = wx * wy * wz;
-                        double* ab = a.abar + node * 3;
-                        unsafeAtomicAdd(ab + 0, w * ax);
-                        unsafeAtomicAdd(ab + 1, w * ay);
-                        unsafeAtomicAdd(ab + 2, w * az);
-                    }
-            l.x += dx;
-            l.y += dy;
-            l.z += dz;
-        }
-        a.lam[p] = l.x;
-        a.lam[a.cap + p] = l.px;
-        a.lam[2 * a.cap + p] = l.y;
-        a.lam[3 * a.cap + p] = l.py;
-        a.lam[4 * a.cap + p] = l.z;
-        a.lam[5 * a.cap + p] = l.d;
     }
     block_accumulate<10>(g, a.gacc);
 }
@@ -365,7 +421,16 @@ hipError_t launch_adj_step(dpic_ctx* cx, int e, const double* st0, const double*
         a.kpar = 0.0;
     }
     if ((err = launch_zero(cx, cx->ws.E, (size_t)nx * ny * nz * 3)) != hipSuccess) return err;
-    hipLaunchKernelGGL(k_adj_kick, dim3(blocks), dim3(ADJ_THREADS), 0, cx->stream, a);
+    int tiles[3], nbins = 0;
+    if (cx->chunks_valid && cx->B == 1 && sort_geometry(cx, tiles, &nbins)) {
+        // the work list of the first sort (the adjoint keeps that order)
+        const AdjTiles t{cx->ws.chunks, cx->ws.nchunks, tiles[0], tiles[1], nbins};
+        const size_t items = max_chunks(cx);
+        hipLaunchKernelGGL(k_adj_kick_tiled, dim3((unsigned)std::max<size_t>(items, 1)), dim3(ADJ_THREADS), 0,
+                           cx->stream, a, t);
+    } else {
+        hipLaunchKernelGGL(k_adj_kick, dim3(blocks), dim3(ADJ_THREADS), 0, cx->stream, a);
+    }
     if ((err = hipGetLastError()) != hipSuccess) return err;
     if (space_charge) {
         const int64_t g = (int64_t)(nx + 2) * (ny + 2) * (nz + 2);

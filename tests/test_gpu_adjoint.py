@@ -190,3 +190,22 @@ def test_zero_current_adjoint_closed_forms():
     assert np.all(np.abs(gp * np.asarray(w.params)) <= 1e-11 * eps[0])
     want = np.array([eps[0] / w.sigma[0], eps[0] / w.sigma[1], 0, 0, 0, 0])
     np.testing.assert_allclose(gs, want, rtol=1e-11, atol=1e-12 * eps[0] / w.sigma[0])
+
+
+def test_adjoint_at_the_benchmark_beam_matches_forward_mode():
+    """The 1e6-particle, 64^3 beam (tiled adjoint deposit, 2 segments of 10
+    steps) against the GPU's own 13-tangent forward mode of the same steps,
+    which the oracle pins at 1e-9 on smaller beams."""
+    from gpu_util import make_sim
+
+    w = synth.c2()
+    T = 20
+    run = _run(w.with_(ntan=0), 10, n_steps=T)
+    run.forward(w.params, w.sigma)
+    gp, gs = run.backward([1.0, 1.0, 0.0])
+    run.sim.close()
+    w13 = w.with_(ntan=13, sigma_tangents=True)
+    sim = make_sim(w13)
+    sim.step(T)
+    e = sim.emittance()
+    _check(gp, gs, e[0, 1:] + e[1, 1:])
