@@ -95,12 +95,43 @@ struct StageTimer {
 };
 
 
+// Particles are re-sorted by grid tile (the deterministic mode keeps the
+// stored order fixed).
+bool sorting(const dpic_ctx* c) { return c->sort_every > 0 && !c->deterministic; }
+
 // keys: the launch also writes the tile keys of the positions it deposits
 // at, for the sort that follows it.
 int run_particles(dpic_ctx* c, int flags, int e_tau, int map_off, bool keys = false, bool scatter = false) {
     StageTimer tm(c, T_PART, true, !keys && !scatter);
-    HIPCHK(c, launch_particles(c, flags, e_tau, map_off, c->sort_every > 0 && c->chunks_valid, keys, scatter));
+    HIPCHK(c, launch_particles(c, flags, e_tau, map_off, sorting(c) && c->chunks_valid, keys, scatter));
     c->keys_ready = keys;
+    return DPIC_OK;
+}
+
+// A particle launch that ends in the deposit. In the deterministic mode the
+// launch only counts, and the fixed-order deposit follows it.
+int run_particles_dep(dpic_ctx* c, int flags, int e_tau, int map_off, bool keys = false, bool scatter = false) {
+    if (!c->deterministic || !(flags & PF_DEPOSIT)) return run_particles(c, flags, e_tau, map_off, keys, scatter);
+    int r = run_particles(c, (flags & ~PF_DEPOSIT) | PF_COUNT, e_tau, map_off);
+    if (r != DPIC_OK) return r;
+    StageTimer tm(c, T_PART, false);
+    HIPCHK(c, launch_deposit_det(c));
+    return DPIC_OK;
+}
+
+void clear_graphs(dpic_ctx* c);
+void set_swapped(dpic_ctx* c, bool swapped);
+
+// The stored order back to the packed original order (before the
+// deterministic mode runs: a sort's order depends on the timing of atomics).
+int restore_packed_order(dpic_ctx* c) {
+    if (!c->beam_init || !c->sorted_order) return DPIC_OK;
+    HIPCHK(c, launch_unsort(c));
+    set_swapped(c, !c->swapped);
+    c->chunks_valid = false;
+    c->keys_ready = false;
+    c->sorted_order = false;
+    clear_graphs(c);
     return DPIC_OK;
 }
 
@@ -123,7 +154,7 @@ int single_step(dpic_ctx* c, int64_t s, double* e_store) {
     const int half = ec_offset(c, e, EC_HALF);
     int r;
     if (c->bunch_charge != 0.0) {
-        if ((r = run_particles(c, PF_MAP | PF_DEPOSIT, e, half)) != DPIC_OK) return r;
+        if ((r = run_particles_dep(c, PF_MAP | PF_DEPOSIT, e, half)) != DPIC_OK) return r;
         if ((r = run_solve_field(c)) != DPIC_OK) return r;
         if (e_store)
             HIPCHK(c, hipMemcpyAsync(e_store, c->ws.E, grid_nodes(c) * 3 * c->NC * sizeof(double),
@@ -147,6 +178,7 @@ int run_solve_field(dpic_ctx* c) {
 int run_sort(dpic_ctx* c) {
     StageTimer tm(c, T_SORT);
     HIPCHK(c, launch_sort(c));
+    c->sorted_order = true;
     return DPIC_OK;
 }
 
@@ -162,6 +194,7 @@ int run_sort_counts(dpic_ctx* c) {
 int run_sort_finish(dpic_ctx* c) {
     StageTimer tm(c, T_SORT);
     HIPCHK(c, launch_sort_finish(c, true));
+    c->sorted_order = true;
     return DPIC_OK;
 }
 
@@ -303,7 +336,7 @@ int step_body(dpic_ctx* c, int n) {
     const size_t rho_n = grid_nodes(c) * c->NC * c->B;
     int r;
     c->keys_ready = false;
-    if (sc && c->sort_every > 0 && !c->chunks_valid)
+    if (sc && sorting(c) && !c->chunks_valid)
         if ((r = run_sort(c)) != DPIC_OK) return r;
     if (c->adj.bound) {
         // reverse-mode forward: unfused steps (the backward replays the same
@@ -322,8 +355,9 @@ int step_body(dpic_ctx* c, int n) {
     }
     c->cur_step = s0;
     if (sc) {
-        HIPCHK(c, launch_zero(c, c->ws.rho, rho_n));
-        if ((r = run_particles(c, PF_MAP | PF_DEPOSIT, c->schedule[s0], ec_offset(c, c->schedule[s0], EC_HALF))) != DPIC_OK)
+        if (!c->deterministic) HIPCHK(c, launch_zero(c, c->ws.rho, rho_n));  // the fixed-order deposit stores every node
+        if ((r = run_particles_dep(c, PF_MAP | PF_DEPOSIT, c->schedule[s0], ec_offset(c, c->schedule[s0], EC_HALF))) !=
+            DPIC_OK)
             return r;
         // Re-sort after step s when (s + 1) is a multiple of the cadence R.
         // With R >= 2 and room in this call, the launch one step earlier
@@ -333,7 +367,7 @@ int step_body(dpic_ctx* c, int n) {
         // positions by one step, well inside the tiles' drift allowance).
         // Otherwise the sort step's launch writes the keys and a plain sort
         // follows it.
-        const int64_t R = c->sort_every;
+        const int64_t R = sorting(c) ? c->sort_every : 0;
         bool counted = false;
         for (int64_t s = s0; s < s1; ++s) {
             c->cur_step = s;
@@ -344,7 +378,7 @@ int step_body(dpic_ctx* c, int n) {
             const bool scatter = sort_next && counted;
             const bool early_keys = R >= 2 && s + 2 < s1 && ((s + 2) % R) == 0;
             const bool keys = (sort_next && !scatter) || early_keys;
-            if ((r = run_particles(c, flags, c->schedule[s], closing_map(c, s, last), keys, scatter)) != DPIC_OK)
+            if ((r = run_particles_dep(c, flags, c->schedule[s], closing_map(c, s, last), keys, scatter)) != DPIC_OK)
                 return r;
             if (scatter) {
                 if ((r = run_sort_finish(c)) != DPIC_OK) return r;
@@ -470,10 +504,11 @@ int init_beams(dpic_ctx* c, const std::vector<int64_t>& nb, const double* xi_dev
     c->beam_init = true;
     c->chunks_valid = false;
     c->keys_ready = false;
+    c->sorted_order = false;
     // the beam is stored sorted by grid tile from the start (the order the
     // tiled particle kernel needs), so that the first dpic_step does not
     // begin with a full sort pass
-    if (c->bunch_charge != 0.0 && c->sort_every > 0 && c->grid_set)
+    if (c->bunch_charge != 0.0 && sorting(c) && c->grid_set)
         if ((r = run_sort(c)) != DPIC_OK) return r;
     return DPIC_OK;
 }
@@ -853,6 +888,10 @@ int dpic_stage(dpic_ctx* c, int stage) {
     switch (stage) {
         case DPIC_STAGE_DEPOSIT:
             if (!c->beam_init || !c->grid_set) return fail(c, DPIC_ESTATE, "stage deposit: needs beam and grid");
+            if (c->deterministic) {
+                HIPCHK(c, launch_deposit_det(c));
+                return DPIC_OK;
+            }
             HIPCHK(c, launch_zero(c, c->ws.rho, grid_nodes(c) * c->NC * c->B));
             HIPCHK(c, launch_particles(c, PF_DEPOSIT, 0, 0, false));
             return DPIC_OK;
@@ -965,6 +1004,9 @@ int dpic_load_state(dpic_ctx* c, const void* dev_buf) {
     c->steps_done = hdr[2];
     c->beam_init = true;
     c->chunks_valid = false;
+    c->keys_ready = false;
+    c->sorted_order = true;  // whatever order the checkpoint was stored in
+    if (c->deterministic) return restore_packed_order(c);
     return DPIC_OK;
 }
 
@@ -1001,6 +1043,13 @@ int dpic_set_option(dpic_ctx* c, int option, int64_t value) {
         case DPIC_OPT_CHECK_FINITE:
             c->check_finite = value != 0;
             return DPIC_OK;
+        case DPIC_OPT_DETERMINISTIC:
+            if ((value != 0) != c->deterministic) {
+                clear_graphs(c);
+                c->deterministic = value != 0;
+                if (c->deterministic) return restore_packed_order(c);
+            }
+            return DPIC_OK;
         default:
             return fail(c, DPIC_EINVAL, "unknown option %d", option);
     }
@@ -1015,6 +1064,7 @@ int dpic_get_option(const dpic_ctx* c, int option, int64_t* value) {
         case DPIC_OPT_PART_BLOCKS: *value = c->part_blocks; return DPIC_OK;
         case DPIC_OPT_GRAPH: *value = c->use_graph; return DPIC_OK;
         case DPIC_OPT_CHECK_FINITE: *value = c->check_finite; return DPIC_OK;
+        case DPIC_OPT_DETERMINISTIC: *value = c->deterministic; return DPIC_OK;
         default: return DPIC_EINVAL;
     }
 }
@@ -1046,6 +1096,7 @@ int dpic_autotune(dpic_ctx* c, void* scratch, size_t scratch_bytes, int trial_st
     if (!c->beam_init || !c->grid_set || c->bunch_charge == 0.0 || !elements_ready(c))
         return fail(c, DPIC_ESTATE, "autotune: needs a space-charge run ready to step");
     if (c->adj.bound) return fail(c, DPIC_ESTATE, "autotune: not with the adjoint bound");
+    if (c->deterministic) return fail(c, DPIC_ESTATE, "autotune: the deterministic mode does not sort or tile");
     if (trial_steps < 1 || c->steps_done + trial_steps > (int64_t)c->schedule.size())
         return fail(c, DPIC_EINVAL, "autotune: %d trial steps do not fit the schedule", trial_steps);
     int r;

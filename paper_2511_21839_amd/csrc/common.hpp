@@ -122,6 +122,30 @@ constexpr unsigned long long NONFINITE_BASE = 1ull << 62;
 
 constexpr int MOM_N = 15;  // 3 planes x 5 moments
 
+// ---------------------------------------------------------------- grid cells
+// Cell of a position on the node grid: s = (u - lo) / h per dimension, cell
+// floor(s), inside iff 0 <= s < n - 1 in every dimension (all 8 corner nodes
+// of the cell exist). Every kernel that decides in or out uses this.
+struct CellPos {
+    double sx, sy, sz;
+    int ix, iy, iz;
+    bool inside;
+};
+
+__device__ __forceinline__ CellPos grid_cell(double x, double y, double z, double lo0, double lo1, double lo2,
+                                             double ih0, double ih1, double ih2, int nx, int ny, int nz) {
+    CellPos r;
+    r.sx = (x - lo0) * ih0;
+    r.sy = (y - lo1) * ih1;
+    r.sz = (z - lo2) * ih2;
+    r.inside = (r.sx >= 0.0) && (r.sx < (double)(nx - 1)) && (r.sy >= 0.0) && (r.sy < (double)(ny - 1)) &&
+               (r.sz >= 0.0) && (r.sz < (double)(nz - 1));
+    r.ix = (int)floor(r.sx);
+    r.iy = (int)floor(r.sy);
+    r.iz = (int)floor(r.sz);
+    return r;
+}
+
 __host__ __device__ constexpr int channels_for(int ntan) { return ntan == 0 ? 1 : (ntan <= 7 ? 8 : 16); }
 
 }  // namespace dpic

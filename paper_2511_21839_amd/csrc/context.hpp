@@ -174,6 +174,8 @@ struct dpic_ctx {
     int stage_timing = 0;  // 0 off, 1 every stage, 2 the particle stage only
     bool use_graph = false;
     bool check_finite = false;  // dpic_step synchronises and reports non-finite state values
+    bool deterministic = false; // fixed-order deposit, no re-sorting: bit-identical runs
+    bool sorted_order = false;  // the stored order may come from a sort (not the packed original order)
     int cu_count = 0;
     int device = 0;  // the device current at dpic_create
     dpic::AdjointWs adj;
@@ -207,6 +209,8 @@ hipError_t launch_init_beam(dpic_ctx* c, const double* xi);
 hipError_t launch_particles(dpic_ctx* c, int flags, int e_tau, int map_off, bool tiled, bool write_keys = false,
                             bool scatter = false);
 hipError_t launch_canonical_state(dpic_ctx* c);  // st -> st2 in packed original order
+hipError_t launch_deposit_det(dpic_ctx* c);      // rho in a fixed summation order (deposit_det.hip)
+hipError_t launch_unsort(dpic_ctx* c);           // st -> st2 (and pid -> pid2) in packed original order slots
 int particle_resident_blocks(dpic_ctx* c);       // resident tiled-kernel workgroups on the device
 hipError_t launch_zero(dpic_ctx* c, double* p, size_t n);
 

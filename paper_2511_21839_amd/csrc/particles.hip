@@ -518,24 +518,8 @@ __device__ __forceinline__ bool qd_nonfinite(const QD<K>& x) {
     return bad;
 }
 
-struct CellPos {
-    double sx, sy, sz;
-    int ix, iy, iz;
-    bool inside;
-};
-
-// s = (u - lo)/h per dimension, cell floor(s), inside iff 0 <= s < n-1 in every dimension.
 __device__ __forceinline__ CellPos cell_of(double x, double y, double z, const PartArgs& a) {
-    CellPos r;
-    r.sx = (x - a.lo0) * a.ih0;
-    r.sy = (y - a.lo1) * a.ih1;
-    r.sz = (z - a.lo2) * a.ih2;
-    r.inside = (r.sx >= 0.0) && (r.sx < (double)(a.nx - 1)) && (r.sy >= 0.0) && (r.sy < (double)(a.ny - 1)) &&
-               (r.sz >= 0.0) && (r.sz < (double)(a.nz - 1));
-    r.ix = (int)floor(r.sx);
-    r.iy = (int)floor(r.sy);
-    r.iz = (int)floor(r.sz);
-    return r;
+    return grid_cell(x, y, z, a.lo0, a.lo1, a.lo2, a.ih0, a.ih1, a.ih2, a.nx, a.ny, a.nz);
 }
 
 // One particle's share of a fused step, lane q of its group: gather and kick
@@ -1046,6 +1030,10 @@ static hipError_t launch_particles_nc(dpic_ctx* cx, int flags, const PartArgs& a
         case PF_MAP | PF_DEPOSIT: launch_one<NC, PF_MAP | PF_DEPOSIT, TL>(cx, a, t, max_items); break;
         case PF_KICK | PF_MAP | PF_DEPOSIT: launch_one<NC, PF_KICK | PF_MAP | PF_DEPOSIT, TL>(cx, a, t, max_items); break;
         case PF_KICK | PF_MAP: launch_one<NC, PF_KICK | PF_MAP, TL>(cx, a, t, max_items); break;
+        case PF_KICK | PF_MAP | PF_COUNT:  // the deterministic deposit follows as its own pass
+            if constexpr (TL) return hipErrorInvalidValue;
+            else launch_one<NC, PF_KICK | PF_MAP | PF_COUNT, TL>(cx, a, t, max_items);
+            break;
         case PF_MAP | PF_COUNT: launch_one<NC, PF_MAP | PF_COUNT, TL>(cx, a, t, max_items); break;
         case PF_MAP: launch_one<NC, PF_MAP, TL>(cx, a, t, max_items); break;
         case PF_DEPOSIT: launch_one<NC, PF_DEPOSIT, TL>(cx, a, t, max_items); break;

@@ -41,12 +41,9 @@ struct SortGeom {
 };
 
 __device__ __forceinline__ uint32_t tile_key(double x, double y, double z, const SortGeom& g) {
-    const double sx = (x - g.lo0) * g.ih0, sy = (y - g.lo1) * g.ih1, sz = (z - g.lo2) * g.ih2;
-    const bool inside = (sx >= 0.0) && (sx < (double)(g.nx - 1)) && (sy >= 0.0) && (sy < (double)(g.ny - 1)) &&
-                        (sz >= 0.0) && (sz < (double)(g.nz - 1));
-    if (!inside) return (uint32_t)(g.nbins - 1);
-    const int ix = (int)sx / TILE_EDGE, iy = (int)sy / TILE_EDGE, iz = (int)sz / TILE_EDGE;
-    return (uint32_t)((iz * g.ty + iy) * g.tx + ix);
+    const CellPos c = grid_cell(x, y, z, g.lo0, g.lo1, g.lo2, g.ih0, g.ih1, g.ih2, g.nx, g.ny, g.nz);
+    if (!c.inside) return (uint32_t)(g.nbins - 1);
+    return (uint32_t)(((c.iz / TILE_EDGE) * g.ty + c.iy / TILE_EDGE) * g.tx + c.ix / TILE_EDGE);
 }
 
 constexpr int SORT_THREADS = 1024;

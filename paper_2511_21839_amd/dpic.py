@@ -26,6 +26,7 @@ DPIC_EUNSUPPORTED = -5
 GRID_RHO, GRID_PHI, GRID_E = 0, 1, 2
 STAGE_DEPOSIT, STAGE_SOLVE, STAGE_FIELD = 0, 1, 2
 OPT_SORT_EVERY, OPT_STAGE_TIMING, OPT_CHUNK, OPT_PART_BLOCKS, OPT_GRAPH, OPT_CHECK_FINITE = 1, 2, 3, 4, 5, 6
+OPT_DETERMINISTIC = 7
 SEG = 1024  # each setting of a batch starts on a multiple of this many storage slots
 N_STAGE_TIMERS = 4
 STAGE_TIMER_NAMES = ("particles", "solve", "field", "sort")

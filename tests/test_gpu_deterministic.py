@@ -1,0 +1,234 @@
+"""The deterministic mode (DPIC_OPT_DETERMINISTIC): the charge deposit as a
+sorted segmented reduction with a fixed summation order and no
+floating-point atomics, no re-sorting.
+
+Witnesses:
+  * run to run: the same inputs give bit-identical particles, moments,
+    emittances and counters, also across graph replays, batches, and a beam
+    that was sorted before the mode was switched on (its original order is
+    restored first);
+  * against the oracle at the usual tolerances (gpu_util);
+  * A/B against the default atomic mode: the two differ only in the order
+    of the deposit's additions, so they agree to rounding, at the
+    benchmark's full size too.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import pic
+from gpu_util import (assert_moments_close, assert_outputs_close, assert_particles_close, make_sim,
+                      normwise_err)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_21839_amd import dpic
+
+    dpic.lib()
+    yield
+
+
+def _det_sim(w, before_init=True, graph=False, xi=None):
+    """before_init: the mode is on before the beam is stored (no sort at
+    all); otherwise the beam is sorted at init and the option restores its
+    original order."""
+    from paper_2511_21839_amd import dpic
+
+    if not before_init:
+        sim = make_sim(w, xi=xi)
+        sim.set_option(dpic.OPT_DETERMINISTIC, 1)
+    else:
+        sim = dpic.Simulation(w.n_particles, w.ntan, w.grid)
+        sim.set_beam(w.kinetic_eV, w.rest_eV, w.charge_e, w.bunch_charge_C)
+        sim.set_grid(w.lo, w.hi)
+        L = w.lattice
+        sim.set_lattice(L.kind, L.n_steps, L.L, L.k, L.L_param, L.k_param, L.n_periods)
+        sim.set_params(w.params, w.param_seed())
+        sim.set_option(dpic.OPT_DETERMINISTIC, 1)
+        sim.init_beam(w.xi() if xi is None else xi, w.sigma, w.sigma_seed())
+    if graph:
+        sim.set_option(dpic.OPT_GRAPH, 1)
+    assert sim.get_option(dpic.OPT_DETERMINISTIC) == 1
+    return sim
+
+
+def _outputs(sim, counters=True):
+    out = [sim.particles(), sim.moments(), sim.emittance(), sim.emittance(centred=True)]
+    if counters:  # out-of-box count, steps, largest |x|, |y|, |z| reached since init
+        oob, steps, ext = sim.counters()
+        out += [np.asarray([oob, steps], dtype=np.int64), np.asarray(ext, dtype=np.float64)]
+    return out
+
+
+def _assert_bit_identical(a, b):
+    for i, (x, y) in enumerate(zip(a, b)):
+        x, y = np.ascontiguousarray(x), np.ascontiguousarray(y)
+        assert x.shape == y.shape and x.dtype == y.dtype, i
+        if x.tobytes() != y.tobytes():
+            d = np.abs(x.astype(np.float64) - y.astype(np.float64)).max()
+            raise AssertionError(f"output {i} differs between runs (max |diff| {d:.3e})")
+
+
+def _compare_with_oracle(w, sim, ref):
+    assert_particles_close(sim.particles(), ref.particles)
+    assert_moments_close(sim.moments(), ref.moments, ref.particles)
+    assert_outputs_close(sim.emittance(), ref.emittance, what="emittance")
+    oob, steps, _ = sim.counters()
+    assert oob == ref.out_of_box and steps == ref.steps
+
+
+def _to_gpu_grid(a):
+    """oracle [ix, iy, iz, ch] -> library [iz, iy, ix, ch]"""
+    return np.ascontiguousarray(np.transpose(a, (2, 1, 0, 3)))
+
+
+def test_fixed_order_deposit_matches_oracle_and_repeats():
+    from paper_2511_21839_amd import dpic
+
+    w = synth.tiny(n_particles=2999, grid=16)
+    sim = make_sim(w)
+    sim.stage(dpic.STAGE_DEPOSIT)
+    atomic = sim.read_grid(dpic.GRID_RHO)
+    sim.set_option(dpic.OPT_DETERMINISTIC, 1)
+    sim.stage(dpic.STAGE_DEPOSIT)
+    got = sim.read_grid(dpic.GRID_RHO)
+    sim.stage(dpic.STAGE_DEPOSIT)
+    assert sim.read_grid(dpic.GRID_RHO).tobytes() == got.tobytes()
+    st = pic.initial_state(w.xi(), w.sigma, w.sigma_seed(), w.ntan)
+    grid = pic.Grid(w.grid, w.lo, w.hi)
+    want = _to_gpu_grid(pic.deposit(pic.cic_weights(st, grid), grid, w.bunch_charge_C / w.n_particles, w.ntan))
+    for ch in range(w.ntan + 1):
+        assert normwise_err(got[..., ch], want[..., ch]) <= 1e-12, ch
+        assert normwise_err(got[..., ch], atomic[..., ch]) <= 1e-13, ch
+
+
+@pytest.mark.parametrize("ntan", [7, 0, 13])
+def test_runs_are_bit_identical_and_match_oracle(ntan):
+    w = synth.tiny(n_particles=3000, grid=16, steps_per_element=4, ntan=ntan)
+    n = w.total_steps()
+    a = _det_sim(w, before_init=True)
+    b = _det_sim(w, before_init=False)  # sorted at init, then restored
+    for sim in (a, b):
+        sim.step(5)
+        sim.step(n - 5)
+    _assert_bit_identical(_outputs(a), _outputs(b))
+    _compare_with_oracle(w, a, pic.simulate_workload(w))
+
+
+def test_particles_outside_the_box():
+    w = synth.tiny(n_particles=1200, grid=16, steps_per_element=3)
+    w = w.with_(lo=(-2.0e-3, -8e-3, -9.2e-3), hi=(2.0e-3, 8e-3, 9.2e-3))
+    a, b = _det_sim(w), _det_sim(w)
+    a.step(w.total_steps())
+    b.step(w.total_steps())
+    _assert_bit_identical(_outputs(a), _outputs(b))
+    ref = pic.simulate_workload(w)
+    assert ref.out_of_box > 0
+    _compare_with_oracle(w, a, ref)
+
+
+def test_graph_replays_are_bit_identical_to_eager():
+    w = synth.tiny(n_particles=2500, grid=16, steps_per_element=3)
+    eager = _det_sim(w)
+    eager.step(w.total_steps())
+    want = _outputs(eager)
+    graphed = _det_sim(w, graph=True)
+    for _ in range(3):
+        graphed.init_beam(w.xi(), w.sigma, w.sigma_seed())
+        graphed.step(w.total_steps())
+        _assert_bit_identical(_outputs(graphed), want)
+
+
+def test_switching_on_mid_run_restores_the_order_and_continues():
+    """Steps in the default mode (re-sorted every 5 steps), then the mode is
+    switched on: the restore is a pure permutation (read-back unchanged to
+    the bit); two copies then continue bit-identically and agree with a
+    default-mode continuation to rounding."""
+    from paper_2511_21839_amd import dpic
+
+    w = synth.tiny(n_particles=2000, grid=16, steps_per_element=4)
+    n = w.total_steps()
+    sims = [make_sim(w) for _ in range(3)]
+    for s in sims:
+        s.step(7)
+    before = sims[0].particles()
+    nbytes = dpic.dpic_state_bytes(sims[0].ctx)
+    import torch
+
+    buf = torch.zeros(nbytes // 8 + 1, dtype=torch.float64, device="cuda")
+    dpic.dpic_save_state(sims[0].ctx, buf.data_ptr())
+    sims[0].set_option(dpic.OPT_DETERMINISTIC, 1)
+    assert sims[0].particles().tobytes() == before.tobytes()
+    # a checkpoint of the sorted default-mode run, loaded in the mode
+    sims[1].set_option(dpic.OPT_DETERMINISTIC, 1)
+    dpic.dpic_load_state(sims[1].ctx, buf.data_ptr())
+    for s in sims:
+        s.step(n - 7)
+    # (the extents also cover the first 7 default-mode steps, which differed)
+    _assert_bit_identical(_outputs(sims[0], counters=False), _outputs(sims[1], counters=False))
+    assert_particles_close(sims[0].particles(), sims[2].particles(), vtol=1e-11, dtol=1e-9)
+    assert_outputs_close(sims[0].emittance(), sims[2].emittance(), vtol=1e-11, dtol=1e-9)
+    _compare_with_oracle(w, sims[0], pic.simulate_workload(w))
+    # the mode does not sort, so the autotuner has nothing to tune
+    with pytest.raises(dpic.DpicError) as ei:
+        sims[0].autotune(trial_steps=1)
+    assert ei.value.code == dpic.DPIC_ESTATE
+
+
+def test_batch_runs_are_bit_identical_and_match_oracle():
+    from paper_2511_21839_amd import dpic
+
+    base = synth.tiny(n_particles=2200, grid=16, steps_per_element=3)
+    batch = synth.perturbed_batch(base, [1500, 0, 2200], 5)
+
+    def run():
+        sim = dpic.Simulation(dpic.batch_capacity(batch.ns), base.ntan, base.grid, nbatch=batch.nbatch)
+        sim.set_beam(base.kinetic_eV, base.rest_eV, base.charge_e, base.bunch_charge_C)
+        sim.set_grid(base.lo, base.hi)
+        L = base.lattice
+        sim.set_lattice(L.kind, L.n_steps, L.L, L.k, L.L_param, L.k_param, L.n_periods)
+        sim.set_params_batch(batch.params, base.param_seed())
+        sim.init_beam_batch(batch.ns, batch.xi(), batch.sigma, base.sigma_seed())
+        sim.set_option(dpic.OPT_DETERMINISTIC, 1)
+        sim.step(base.total_steps())
+        return sim
+
+    a, b = run(), run()
+    _assert_bit_identical([a.particles(), a.moments(), a.emittance(), np.asarray(a.batch_counters())],
+                          [b.particles(), b.moments(), b.emittance(), np.asarray(b.batch_counters())])
+    parts, emit, r = a.particles(), a.emittance(), 0
+    for i, n in enumerate(batch.ns):
+        if n:
+            ref = pic.simulate_workload(batch.setting(i))
+            assert_particles_close(parts[r:r + n], ref.particles)
+            assert_outputs_close(emit[i], ref.emittance, what=f"emittance of setting {i}")
+        r += n
+
+
+def test_full_size_runs_are_bit_identical_and_agree_with_the_atomic_mode():
+    """The 1e6-particle, 64^3 workload, 10 steps: two runs in the mode are
+    bit-identical, and the default (tiled, atomic, re-sorted) run agrees
+    with them to rounding."""
+    w = synth.c2()
+    xi = w.xi()
+    steps = 10
+    a = _det_sim(w, xi=xi)
+    a.step(steps)
+    pa = a.particles()
+    oa = [pa, a.moments(), a.emittance()]
+    del a
+    b = _det_sim(w, before_init=False, xi=xi)
+    b.step(steps)
+    _assert_bit_identical(oa, [b.particles(), b.moments(), b.emittance()])
+    del b
+    d = make_sim(w, xi=xi)
+    d.step(steps)
+    assert_particles_close(d.particles(), pa, vtol=1e-11, dtol=1e-9)
+    assert_outputs_close(d.emittance(), oa[2], vtol=1e-11, dtol=1e-9)
