@@ -57,10 +57,47 @@ def _cpu_baseline(w, xi, steps: int):
 PROFILE_RECORD = os.path.join(ROOT, "profiles", "k_particles_tiled_c2.md")
 
 
-def _recorded_traffic():
-    """HBM bytes per launch of the particle kernel from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when
-    the kernel's sources changed since the counters were taken."""
+def _particle_launch_mix(n: int, sort_every: int) -> dict:
+    """Particle-kernel launches of one dpic_step(n) call from a fresh beam, by
+    kernel, following the library's step loop (1e6 particles on 64^3 nodes:
+    tiled kernels with the E tile's drift allowance): the opening half-step
+    deposit, then per step the plain fused launch, the launch that also
+    writes the sort keys (two steps before a re-sort), the launch that stores
+    the state in sorted order (the step before), and the call's last launch
+    (no deposit)."""
+    R = sort_every
+    if R == 0:  # no re-sort: the storage-order kernel, deposit by global atomics
+        return {k: v for k, v in (("k_particles<8, 6>", 1), ("k_particles<8, 7>", n - 1),
+                                   ("k_particles<8, 3>", 1)) if v}
+    mix = {"k_particles_tiled<8, 6>": 1}
+    counted = False
+    for s in range(n):
+        last = s == n - 1
+        sort_next = R > 0 and not last and (s + 1) % R == 0
+        scatter = sort_next and counted
+        early = R >= 2 and s + 2 < n and (s + 2) % R == 0
+        keys = (sort_next and not scatter) or early
+        if last:
+            name = "k_particles_tiled<8, 19>"
+        elif scatter:
+            name = "k_particles_sorted<8, 87>"
+        elif keys:
+            name = "k_particles_tiled<8, 55>"
+        else:
+            name = "k_particles_tiled<8, 23>"
+        mix[name] = mix.get(name, 0) + 1
+        if scatter:
+            counted = False
+        elif early and not sort_next:
+            counted = True
+    return mix
+
+
+def _recorded_traffic(mix: dict):
+    """HBM bytes per launch averaged over the launches in `mix` (kernel ->
+    count), from the committed counter summary (FETCH_SIZE and WRITE_SIZE per
+    kernel, scaled by a plain copy); None when the kernels' sources changed
+    since the counters were taken or a kernel has no record."""
     import hashlib
     import re
 
@@ -72,8 +109,10 @@ def _recorded_traffic():
             h.update(open(os.path.join(ROOT, p), "rb").read())
         if h.hexdigest() != rec["source_sha256"]:
             return None
-        return float(rec["traffic_bytes_per_launch"])
-    except (OSError, AttributeError, KeyError, ValueError):
+        per = rec["traffic_bytes_per_launch"]
+        total = sum(mix.values())
+        return sum(float(per[k]) * c for k, c in mix.items()) / total if total else None
+    except (OSError, AttributeError, KeyError, ValueError, TypeError):
         return None
 
 
@@ -648,6 +687,7 @@ def main(argv=None):
     torch.cuda.empty_cache()
     copy = _copy_rate()
 
+    mix = _particle_launch_mix(K, args.sort_every)
     part_avg_s = ms[0] / 1e3 / max(int(launches[0]), 1)
     achieved = w.n_particles * BYTES_PER_PARTICLE_STEP / part_avg_s / 1e9
     plain_avg_s = pms[0] / 1e3 / max(int(plaunches[0]), 1)
@@ -681,13 +721,15 @@ def main(argv=None):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": _recorded_traffic(),
+            "traffic": _recorded_traffic(mix),
             "kernel": "fused particle kernel (gather, kick, half-maps, deposit): every launch of the timed steps",
             "timed_launches": int(launches[0]),
+            "launch_mix": mix,
             "avg_launch_us": part_avg_s * 1e6,
             "plain_launches_only": {"kernel": "k_particles_tiled<8, 23>", "launches": int(plaunches[0]),
                                     "avg_launch_us": plain_avg_s * 1e6, "achieved": plain_achieved,
-                                    "frac": plain_achieved / HBM_PEAK_GBS},
+                                    "frac": plain_achieved / HBM_PEAK_GBS,
+                                    "traffic": _recorded_traffic({"k_particles_tiled<8, 23>": 1})},
             "copy_ceiling": {"what": "device-to-device copy, 384 MiB each way", "GBps": copy["GBps"],
                              "frac_of_peak": copy["GBps"] / HBM_PEAK_GBS,
                              "kernel_over_copy": achieved / copy["GBps"]},
