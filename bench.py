@@ -213,6 +213,39 @@ def _c1_timing(reps=5):
     return out
 
 
+def _deterministic_timing(steps=20):
+    """The 1e6-particle, 64^3 workload in the deterministic mode (fixed-order
+    deposit, no re-sorting) against the default mode, `steps` steps from the
+    start of the schedule; a second run in the mode must match the first to
+    the bit."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2511_21839_amd import dpic
+
+    w = synth.c2()
+    xi = w.xi()
+    out = {"workload": f"{w.name}, first {steps} steps"}
+    emits = []
+    for mode in ("default", "deterministic", "deterministic"):
+        sim = _sim_for(w, w.n_particles)
+        sim.set_params(w.params, w.param_seed())
+        sim.set_option(dpic.OPT_DETERMINISTIC, int(mode == "deterministic"))
+        sim.init_beam(xi, w.sigma, w.sigma_seed())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        out[f"{mode}_ms_per_step"] = (time.perf_counter() - t0) / steps * 1e3
+        emits.append(sim.emittance())
+        sim.close()
+    out["deterministic_over_default"] = out["deterministic_ms_per_step"] / out["default_ms_per_step"]
+    out["bit_identical_runs"] = emits[1].tobytes() == emits[2].tobytes()
+    out["max_rel_diff_vs_default"] = float(np.max(np.abs(emits[1] - emits[0]) / np.abs(emits[0]).max(axis=-1, keepdims=True)))
+    return out
+
+
 def _copy_rate():
     """Achievable streaming rate: a device-to-device copy of the particle
     state's size (384 MiB read and written), GB/s of read + write."""
@@ -749,6 +782,8 @@ def main(argv=None):
         _log("reverse mode timed")
         line["batched"] = _batched_timing()
         _log("batched runs timed")
+        line["deterministic"] = _deterministic_timing()
+        _log("deterministic mode timed")
         line["surrogate"] = _surrogate_timing()
         _log("surrogate timed")
         line["pipe2d"] = _pipe2d_timing()
