@@ -232,3 +232,28 @@ def test_full_size_runs_are_bit_identical_and_agree_with_the_atomic_mode():
     d.step(steps)
     assert_particles_close(d.particles(), pa, vtol=1e-11, dtol=1e-9)
     assert_outputs_close(d.emittance(), oa[2], vtol=1e-11, dtol=1e-9)
+
+
+def test_reverse_mode_in_the_mode():
+    """With the adjoint bound, the forward steps use the fixed-order deposit
+    too: two forwards give bit-identical emittances, and the adjoint gradient
+    (whose sweep still accumulates with atomics) equals the oracle's forward
+    mode at 1e-9."""
+    from paper_2511_21839_amd import dpic
+    from paper_2511_21839_amd.autograd import AdjointRun
+
+    w = synth.tiny(n_particles=2000, grid=16, steps_per_element=3, ntan=0)
+    w = w.with_(bunch_charge_C=w.bunch_charge_C * 10)
+    L = w.lattice
+    run = AdjointRun(w.n_particles, w.grid, w.lo, w.hi, (w.kinetic_eV, w.rest_eV, w.charge_e, w.bunch_charge_C),
+                     (L.kind, L.n_steps, L.L, L.k, L.L_param, L.k_param, L.n_periods), w.xi(), w.total_steps(),
+                     checkpoint_every=7)
+    run.sim.set_option(dpic.OPT_DETERMINISTIC, 1)
+    e1 = run.forward(w.params, w.sigma)
+    e2 = run.forward(w.params, w.sigma)
+    assert e1.tobytes() == e2.tobytes()
+    gp, gs = run.backward([1.0, 1.0, 0.0])
+    ref = pic.simulate_workload(w.with_(ntan=13, sigma_tangents=True)).emittance
+    g = ref[0, 1:] + ref[1, 1:]
+    for got, want in ((gp, g[:7]), (gs, g[7:])):
+        assert np.abs(got - want).max() <= 1e-9 * np.abs(want).max()
