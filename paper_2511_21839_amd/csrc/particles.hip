@@ -557,6 +557,20 @@ __device__ __forceinline__ RawState<LaneGroup<NC>::K> load_raw(const PartArgs& a
     return s;
 }
 
+// An empty use of prefetched registers. The compiler's wait for a load
+// covers every store issued before it too (loads and stores share one
+// counter), so a prefetch first used after the current particle's stores
+// waits for those stores; used here, just before them, it waits only for
+// loads issued a whole particle earlier and for the previous particle's
+// stores, long done by then.
+template <int K>
+__device__ __forceinline__ void pin_raw(const RawState<K>& s) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+#pragma unroll
+        for (int k = 0; k < K; ++k) asm volatile("" ::"v"(s.r[j][k]));
+}
+
 template <int K, int G>
 __device__ __forceinline__ QD<K> raw_to_qd(const double* r, int q) {
     QD<K> x;
@@ -885,6 +899,7 @@ __device__ __forceinline__ void tiled_body(const PartArgs& a, const TiledArgs& t
             }
         }
         __syncthreads();
+        pin_raw(next);
         {
             // software pipeline: a thread's loads for its next particle are
             // issued before the current one is processed (two iterations deep
@@ -904,6 +919,7 @@ __device__ __forceinline__ void tiled_body(const PartArgs& a, const TiledArgs& t
                 const int64_t p = (int64_t)ck.y + i;
                 // PF_SCATTER: the sorted slot is claimed just before the stores
                 auto dest = [&]() -> int64_t {
+                    pin_raw(next);
                     if constexpr ((F & PF_SCATTER) != 0)
                         return scatter_slot<G>(a, t, q, kin, rin, sclaim, ck.w, tx, ty, tz, use_tile);
                     else
