@@ -15,9 +15,8 @@
 //           run inside the block;
 //   starts: the particles with base node s = setting * nodes + node are the
 //           sorted positions [start[s], start[s + 1]), found by binary search;
-//   sum:    one thread per (setting, node, channel) adds the shares of the 8
-//           cells around its node, cell after cell in a fixed order and, in a
-//           cell, in slot order, then stores the sum.
+//   sum:    one workgroup per (setting, node) adds the shares of the 8 cells
+//           around its node in a fixed order (below) and stores the sum.
 // Each particle is read once per corner, so the mode costs several times the
 // atomic deposit: it is a reproducibility witness, not the production path.
 //
@@ -119,39 +118,87 @@ __global__ void k_det_starts(const uint64_t* __restrict__ keys, int64_t n2, int6
     start[s] = (uint32_t)lo;
 }
 
-// Node charge of one (setting, node, channel): the particles of the 8 cells
-// that have the node as a corner, each with its CIC weight as a dual.
+// Node charge of one (setting, node): a workgroup walks the particles of the
+// 8 cells that have the node as a corner, concatenated cell after cell;
+// thread t takes items t, t + DET_SUM_THREADS, ... and sums their shares
+// (each particle's CIC weight for this node as a dual) in that order, then
+// the threads' sums meet in a fixed butterfly per wavefront and the
+// wavefronts in index order. Every step of the order depends only on the
+// sorted keys, so the result is the same on every run.
+constexpr int DET_SUM_THREADS = 256;
+
 template <int NC>
-__global__ void k_det_sum(const double* __restrict__ st, int64_t cap, const uint64_t* __restrict__ keys,
-                          const uint32_t* __restrict__ start, const SettingDev* __restrict__ set, DetGeom g, int B) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = (int)(gid % NC);
-    const int64_t sn = gid / NC;
-    if (sn >= (int64_t)B * g.nodes) return;
-    const int b = (int)(sn / g.nodes);
-    const int64_t node = sn - (int64_t)b * g.nodes;
+__global__ __launch_bounds__(DET_SUM_THREADS) void k_det_sum(const double* __restrict__ st, int64_t cap,
+                                                             const uint64_t* __restrict__ keys,
+                                                             const uint32_t* __restrict__ start,
+                                                             const SettingDev* __restrict__ set, DetGeom g) {
+    __shared__ double red[DET_SUM_THREADS / 64][NC];
+    const int b = blockIdx.y;  // setting
+    const int64_t node = blockIdx.x;
     const int ix = (int)(node % g.nx), iy = (int)((node / g.nx) % g.ny), iz = (int)(node / ((int64_t)g.nx * g.ny));
+    // the 8 cells, corner order (kz, ky, kx); cells off the grid are empty
+    uint32_t beg[8], cum[9];
+    cum[0] = 0u;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int cx = ix - (c & 1), cy = iy - ((c >> 1) & 1), cz = iz - (c >> 2);
+        uint32_t n = 0u;
+        beg[c] = 0u;
+        if (cx >= 0 && cy >= 0 && cz >= 0) {
+            const int64_t s = (int64_t)b * g.nodes + ((int64_t)cz * g.ny + cy) * g.nx + cx;
+            beg[c] = start[s];
+            n = start[s + 1] - beg[c];
+        }
+        cum[c + 1] = cum[c] + n;
+    }
+    double* out = set[b].rho + node * NC;
+    if (cum[8] == 0u) {
+        if (threadIdx.x < NC) out[threadIdx.x] = 0.0;
+        return;
+    }
     const double q = set[b].q;
-    double acc = 0.0;
-    for (int kz = 0; kz < 2; ++kz)
-        for (int ky = 0; ky < 2; ++ky)
-            for (int kx = 0; kx < 2; ++kx) {
-                const int cx = ix - kx, cy = iy - ky, cz = iz - kz;
-                if (cx < 0 || cy < 0 || cz < 0) continue;
-                const int64_t s = (int64_t)b * g.nodes + ((int64_t)cz * g.ny + cy) * g.nx + cx;
-                const uint32_t e = start[s + 1];
-                for (uint32_t i = start[s]; i < e; ++i) {
-                    const int64_t p = (int64_t)(keys[i] & 0xffffffffull);
-                    const LD x = ldload(st + p * NC, c), y = ldload(st + (2 * cap + p) * NC, c),
-                             z = ldload(st + (4 * cap + p) * NC, c);
-                    const LD fx{(x.v - g.lo0) * g.ih0 - (double)cx, x.t * g.ih0};
-                    const LD fy{(y.v - g.lo1) * g.ih1 - (double)cy, y.t * g.ih1};
-                    const LD fz{(z.v - g.lo2) * g.ih2 - (double)cz, z.t * g.ih2};
-                    const LD w = (kx ? fx : 1.0 - fx) * ((ky ? fy : 1.0 - fy) * (kz ? fz : 1.0 - fz));
-                    acc += ldchan(w, c) * q;
-                }
-            }
-    set[b].rho[node * NC + c] = acc;
+    double acc[NC];
+#pragma unroll
+    for (int ch = 0; ch < NC; ++ch) acc[ch] = 0.0;
+    for (uint32_t j = threadIdx.x; j < cum[8]; j += DET_SUM_THREADS) {
+        int c = 0;
+#pragma unroll
+        for (int k = 1; k < 8; ++k) c += j >= cum[k] ? 1 : 0;
+        const int kx = c & 1, ky = (c >> 1) & 1, kz = c >> 2;
+        const int64_t p = (int64_t)(keys[beg[c] + (j - cum[c])] & 0xffffffffull);
+        const double* xs = st + p * NC;
+        const double* ys = st + (2 * cap + p) * NC;
+        const double* zs = st + (4 * cap + p) * NC;
+        const double sx = (xs[0] - g.lo0) * g.ih0, sy = (ys[0] - g.lo1) * g.ih1, sz = (zs[0] - g.lo2) * g.ih2;
+        // the cell's lower corner is (ix - kx, iy - ky, iz - kz); weight factor f or 1 - f per dimension
+        const double fx = sx - (double)(ix - kx), fy = sy - (double)(iy - ky), fz = sz - (double)(iz - kz);
+        const double ax = kx ? fx : 1.0 - fx, ay = ky ? fy : 1.0 - fy, az = kz ? fz : 1.0 - fz;
+        const double sgx = kx ? g.ih0 : -g.ih0, sgy = ky ? g.ih1 : -g.ih1, sgz = kz ? g.ih2 : -g.ih2;
+        const double ayz = ay * az;
+        acc[0] += (ax * ayz) * q;
+#pragma unroll
+        for (int ch = 1; ch < NC; ++ch) {
+            // d(ax ay az) = dax (ay az) + ax (day az + ay daz)
+            const double dyz = fma(ay, zs[ch] * sgz, (ys[ch] * sgy) * az);
+            const double w = fma(xs[ch] * sgx, ayz, ax * dyz);
+            acc[ch] += w * q;
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int ch = 0; ch < NC; ++ch) {
+        double v = acc[ch];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) red[wave][ch] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NC) {
+        double v = red[0][threadIdx.x];
+#pragma unroll
+        for (int w = 1; w < DET_SUM_THREADS / 64; ++w) v += red[w][threadIdx.x];
+        out[threadIdx.x] = v;
+    }
 }
 
 // Stored order back to the packed original order: the particle in slot p
@@ -215,12 +262,11 @@ hipError_t launch_deposit_det(dpic_ctx* cx) {
     }
     hipLaunchKernelGGL(k_det_starts, dim3((unsigned)((nseg + 1 + 255) / 256)), dim3(256), 0, cx->stream, keys, n2,
                        nseg, start);
-    const int64_t threads = nseg * NC;
-    const dim3 grid((unsigned)((threads + 255) / 256)), block(256);
+    const dim3 grid((unsigned)g.nodes, (unsigned)B), block(DET_SUM_THREADS);
     switch (NC) {
-        case 1: hipLaunchKernelGGL(k_det_sum<1>, grid, block, 0, cx->stream, w.st, cap, keys, start, w.set, g, B); break;
-        case 8: hipLaunchKernelGGL(k_det_sum<8>, grid, block, 0, cx->stream, w.st, cap, keys, start, w.set, g, B); break;
-        default: hipLaunchKernelGGL(k_det_sum<16>, grid, block, 0, cx->stream, w.st, cap, keys, start, w.set, g, B); break;
+        case 1: hipLaunchKernelGGL(k_det_sum<1>, grid, block, 0, cx->stream, w.st, cap, keys, start, w.set, g); break;
+        case 8: hipLaunchKernelGGL(k_det_sum<8>, grid, block, 0, cx->stream, w.st, cap, keys, start, w.set, g); break;
+        default: hipLaunchKernelGGL(k_det_sum<16>, grid, block, 0, cx->stream, w.st, cap, keys, start, w.set, g); break;
     }
     return hipGetLastError();
 }
