@@ -295,6 +295,244 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_cols(const double2* __res
     }
 }
 
+// ---------------------------------------------------------------- passes 2-4 fused
+// With 64 nodes in y and z (128-point transforms), passes 2-4 of the forward
+// solve run as one kernel: a workgroup takes one complex column (kx,
+// channel) of one setting and keeps its (z, y) plane in LDS, 66 x 128
+// values, so the two intermediates of passes 2 and 3 never reach HBM (the
+// solve's pass traffic falls from ~470 to ~200 MB at 64^3).
+//   y forward: each of the 64 input rows z, a 128-point transform of its 64
+//     nonzero values, as 16- and 8-point register DFTs around one in-place
+//     exchange in its plane row. Row slot 8 k1 + k2 ends up holding
+//     ky = k1 + 16 k2.
+//   z: each ky column, forward over its 64 nonzero z, times Ghat, inverse
+//     to the 66 needed z. The column has 66 slots, not 128, so the
+//     128-point transform is split by the parity of kz. The even kz are the
+//     64-point transform of x, the odd kz that of x W_128^z. Each half is
+//     two 8-point register stages around an exchange in the column's first
+//     64 slots, and so is its inverse. The inverse 128-point transform at z
+//     is e(z mod 64) + W_128^-z o(z mod 64), with e and o the two inverse
+//     halves.
+//   y inverse: each of the 66 output rows, 8- and 16-point stages around an
+//     exchange in the row, written to global memory at the 66 needed y.
+// All transforms are unnormalised; 1/(Mx My Mz) is in Ghat. The layouts in
+// global memory are those of passes 2-4, so passes 1 and 5 are unchanged.
+constexpr int YZ_M = 128, YZ_N = 64, YZ_NO = 66;
+constexpr int YZ_PS = YZ_M + 1;  // plane row stride (complex values), padded against bank conflicts
+constexpr int YZ_THREADS = 1024;
+
+struct YzArgs {
+    int W;                        // complex columns (Mx * NCC)
+    int64_t in_batch, out_batch;  // strides between settings
+    const double* ghat;
+    int ncc, gnx1, Mx;
+};
+
+__global__ __launch_bounds__(YZ_THREADS) void k_fft_yz(const double2* __restrict__ in, double2* __restrict__ out,
+                                                       YzArgs a, const double2* __restrict__ tw) {
+    constexpr int M = YZ_M, N = YZ_N, NO = YZ_NO, PS = YZ_PS, GZ = M / 2 + 1;
+    __shared__ double2 P[NO * PS];
+    __shared__ double twr[M], twi[M];
+    const int t = threadIdx.x;
+    for (int m = t; m < M; m += YZ_THREADS) {
+        const double2 w = tw[m];
+        twr[m] = w.x;
+        twi[m] = w.y;
+    }
+    // column of this workgroup: each XCD (workgroups round-robin over 8)
+    // takes a contiguous eighth of the columns, so the columns that share a
+    // cache line are read and written through one L2
+    const int wpx = a.W / 8;
+    const int col = (blockIdx.x % 8) * wpx + blockIdx.x / 8;
+    const double2* src = in + (int64_t)blockIdx.y * a.in_batch + col;
+    double2* dst = out + (int64_t)blockIdx.y * a.out_batch + col;
+    const int lo = t & 7;  // n2 or r: the thread's place in its group of 8
+    // the Ghat row (kx, ky) of this thread's z column p = t >> 3 (kz fastest)
+    const double* grow;
+    {
+        const int p = t >> 3, ky = (p >> 3) + 16 * (p & 7), kx = col / a.ncc;
+        const int gy = ky <= M - ky ? ky : M - ky;
+        const int gx = kx <= a.Mx - kx ? kx : a.Mx - kx;
+        grow = a.ghat + ((int64_t)gy * a.gnx1 + gx) * GZ;
+    }
+    // y forward, rows z < 64: stage A (thread (z, n2)), exchange, stage B (thread (z, r))
+    const bool rowt = t < N * 8;
+    const int zr = t >> 3;
+    double xr[16], xi[16];
+    if (rowt) {
+#pragma unroll
+        for (int n1 = 0; n1 < 16; ++n1) {
+            xr[n1] = 0.0;
+            xi[n1] = 0.0;
+        }
+#pragma unroll
+        for (int n1 = 0; n1 < 8; ++n1) {
+            const double2 v = src[((int64_t)zr * N + 8 * n1 + lo) * a.W];
+            xr[n1] = v.x;
+            xi[n1] = v.y;
+        }
+    }
+    __syncthreads();  // twiddle table
+    if (rowt) {
+        dft_reg<M, 16, false>(xr, xi);
+#pragma unroll
+        for (int k1 = 0; k1 < 16; ++k1) {
+            if (k1 > 0) twiddle<M, false>(xr[k1], xi[k1], lo * k1, twr, twi);
+            P[zr * PS + 8 * k1 + lo] = make_double2(xr[k1], xi[k1]);
+        }
+    }
+    __syncthreads();
+    if (rowt) {
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const int k1 = lo + 8 * g;
+            double hr[8], hi[8];
+#pragma unroll
+            for (int n2 = 0; n2 < 8; ++n2) {
+                const double2 v = P[zr * PS + 8 * k1 + n2];
+                hr[n2] = v.x;
+                hi[n2] = v.y;
+            }
+            dft_reg<M, 8, false>(hr, hi);
+#pragma unroll
+            for (int k2 = 0; k2 < 8; ++k2) P[zr * PS + 8 * k1 + k2] = make_double2(hr[k2], hi[k2]);
+        }
+    }
+    __syncthreads();
+    // z, column p = t >> 3 (slot p of every row): the thread holds x at z = 8 n1 + n2 (n2 = lo)
+    const int p = t >> 3;
+    double x0r[8], x0i[8];
+#pragma unroll
+    for (int n1 = 0; n1 < 8; ++n1) {
+        const double2 v = P[(8 * n1 + lo) * PS + p];
+        x0r[n1] = v.x;
+        x0i[n1] = v.y;
+    }
+    double er[8], ei[8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        // Ghat at kz = 2 (r + 8 k2) + h for role r = lo, issued before the stage that needs it
+        double gv[8];
+#pragma unroll
+        for (int k2 = 0; k2 < 8; ++k2) {
+            const int kz = 2 * (lo + 8 * k2) + h;
+            gv[k2] = grow[kz <= M - kz ? kz : M - kz];
+        }
+        __syncthreads();  // every read of the column's slots before is done
+        // stage A: 8-point DFT over n1 of x (x W_128^z for the odd kz), twiddle W_64^(n2 k1)
+        double ar[8], ai[8];
+#pragma unroll
+        for (int n1 = 0; n1 < 8; ++n1) {
+            ar[n1] = x0r[n1];
+            ai[n1] = x0i[n1];
+            if (h == 1) twiddle<M, false>(ar[n1], ai[n1], 8 * n1 + lo, twr, twi);
+        }
+        dft_reg<M, 8, false>(ar, ai);
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1) {
+            if (k1 > 0) twiddle<M, false>(ar[k1], ai[k1], 2 * lo * k1, twr, twi);
+            P[(8 * k1 + lo) * PS + p] = make_double2(ar[k1], ai[k1]);
+        }
+        __syncthreads();
+        // stage B (r = lo): 8-point DFT over n2 gives kk = r + 8 k2; times Ghat;
+        // inverse 8-point DFT over k2, twiddle W_64^(-r n2)
+        double br[8], bi[8];
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) {
+            const double2 v = P[(8 * lo + n2) * PS + p];
+            br[n2] = v.x;
+            bi[n2] = v.y;
+        }
+        dft_reg<M, 8, false>(br, bi);
+#pragma unroll
+        for (int k2 = 0; k2 < 8; ++k2) {
+            br[k2] *= gv[k2];
+            bi[k2] *= gv[k2];
+        }
+        dft_reg<M, 8, true>(br, bi);
+#pragma unroll
+        for (int n2 = 1; n2 < 8; ++n2) twiddle<M, true>(br[n2], bi[n2], 2 * lo * n2, twr, twi);
+        __syncthreads();  // every stage-B read is done
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) P[(8 * n2 + lo) * PS + p] = make_double2(br[n2], bi[n2]);
+        __syncthreads();
+        // stage A' (n2 = lo): inverse 8-point DFT over r gives z = n2 + 8 n1
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const double2 v = P[(8 * lo + r) * PS + p];
+            ar[r] = v.x;
+            ai[r] = v.y;
+        }
+        dft_reg<M, 8, true>(ar, ai);
+        if (h == 0) {
+#pragma unroll
+            for (int n1 = 0; n1 < 8; ++n1) {
+                er[n1] = ar[n1];
+                ei[n1] = ai[n1];
+            }
+        } else {
+            // combine at z = n2 + 8 n1 (slot z + 1); z = -1 and z = 64 reuse z mod 64
+            __syncthreads();  // every stage-A' read is done
+#pragma unroll
+            for (int n1 = 0; n1 < 8; ++n1) {
+                const int z = lo + 8 * n1;
+                double orr = ar[n1], oi = ai[n1];
+                twiddle<M, true>(orr, oi, z, twr, twi);
+                P[(z + 1) * PS + p] = make_double2(er[n1] + orr, ei[n1] + oi);
+            }
+            if (lo == 7) {  // z = -1 from z mod 64 = 63 (n1 = 7)
+                double orr = ar[7], oi = ai[7];
+                twiddle<M, true>(orr, oi, M - 1, twr, twi);
+                P[p] = make_double2(er[7] + orr, ei[7] + oi);
+            }
+            if (lo == 0) {  // z = 64 from z mod 64 = 0: W_128^-64 = -1
+                P[65 * PS + p] = make_double2(er[0] - ar[0], ei[0] - ai[0]);
+            }
+        }
+    }
+    __syncthreads();
+    // y inverse, rows zo < 66: stage 1 (thread (zo, r)), exchange, stage 2 (thread (zo, n2))
+    const bool outt = t < NO * 8;
+    double cr[2][8], ci[2][8];
+    if (outt) {
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const int k1 = lo + 8 * g;
+#pragma unroll
+            for (int k2 = 0; k2 < 8; ++k2) {
+                const double2 v = P[zr * PS + 8 * k1 + k2];
+                cr[g][k2] = v.x;
+                ci[g][k2] = v.y;
+            }
+            dft_reg<M, 8, true>(cr[g], ci[g]);
+#pragma unroll
+            for (int n2 = 1; n2 < 8; ++n2) twiddle<M, true>(cr[g][n2], ci[g][n2], n2 * k1, twr, twi);
+        }
+    }
+    __syncthreads();
+    if (outt) {
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int n2 = 0; n2 < 8; ++n2) P[zr * PS + 16 * n2 + lo + 8 * g] = make_double2(cr[g][n2], ci[g][n2]);
+    }
+    __syncthreads();
+    if (outt) {
+#pragma unroll
+        for (int k1 = 0; k1 < 16; ++k1) {
+            const double2 v = P[zr * PS + 16 * lo + k1];
+            xr[k1] = v.x;
+            xi[k1] = v.y;
+        }
+        dft_reg<M, 16, true>(xr, xi);
+#pragma unroll
+        for (int n1 = 0; n1 < 16; ++n1) {
+            const int yo = (lo + 8 * n1 + 1) & (M - 1);
+            if (yo < NO) dst[((int64_t)zr * NO + yo) * a.W] = make_double2(xr[n1], xi[n1]);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- passes 1 and 5
 // x transforms with the column kernels' stages: column b of a block is
 // complex channel j = b % NCC of row b / NCC; its value at x is the pair of
@@ -513,6 +751,26 @@ hipError_t launch_conv(dpic_ctx* cx, double* in, const int nin[3], double* out, 
     }
     if (e != hipSuccess) return e;
     const int64_t W = (int64_t)Mx * NCC;
+    if (My == YZ_M && Mz == YZ_M && nin[1] == YZ_N && nin[2] == YZ_N && nout[1] == YZ_NO && nout[2] == YZ_NO &&
+        shift == 1 && W % 8 == 0) {
+        // 2-4 fused: A -> D without the two intermediates
+        YzArgs y{};
+        y.W = (int)W;
+        y.in_batch = (int64_t)YZ_N * YZ_N * W;
+        y.out_batch = (int64_t)YZ_NO * YZ_NO * W;
+        y.ghat = cx->ws.ghat;
+        y.ncc = NCC;
+        y.gnx1 = nx + 1;
+        y.Mx = Mx;
+        hipLaunchKernelGGL(k_fft_yz, dim3((unsigned)W, nb), dim3(YZ_THREADS), 0, s, cx->ws.buf0, cx->ws.buf1, y, twy);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int rows = nout[1] * nout[2] * nb;
+        switch (NC) {
+            case 1: return launch_rows_inv_nc<1>(Mx, cx->ws.buf1, out, nout[0], shift, rows, twx, s);
+            case 8: return launch_rows_inv_nc<8>(Mx, cx->ws.buf1, out, nout[0], shift, rows, twx, s);
+            default: return launch_rows_inv_nc<16>(Mx, cx->ws.buf1, out, nout[0], shift, rows, twx, s);
+        }
+    }
     ColArgs a{};
     a.W = (int)W;
     a.bstride = 1;
