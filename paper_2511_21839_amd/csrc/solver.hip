@@ -328,6 +328,27 @@ struct YzArgs {
     int ncc, gnx1, Mx;
 };
 
+// (re, im) *= (wr, wi)
+__device__ __forceinline__ void cmul_by(double& re, double& im, double wr, double wi) {
+    const double t = re * wr - im * wi;
+    im = re * wi + im * wr;
+    re = t;
+}
+
+// (re, im) *= W_16^j (conjugated for inv), j a constant once the caller's loop is unrolled
+__device__ __forceinline__ void mul_w16_at(double& re, double& im, int j, bool inv) {
+#define DPIC_W16(J)                                        \
+    case J:                                                \
+        if (inv) mul_w16<J, true>(re, im);                 \
+        else mul_w16<J, false>(re, im);                    \
+        break;
+    switch (j & 15) {
+        DPIC_W16(0) DPIC_W16(1) DPIC_W16(2) DPIC_W16(3) DPIC_W16(4) DPIC_W16(5) DPIC_W16(6) DPIC_W16(7)
+        DPIC_W16(8) DPIC_W16(9) DPIC_W16(10) DPIC_W16(11) DPIC_W16(12) DPIC_W16(13) DPIC_W16(14) DPIC_W16(15)
+    }
+#undef DPIC_W16
+}
+
 __global__ __launch_bounds__(YZ_THREADS) void k_fft_yz(const double2* __restrict__ in, double2* __restrict__ out,
                                                        YzArgs a, const double2* __restrict__ tw) {
     constexpr int M = YZ_M, N = YZ_N, NO = YZ_NO, PS = YZ_PS, GZ = M / 2 + 1;
@@ -373,11 +394,18 @@ __global__ __launch_bounds__(YZ_THREADS) void k_fft_yz(const double2* __restrict
         }
     }
     __syncthreads();  // twiddle table
+    // the thread's twiddles are powers of W_128^lo (lo fixed per thread), times
+    // compile-time powers of W_16, formed in registers
     if (rowt) {
+        const double w1r = twr[lo], w1i = twi[lo];
         dft_reg<M, 16, false>(xr, xi);
+        double wr = w1r, wi = w1i;  // W^(lo k1)
 #pragma unroll
         for (int k1 = 0; k1 < 16; ++k1) {
-            if (k1 > 0) twiddle<M, false>(xr[k1], xi[k1], lo * k1, twr, twi);
+            if (k1 > 0) {
+                cmul_by(xr[k1], xi[k1], wr, wi);
+                cmul_by(wr, wi, w1r, w1i);
+            }
             P[zr * PS + 8 * k1 + lo] = make_double2(xr[k1], xi[k1]);
         }
     }
@@ -421,17 +449,28 @@ __global__ __launch_bounds__(YZ_THREADS) void k_fft_yz(const double2* __restrict
         __syncthreads();  // every read of the column's slots before is done
         // stage A: 8-point DFT over n1 of x (x W_128^z for the odd kz), twiddle W_64^(n2 k1)
         double ar[8], ai[8];
+        const double w1r = twr[lo], w1i = twi[lo];
 #pragma unroll
         for (int n1 = 0; n1 < 8; ++n1) {
             ar[n1] = x0r[n1];
             ai[n1] = x0i[n1];
-            if (h == 1) twiddle<M, false>(ar[n1], ai[n1], 8 * n1 + lo, twr, twi);
+            if (h == 1) {  // W_128^(8 n1 + lo)
+                cmul_by(ar[n1], ai[n1], w1r, w1i);
+                mul_w16_at(ar[n1], ai[n1], n1, false);
+            }
         }
         dft_reg<M, 8, false>(ar, ai);
+        const double w2r = twr[2 * lo], w2i = twi[2 * lo];  // W_128^(2 lo)
+        {
+            double wr = w2r, wi = w2i;  // W^(2 lo k1)
 #pragma unroll
-        for (int k1 = 0; k1 < 8; ++k1) {
-            if (k1 > 0) twiddle<M, false>(ar[k1], ai[k1], 2 * lo * k1, twr, twi);
-            P[(8 * k1 + lo) * PS + p] = make_double2(ar[k1], ai[k1]);
+            for (int k1 = 0; k1 < 8; ++k1) {
+                if (k1 > 0) {
+                    cmul_by(ar[k1], ai[k1], wr, wi);
+                    cmul_by(wr, wi, w2r, w2i);
+                }
+                P[(8 * k1 + lo) * PS + p] = make_double2(ar[k1], ai[k1]);
+            }
         }
         __syncthreads();
         // stage B (r = lo): 8-point DFT over n2 gives kk = r + 8 k2; times Ghat;
@@ -450,8 +489,15 @@ __global__ __launch_bounds__(YZ_THREADS) void k_fft_yz(const double2* __restrict
             bi[k2] *= gv[k2];
         }
         dft_reg<M, 8, true>(br, bi);
+        {
+            const double w2r = twr[2 * lo], w2i = twi[2 * lo];
+            double wr = w2r, wi = -w2i;  // W^(-2 lo n2)
 #pragma unroll
-        for (int n2 = 1; n2 < 8; ++n2) twiddle<M, true>(br[n2], bi[n2], 2 * lo * n2, twr, twi);
+            for (int n2 = 1; n2 < 8; ++n2) {
+                cmul_by(br[n2], bi[n2], wr, wi);
+                cmul_by(wr, wi, w2r, -w2i);
+            }
+        }
         __syncthreads();  // every stage-B read is done
 #pragma unroll
         for (int n2 = 0; n2 < 8; ++n2) P[(8 * n2 + lo) * PS + p] = make_double2(br[n2], bi[n2]);
@@ -473,11 +519,13 @@ __global__ __launch_bounds__(YZ_THREADS) void k_fft_yz(const double2* __restrict
         } else {
             // combine at z = n2 + 8 n1 (slot z + 1); z = -1 and z = 64 reuse z mod 64
             __syncthreads();  // every stage-A' read is done
+            const double w1r = twr[lo], w1i = twi[lo];
 #pragma unroll
             for (int n1 = 0; n1 < 8; ++n1) {
                 const int z = lo + 8 * n1;
-                double orr = ar[n1], oi = ai[n1];
-                twiddle<M, true>(orr, oi, z, twr, twi);
+                double orr = ar[n1], oi = ai[n1];  // times W_128^-z = W_128^-lo W_16^-n1
+                cmul_by(orr, oi, w1r, -w1i);
+                mul_w16_at(orr, oi, n1, true);
                 P[(z + 1) * PS + p] = make_double2(er[n1] + orr, ei[n1] + oi);
             }
             if (lo == 7) {  // z = -1 from z mod 64 = 63 (n1 = 7)
@@ -505,8 +553,14 @@ __global__ __launch_bounds__(YZ_THREADS) void k_fft_yz(const double2* __restrict
                 ci[g][k2] = v.y;
             }
             dft_reg<M, 8, true>(cr[g], ci[g]);
+            const double w1r = twr[lo], w1i = twi[lo];
+            double wr = w1r, wi = -w1i;  // W^(-n2 lo); k1 = lo + 8 g adds W_16^(-n2 g)
 #pragma unroll
-            for (int n2 = 1; n2 < 8; ++n2) twiddle<M, true>(cr[g][n2], ci[g][n2], n2 * k1, twr, twi);
+            for (int n2 = 1; n2 < 8; ++n2) {
+                cmul_by(cr[g][n2], ci[g][n2], wr, wi);
+                if (g == 1) mul_w16_at(cr[g][n2], ci[g][n2], n2, true);
+                cmul_by(wr, wi, w1r, -w1i);
+            }
         }
     }
     __syncthreads();
