@@ -239,8 +239,13 @@ int dpic_load_state(dpic_ctx* ctx, const void* dev_buf);
 
 /*
  * Options:
- *  DPIC_OPT_SORT_EVERY = re-sort particles by grid tile every k steps (0 = never,
- *    default 5);
+ *  DPIC_OPT_SORT_EVERY = re-sort particles by grid tile every k steps, for
+ *    the tiled particle kernel (k > 0); 0 = never (storage-order kernel,
+ *    deposit by global atomics); -1 = automatic, the default: every 5 steps
+ *    from 32768 particles (all settings together) up, or while the adjoint
+ *    is bound, else never (with fewer particles the storage-order kernel
+ *    is faster). Other values are EINVAL; dpic_get_option returns -1 while
+ *    automatic;
  *  DPIC_OPT_STAGE_TIMING = 1 records HIP events around every stage launch of
  *    dpic_step, 2 around the particle stage only (fewer event records in the
  *    stream: each leaves the GPU idle for a few microseconds), 3 around the
@@ -296,8 +301,8 @@ int dpic_get_option(const dpic_ctx* ctx, int option, int64_t* value);
 
 /*
  * Autotuner: times trial_steps steps from the current state for candidate
- * work-item sizes, persistent grid sizes and sort cadences (coordinate
- * search), restores the state and the counters after every trial, and keeps
+ * work-item sizes, persistent grid sizes and sort cadences (0, 5, 10, 12,
+ * 20, 40 steps; coordinate search), restores the state and the counters after every trial, and keeps
  * the fastest setting. scratch_dev: caller device memory of at least
  * dpic_state_bytes(). best[3] (host, may be NULL) receives
  * {sort_every, chunk, part_blocks}; ms_best the time of the winning trial.

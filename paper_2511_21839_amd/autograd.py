@@ -18,9 +18,11 @@ from . import dpic
 
 class AdjointRun:
     def __init__(self, n_particles: int, grid, lo, hi, beam, lattice, xi: np.ndarray, n_steps: int,
-                 checkpoint_every: int = 50, sort_every: int = 20, graph: bool = False):
+                 checkpoint_every: int = 50, sort_every: int = -1, graph: bool = False):
         """beam = (kinetic_eV, rest_eV, charge_e, bunch_charge_C);
         lattice = (kind, n_steps, L, k, L_param, k_param, n_periods);
+        sort_every: the library option (-1, automatic: with the adjoint bound
+        the beam is sorted once and the tiled kernels run);
         graph: capture the forward steps and the adjoint sweep in HIP graphs
         on first use and replay them afterwards."""
         self.sim = dpic.Simulation(n_particles, 0, grid)

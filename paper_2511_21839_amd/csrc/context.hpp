@@ -75,6 +75,8 @@ constexpr int TILE_HALO = 1;                             // drift allowance (cel
 constexpr int TILE_R = TILE_EDGE + 2 * TILE_HALO + 1;    // deposit tile nodes per dimension
 constexpr int TILE_RZ_E = TILE_EDGE + 1;                 // E tile nodes in z
 constexpr int TILE_CHUNK = 768;                          // default particles per tiled work item
+constexpr int64_t SORT_AUTO_CADENCE = 5;                 // automatic cadence: re-sort every 5 steps
+constexpr int64_t SORT_AUTO_MIN_PARTICLES = 32768;       // ... from this many particles (all settings) up
 constexpr int CHUNK_MIN = 128;                           // smallest work item (sizes the work list)
 constexpr int CHUNK_MAX = 8192;
 constexpr int SORT_PB = SEG;                             // particles per sort block
@@ -166,7 +168,7 @@ struct dpic_ctx {
     int64_t cur_step = 0;             // schedule step of the particle launch being enqueued
     bool swapped = false;             // ws.st holds the second state buffer
     // options
-    int64_t sort_every = 5;
+    int64_t sort_every = -1;  // re-sort cadence; -1 automatic (sort_cadence in capi.hip)
     int64_t chunk = dpic::TILE_CHUNK;  // particles per tiled work item
     int64_t part_blocks = 0;           // workgroups of the tiled particle kernel (0: resident capacity)
     bool chunks_valid = false;  // the tiled work list matches the stored order

@@ -34,7 +34,7 @@ def _batch(ns, ntan=7, grid=16, steps_per_element=3, seed=5, perturb_sigma=True,
     return synth.perturbed_batch(base, ns, seed, perturb_sigma=perturb_sigma)
 
 
-def _make(batch, capacity=None, sort_every=None, graph=False, chunk=None, part_blocks=None):
+def _make(batch, capacity=None, sort_every=5, graph=False, chunk=None, part_blocks=None):
     from paper_2511_21839_amd import dpic
 
     w = batch.base
@@ -114,7 +114,7 @@ def test_batch_with_streamed_fields_matches_oracle():
         assert_outputs_close(emit[b], ref.emittance, what=f"emittance of setting {b}")
 
 
-@pytest.mark.parametrize("sort_every", [None, 0, 4])
+@pytest.mark.parametrize("sort_every", [None, 5, 0, 4])
 def test_batch_settings_match_their_own_oracle_runs(sort_every):
     # ragged counts: one below a segment, one empty, one spanning three segments
     batch = _batch([1500, 0, 2600, 700])
@@ -289,7 +289,7 @@ def test_autotune_keeps_the_state_and_picks_a_candidate():
     sim.step(3)
     res = sim.autotune(trial_steps=8)
     assert res["chunk"] in (256, 512, 768, 1024, 2048)
-    assert res["sort_every"] in (5, 10, 12, 20, 40)
+    assert res["sort_every"] in (0, 5, 10, 12, 20, 40)
     assert res["part_blocks"] >= 0 and res["ms"] > 0
     assert sim.get_option(dpic.OPT_CHUNK) == res["chunk"]
     assert sim.counters()[1] == 3  # state and step counter restored

@@ -140,6 +140,24 @@ def test_tiny_space_charge_run_matches_oracle(sort_every):
     _compare_run(w, sim, _oracle(w))
 
 
+def test_automatic_sort_choice_follows_the_beam_size():
+    """The default cadence (-1) tiles and re-sorts only from 32768 particles
+    up; either way the run matches the oracle."""
+    from paper_2511_21839_amd import dpic
+
+    for n, sorted_run in ((3000, False), (40000, True)):
+        w = synth.tiny(n_particles=n, grid=16, steps_per_element=3)
+        sim = make_sim(w, sort_every=None)
+        assert sim.get_option(dpic.OPT_SORT_EVERY) == -1
+        sim.set_option(dpic.OPT_STAGE_TIMING, 1)
+        sim.stage_times()
+        sim.step(w.total_steps())
+        _, launches = sim.stage_times()
+        assert (launches[3] > 0) == sorted_run, (n, launches)
+        sim.set_option(dpic.OPT_STAGE_TIMING, 0)
+        _compare_run(w, sim, _oracle(w))
+
+
 def test_tiled_deposit_with_drift_beyond_the_halo():
     # large momentum spread and a single sort: many particles leave their
     # tile's LDS window and take the global-atomic path of the tiled kernel
