@@ -296,30 +296,39 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_cols(const double2* __res
 }
 
 // ---------------------------------------------------------------- passes 2-4 fused
-// With 64 nodes in y and z (128-point transforms), passes 2-4 of the forward
-// solve run as one kernel: a workgroup takes one complex column (kx,
-// channel) of one setting and keeps its (z, y) plane in LDS, 66 x 128
-// values, so the two intermediates of passes 2 and 3 never reach HBM (the
-// solve's pass traffic falls from ~470 to ~200 MB at 64^3).
-//   y forward: each of the 64 input rows z, a 128-point transform of its 64
-//     nonzero values, as 16- and 8-point register DFTs around one in-place
+// With M-point y and z transforms, M = 128 or 64 (64 or 32 nodes), passes
+// 2-4 of the forward solve run as one kernel: a workgroup takes one complex
+// column (kx, channel) of one setting and keeps its (z, y) plane in LDS,
+// (M/2 + 2) x M values, so the two intermediates of passes 2 and 3 never
+// reach HBM (at 64^3 the solve's pass traffic falls from ~470 to ~200 MB).
+// With n = M/2 nonzero inputs per dimension and RA = M/8:
+//   y forward: each of the n input rows z, an M-point transform of its n
+//     nonzero values, as RA- and 8-point register DFTs around one in-place
 //     exchange in its plane row. Row slot 8 k1 + k2 ends up holding
-//     ky = k1 + 16 k2.
-//   z: each ky column, forward over its 64 nonzero z, times Ghat, inverse
-//     to the 66 needed z. The column has 66 slots, not 128, so the
-//     128-point transform is split by the parity of kz. The even kz are the
-//     64-point transform of x, the odd kz that of x W_128^z. Each half is
-//     two 8-point register stages around an exchange in the column's first
-//     64 slots, and so is its inverse. The inverse 128-point transform at z
-//     is e(z mod 64) + W_128^-z o(z mod 64), with e and o the two inverse
-//     halves.
-//   y inverse: each of the 66 output rows, 8- and 16-point stages around an
-//     exchange in the row, written to global memory at the 66 needed y.
+//     ky = k1 + RA k2.
+//   z: each ky column, forward over its n nonzero z, times Ghat, inverse to
+//     the n + 2 needed z. The column has n + 2 slots, not M, so the M-point
+//     transform is split by the parity of kz. The even kz are the n-point
+//     transform of x, the odd kz that of x W_M^z. Each half is an
+//     (n/8)-point and an 8-point register stage around an exchange in the
+//     column's first n slots, and so is its inverse. The inverse M-point
+//     transform at z is e(z mod n) + W_M^-z o(z mod n), with e and o the
+//     two inverse halves.
+//   y inverse: each of the n + 2 output rows, 8- and RA-point stages around
+//     an exchange in the row, written to global memory at the n + 2 needed y.
 // All transforms are unnormalised; 1/(Mx My Mz) is in Ghat. The layouts in
 // global memory are those of passes 2-4, so passes 1 and 5 are unchanged.
-constexpr int YZ_M = 128, YZ_N = 64, YZ_NO = 66;
-constexpr int YZ_PS = YZ_M + 1;  // plane row stride (complex values), padded against bank conflicts
-constexpr int YZ_THREADS = 1024;
+// A thread's twiddles are powers of W_M^lo (lo, its place in its group of
+// 8, is fixed) times compile-time powers of W_16, formed in registers.
+template <int M>
+struct YzCfg {
+    static constexpr int N = M / 2, NO = N + 2;
+    static constexpr int PS = M + 1;        // plane row stride (complex values), padded against bank conflicts
+    static constexpr int RA = M / 8;        // row transforms: RA-point then 8-point stages
+    static constexpr int HA = M / 16;       // z halves (N points): HA-point then 8-point stages
+    static constexpr int NT = 8 * M;        // threads: 8 per column in the z transforms
+    static constexpr int W16 = 128 / M;     // W_M^8 = W_16^W16
+};
 
 struct YzArgs {
     int W;                        // complex columns (Mx * NCC)
@@ -349,13 +358,16 @@ __device__ __forceinline__ void mul_w16_at(double& re, double& im, int j, bool i
 #undef DPIC_W16
 }
 
-__global__ __launch_bounds__(YZ_THREADS) void k_fft_yz(const double2* __restrict__ in, double2* __restrict__ out,
-                                                       YzArgs a, const double2* __restrict__ tw) {
-    constexpr int M = YZ_M, N = YZ_N, NO = YZ_NO, PS = YZ_PS, GZ = M / 2 + 1;
+template <int M>
+__global__ __launch_bounds__(YzCfg<M>::NT) void k_fft_yz(const double2* __restrict__ in, double2* __restrict__ out,
+                                                         YzArgs a, const double2* __restrict__ tw) {
+    using C = YzCfg<M>;
+    constexpr int N = C::N, NO = C::NO, PS = C::PS, RA = C::RA, HA = C::HA, NT = C::NT, W16 = C::W16;
+    constexpr int GZ = M / 2 + 1;
     __shared__ double2 P[NO * PS];
     __shared__ double twr[M], twi[M];
     const int t = threadIdx.x;
-    for (int m = t; m < M; m += YZ_THREADS) {
+    for (int m = t; m < M; m += NT) {
         const double2 w = tw[m];
         twr[m] = w.x;
         twi[m] = w.y;
@@ -371,37 +383,35 @@ __global__ __launch_bounds__(YZ_THREADS) void k_fft_yz(const double2* __restrict
     // the Ghat row (kx, ky) of this thread's z column p = t >> 3 (kz fastest)
     const double* grow;
     {
-        const int p = t >> 3, ky = (p >> 3) + 16 * (p & 7), kx = col / a.ncc;
+        const int p = t >> 3, ky = (p >> 3) + RA * (p & 7), kx = col / a.ncc;
         const int gy = ky <= M - ky ? ky : M - ky;
         const int gx = kx <= a.Mx - kx ? kx : a.Mx - kx;
         grow = a.ghat + ((int64_t)gy * a.gnx1 + gx) * GZ;
     }
-    // y forward, rows z < 64: stage A (thread (z, n2)), exchange, stage B (thread (z, r))
+    // y forward, rows z < n: stage A (thread (z, n2)), exchange, stage B (thread (z, r))
     const bool rowt = t < N * 8;
     const int zr = t >> 3;
-    double xr[16], xi[16];
+    double xr[RA], xi[RA];
     if (rowt) {
 #pragma unroll
-        for (int n1 = 0; n1 < 16; ++n1) {
+        for (int n1 = 0; n1 < RA; ++n1) {
             xr[n1] = 0.0;
             xi[n1] = 0.0;
         }
 #pragma unroll
-        for (int n1 = 0; n1 < 8; ++n1) {
+        for (int n1 = 0; n1 < RA / 2; ++n1) {
             const double2 v = src[((int64_t)zr * N + 8 * n1 + lo) * a.W];
             xr[n1] = v.x;
             xi[n1] = v.y;
         }
     }
     __syncthreads();  // twiddle table
-    // the thread's twiddles are powers of W_128^lo (lo fixed per thread), times
-    // compile-time powers of W_16, formed in registers
     if (rowt) {
         const double w1r = twr[lo], w1i = twi[lo];
-        dft_reg<M, 16, false>(xr, xi);
+        dft_reg<M, RA, false>(xr, xi);
         double wr = w1r, wi = w1i;  // W^(lo k1)
 #pragma unroll
-        for (int k1 = 0; k1 < 16; ++k1) {
+        for (int k1 = 0; k1 < RA; ++k1) {
             if (k1 > 0) {
                 cmul_by(xr[k1], xi[k1], wr, wi);
                 cmul_by(wr, wi, w1r, w1i);
@@ -412,7 +422,7 @@ __global__ __launch_bounds__(YZ_THREADS) void k_fft_yz(const double2* __restrict
     __syncthreads();
     if (rowt) {
 #pragma unroll
-        for (int g = 0; g < 2; ++g) {
+        for (int g = 0; g < RA / 8; ++g) {
             const int k1 = lo + 8 * g;
             double hr[8], hi[8];
 #pragma unroll
@@ -429,42 +439,45 @@ __global__ __launch_bounds__(YZ_THREADS) void k_fft_yz(const double2* __restrict
     __syncthreads();
     // z, column p = t >> 3 (slot p of every row): the thread holds x at z = 8 n1 + n2 (n2 = lo)
     const int p = t >> 3;
-    double x0r[8], x0i[8];
+    double x0r[HA], x0i[HA];
 #pragma unroll
-    for (int n1 = 0; n1 < 8; ++n1) {
+    for (int n1 = 0; n1 < HA; ++n1) {
         const double2 v = P[(8 * n1 + lo) * PS + p];
         x0r[n1] = v.x;
         x0i[n1] = v.y;
     }
-    double er[8], ei[8];
+    double er[HA], ei[HA];
+    const bool bt = lo < HA;  // stage-B role r = lo: the HA groups k1
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        // Ghat at kz = 2 (r + 8 k2) + h for role r = lo, issued before the stage that needs it
+        // Ghat at kz = 2 (r + HA k2) + h for role r = lo, issued before the stage that needs it
         double gv[8];
 #pragma unroll
         for (int k2 = 0; k2 < 8; ++k2) {
-            const int kz = 2 * (lo + 8 * k2) + h;
-            gv[k2] = grow[kz <= M - kz ? kz : M - kz];
+            const int kz = 2 * (lo + HA * k2) + h;
+            gv[k2] = bt ? grow[kz <= M - kz ? kz : M - kz] : 0.0;
         }
         __syncthreads();  // every read of the column's slots before is done
-        // stage A: 8-point DFT over n1 of x (x W_128^z for the odd kz), twiddle W_64^(n2 k1)
-        double ar[8], ai[8];
-        const double w1r = twr[lo], w1i = twi[lo];
+        // stage A: HA-point DFT over n1 of x (x W_M^z for the odd kz), twiddle W_n^(n2 k1)
+        double ar[HA], ai[HA];
+        {
+            const double w1r = twr[lo], w1i = twi[lo];
 #pragma unroll
-        for (int n1 = 0; n1 < 8; ++n1) {
-            ar[n1] = x0r[n1];
-            ai[n1] = x0i[n1];
-            if (h == 1) {  // W_128^(8 n1 + lo)
-                cmul_by(ar[n1], ai[n1], w1r, w1i);
-                mul_w16_at(ar[n1], ai[n1], n1, false);
+            for (int n1 = 0; n1 < HA; ++n1) {
+                ar[n1] = x0r[n1];
+                ai[n1] = x0i[n1];
+                if (h == 1) {  // W_M^(8 n1 + lo)
+                    cmul_by(ar[n1], ai[n1], w1r, w1i);
+                    mul_w16_at(ar[n1], ai[n1], W16 * n1, false);
+                }
             }
         }
-        dft_reg<M, 8, false>(ar, ai);
-        const double w2r = twr[2 * lo], w2i = twi[2 * lo];  // W_128^(2 lo)
+        dft_reg<M, HA, false>(ar, ai);
         {
-            double wr = w2r, wi = w2i;  // W^(2 lo k1)
+            const double w2r = twr[2 * lo], w2i = twi[2 * lo];  // W_M^(2 lo) = W_n^lo
+            double wr = w2r, wi = w2i;
 #pragma unroll
-            for (int k1 = 0; k1 < 8; ++k1) {
+            for (int k1 = 0; k1 < HA; ++k1) {
                 if (k1 > 0) {
                     cmul_by(ar[k1], ai[k1], wr, wi);
                     cmul_by(wr, wi, w2r, w2i);
@@ -473,23 +486,23 @@ __global__ __launch_bounds__(YZ_THREADS) void k_fft_yz(const double2* __restrict
             }
         }
         __syncthreads();
-        // stage B (r = lo): 8-point DFT over n2 gives kk = r + 8 k2; times Ghat;
-        // inverse 8-point DFT over k2, twiddle W_64^(-r n2)
+        // stage B (r = lo < HA): 8-point DFT over n2 gives kk = r + HA k2; times Ghat;
+        // inverse 8-point DFT over k2, twiddle W_n^(-r n2)
         double br[8], bi[8];
+        if (bt) {
 #pragma unroll
-        for (int n2 = 0; n2 < 8; ++n2) {
-            const double2 v = P[(8 * lo + n2) * PS + p];
-            br[n2] = v.x;
-            bi[n2] = v.y;
-        }
-        dft_reg<M, 8, false>(br, bi);
+            for (int n2 = 0; n2 < 8; ++n2) {
+                const double2 v = P[(8 * lo + n2) * PS + p];
+                br[n2] = v.x;
+                bi[n2] = v.y;
+            }
+            dft_reg<M, 8, false>(br, bi);
 #pragma unroll
-        for (int k2 = 0; k2 < 8; ++k2) {
-            br[k2] *= gv[k2];
-            bi[k2] *= gv[k2];
-        }
-        dft_reg<M, 8, true>(br, bi);
-        {
+            for (int k2 = 0; k2 < 8; ++k2) {
+                br[k2] *= gv[k2];
+                bi[k2] *= gv[k2];
+            }
+            dft_reg<M, 8, true>(br, bi);
             const double w2r = twr[2 * lo], w2i = twi[2 * lo];
             double wr = w2r, wi = -w2i;  // W^(-2 lo n2)
 #pragma unroll
@@ -499,52 +512,54 @@ __global__ __launch_bounds__(YZ_THREADS) void k_fft_yz(const double2* __restrict
             }
         }
         __syncthreads();  // every stage-B read is done
+        if (bt)
 #pragma unroll
-        for (int n2 = 0; n2 < 8; ++n2) P[(8 * n2 + lo) * PS + p] = make_double2(br[n2], bi[n2]);
+            for (int n2 = 0; n2 < 8; ++n2) P[(HA * n2 + lo) * PS + p] = make_double2(br[n2], bi[n2]);
         __syncthreads();
-        // stage A' (n2 = lo): inverse 8-point DFT over r gives z = n2 + 8 n1
+        // stage A' (n2 = lo): inverse HA-point DFT over r gives z = n2 + 8 n1
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const double2 v = P[(8 * lo + r) * PS + p];
+        for (int r = 0; r < HA; ++r) {
+            const double2 v = P[(HA * lo + r) * PS + p];
             ar[r] = v.x;
             ai[r] = v.y;
         }
-        dft_reg<M, 8, true>(ar, ai);
+        dft_reg<M, HA, true>(ar, ai);
         if (h == 0) {
 #pragma unroll
-            for (int n1 = 0; n1 < 8; ++n1) {
+            for (int n1 = 0; n1 < HA; ++n1) {
                 er[n1] = ar[n1];
                 ei[n1] = ai[n1];
             }
         } else {
-            // combine at z = n2 + 8 n1 (slot z + 1); z = -1 and z = 64 reuse z mod 64
+            // combine at z = n2 + 8 n1 (slot z + 1); z = -1 and z = n reuse z mod n
             __syncthreads();  // every stage-A' read is done
             const double w1r = twr[lo], w1i = twi[lo];
 #pragma unroll
-            for (int n1 = 0; n1 < 8; ++n1) {
+            for (int n1 = 0; n1 < HA; ++n1) {
                 const int z = lo + 8 * n1;
-                double orr = ar[n1], oi = ai[n1];  // times W_128^-z = W_128^-lo W_16^-n1
+                double orr = ar[n1], oi = ai[n1];  // times W_M^-z = W_M^-lo W_16^-(W16 n1)
                 cmul_by(orr, oi, w1r, -w1i);
-                mul_w16_at(orr, oi, n1, true);
+                mul_w16_at(orr, oi, W16 * n1, true);
                 P[(z + 1) * PS + p] = make_double2(er[n1] + orr, ei[n1] + oi);
             }
-            if (lo == 7) {  // z = -1 from z mod 64 = 63 (n1 = 7)
-                double orr = ar[7], oi = ai[7];
+            if (lo == 7) {  // z = -1 from z mod n = n - 1 (n1 = HA - 1)
+                double orr = ar[HA - 1], oi = ai[HA - 1];
                 twiddle<M, true>(orr, oi, M - 1, twr, twi);
-                P[p] = make_double2(er[7] + orr, ei[7] + oi);
+                P[p] = make_double2(er[HA - 1] + orr, ei[HA - 1] + oi);
             }
-            if (lo == 0) {  // z = 64 from z mod 64 = 0: W_128^-64 = -1
-                P[65 * PS + p] = make_double2(er[0] - ar[0], ei[0] - ai[0]);
+            if (lo == 0) {  // z = n from z mod n = 0: W_M^-n = -1
+                P[(N + 1) * PS + p] = make_double2(er[0] - ar[0], ei[0] - ai[0]);
             }
         }
     }
     __syncthreads();
-    // y inverse, rows zo < 66: stage 1 (thread (zo, r)), exchange, stage 2 (thread (zo, n2))
+    // y inverse, rows zo < n + 2: stage 1 (thread (zo, r)), exchange, stage 2 (thread (zo, n2))
     const bool outt = t < NO * 8;
-    double cr[2][8], ci[2][8];
+    double cr[RA / 8][8], ci[RA / 8][8];
     if (outt) {
+        const double w1r = twr[lo], w1i = twi[lo];
 #pragma unroll
-        for (int g = 0; g < 2; ++g) {
+        for (int g = 0; g < RA / 8; ++g) {
             const int k1 = lo + 8 * g;
 #pragma unroll
             for (int k2 = 0; k2 < 8; ++k2) {
@@ -553,12 +568,11 @@ __global__ __launch_bounds__(YZ_THREADS) void k_fft_yz(const double2* __restrict
                 ci[g][k2] = v.y;
             }
             dft_reg<M, 8, true>(cr[g], ci[g]);
-            const double w1r = twr[lo], w1i = twi[lo];
-            double wr = w1r, wi = -w1i;  // W^(-n2 lo); k1 = lo + 8 g adds W_16^(-n2 g)
+            double wr = w1r, wi = -w1i;  // W^(-n2 lo); k1 = lo + 8 g adds W_M^(-8 n2 g)
 #pragma unroll
             for (int n2 = 1; n2 < 8; ++n2) {
                 cmul_by(cr[g][n2], ci[g][n2], wr, wi);
-                if (g == 1) mul_w16_at(cr[g][n2], ci[g][n2], n2, true);
+                if (g > 0) mul_w16_at(cr[g][n2], ci[g][n2], W16 * n2 * g, true);
                 cmul_by(wr, wi, w1r, -w1i);
             }
         }
@@ -566,21 +580,21 @@ __global__ __launch_bounds__(YZ_THREADS) void k_fft_yz(const double2* __restrict
     __syncthreads();
     if (outt) {
 #pragma unroll
-        for (int g = 0; g < 2; ++g)
+        for (int g = 0; g < RA / 8; ++g)
 #pragma unroll
-            for (int n2 = 0; n2 < 8; ++n2) P[zr * PS + 16 * n2 + lo + 8 * g] = make_double2(cr[g][n2], ci[g][n2]);
+            for (int n2 = 0; n2 < 8; ++n2) P[zr * PS + RA * n2 + lo + 8 * g] = make_double2(cr[g][n2], ci[g][n2]);
     }
     __syncthreads();
     if (outt) {
 #pragma unroll
-        for (int k1 = 0; k1 < 16; ++k1) {
-            const double2 v = P[zr * PS + 16 * lo + k1];
+        for (int k1 = 0; k1 < RA; ++k1) {
+            const double2 v = P[zr * PS + RA * lo + k1];
             xr[k1] = v.x;
             xi[k1] = v.y;
         }
-        dft_reg<M, 16, true>(xr, xi);
+        dft_reg<M, RA, true>(xr, xi);
 #pragma unroll
-        for (int n1 = 0; n1 < 16; ++n1) {
+        for (int n1 = 0; n1 < RA; ++n1) {
             const int yo = (lo + 8 * n1 + 1) & (M - 1);
             if (yo < NO) dst[((int64_t)zr * NO + yo) * a.W] = make_double2(xr[n1], xi[n1]);
         }
@@ -805,18 +819,24 @@ hipError_t launch_conv(dpic_ctx* cx, double* in, const int nin[3], double* out, 
     }
     if (e != hipSuccess) return e;
     const int64_t W = (int64_t)Mx * NCC;
-    if (My == YZ_M && Mz == YZ_M && nin[1] == YZ_N && nin[2] == YZ_N && nout[1] == YZ_NO && nout[2] == YZ_NO &&
-        shift == 1 && W % 8 == 0) {
+    if (My == Mz && (My == 128 || My == 64) && nin[1] == My / 2 && nin[2] == My / 2 && nout[1] == My / 2 + 2 &&
+        nout[2] == My / 2 + 2 && shift == 1 && W % 8 == 0) {
         // 2-4 fused: A -> D without the two intermediates
+        const int64_t n = My / 2;
         YzArgs y{};
         y.W = (int)W;
-        y.in_batch = (int64_t)YZ_N * YZ_N * W;
-        y.out_batch = (int64_t)YZ_NO * YZ_NO * W;
+        y.in_batch = n * n * W;
+        y.out_batch = (n + 2) * (n + 2) * W;
         y.ghat = cx->ws.ghat;
         y.ncc = NCC;
         y.gnx1 = nx + 1;
         y.Mx = Mx;
-        hipLaunchKernelGGL(k_fft_yz, dim3((unsigned)W, nb), dim3(YZ_THREADS), 0, s, cx->ws.buf0, cx->ws.buf1, y, twy);
+        if (My == 128)
+            hipLaunchKernelGGL(k_fft_yz<128>, dim3((unsigned)W, nb), dim3(YzCfg<128>::NT), 0, s, cx->ws.buf0,
+                               cx->ws.buf1, y, twy);
+        else
+            hipLaunchKernelGGL(k_fft_yz<64>, dim3((unsigned)W, nb), dim3(YzCfg<64>::NT), 0, s, cx->ws.buf0,
+                               cx->ws.buf1, y, twy);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const int rows = nout[1] * nout[2] * nb;
         switch (NC) {

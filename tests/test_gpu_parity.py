@@ -71,9 +71,10 @@ def test_stage_deposit_matches_oracle():
         assert normwise_err(got[..., ch], want[..., ch]) <= 1e-12, ch
 
 
-# 64 nodes in y and z take the fused y-z pass (passes 2-4 in one kernel)
+# 64 or 32 nodes in both y and z take the fused y-z pass (passes 2-4 in one kernel)
 @pytest.mark.parametrize("grid,ntan", [((16, 16, 16), 7), ((32, 16, 8), 7), ((8, 64, 16), 7), ((16, 64, 64), 7),
-                                       ((16, 64, 64), 0), ((16, 64, 64), 13), ((64, 64, 64), 7)])
+                                       ((16, 64, 64), 0), ((16, 64, 64), 13), ((64, 64, 64), 7), ((32, 32, 32), 7),
+                                       ((16, 32, 32), 13), ((64, 32, 32), 0)])
 def test_stage_solve_matches_oracle(grid, ntan):
     from paper_2511_21839_amd import dpic
 
