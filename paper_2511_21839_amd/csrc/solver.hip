@@ -316,8 +316,9 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_cols(const double2* __res
 //     two inverse halves.
 //   y inverse: each of the n + 2 output rows, 8- and RA-point stages around
 //     an exchange in the row, written to global memory at the n + 2 needed y.
-// All transforms are unnormalised; 1/(Mx My Mz) is in Ghat. The layouts in
-// global memory are those of passes 2-4, so passes 1 and 5 are unchanged.
+// All transforms are unnormalised; 1/(Mx My Mz) is in Ghat. In global memory
+// each column's input (z, y) and output (zo, yo) values are contiguous
+// ("column planes"), which passes 1 and 5 write and read with strides.
 // A thread's twiddles are powers of W_M^lo (lo, its place in its group of
 // 8, is fixed) times compile-time powers of W_16, formed in registers.
 template <int M>
@@ -332,7 +333,8 @@ struct YzCfg {
 
 struct YzArgs {
     int W;                        // complex columns (Mx * NCC)
-    int64_t in_batch, out_batch;  // strides between settings
+    int64_t cp_in, cp_out;        // column plane lengths: n n, and (n + 2)^2 padded to 8
+    int64_t in_batch, out_batch;  // strides between settings (W cp_in, W cp_out)
     const double* ghat;
     int ncc, gnx1, Mx;
 };
@@ -373,12 +375,12 @@ __global__ __launch_bounds__(YzCfg<M>::NT) void k_fft_yz(const double2* __restri
         twi[m] = w.y;
     }
     // column of this workgroup: each XCD (workgroups round-robin over 8)
-    // takes a contiguous eighth of the columns, so the columns that share a
-    // cache line are read and written through one L2
+    // takes a contiguous eighth of the columns, so the NCC columns of one kx,
+    // which read the same Ghat rows, go through one L2
     const int wpx = a.W / 8;
     const int col = (blockIdx.x % 8) * wpx + blockIdx.x / 8;
-    const double2* src = in + (int64_t)blockIdx.y * a.in_batch + col;
-    double2* dst = out + (int64_t)blockIdx.y * a.out_batch + col;
+    const double2* src = in + (int64_t)blockIdx.y * a.in_batch + col * a.cp_in;
+    double2* dst = out + (int64_t)blockIdx.y * a.out_batch + col * a.cp_out;
     const int lo = t & 7;  // n2 or r: the thread's place in its group of 8
     // the Ghat row (kx, ky) of this thread's z column p = t >> 3 (kz fastest)
     const double* grow;
@@ -400,7 +402,7 @@ __global__ __launch_bounds__(YzCfg<M>::NT) void k_fft_yz(const double2* __restri
         }
 #pragma unroll
         for (int n1 = 0; n1 < RA / 2; ++n1) {
-            const double2 v = src[((int64_t)zr * N + 8 * n1 + lo) * a.W];
+            const double2 v = src[zr * N + 8 * n1 + lo];
             xr[n1] = v.x;
             xi[n1] = v.y;
         }
@@ -596,7 +598,7 @@ __global__ __launch_bounds__(YzCfg<M>::NT) void k_fft_yz(const double2* __restri
 #pragma unroll
         for (int n1 = 0; n1 < RA; ++n1) {
             const int yo = (lo + 8 * n1 + 1) & (M - 1);
-            if (yo < NO) dst[((int64_t)zr * NO + yo) * a.W] = make_double2(xr[n1], xi[n1]);
+            if (yo < NO) dst[zr * NO + yo] = make_double2(xr[n1], xi[n1]);
         }
     }
 }
@@ -606,10 +608,22 @@ __global__ __launch_bounds__(YzCfg<M>::NT) void k_fft_yz(const double2* __restri
 // complex channel j = b % NCC of row b / NCC; its value at x is the pair of
 // real channels (j, j + NCC) (the real channel alone when NC = 1).
 
-// pass 1: rho[row][x < nx][NC] -> out[row][kx < M][NCC], clearing rho
+// Where the x passes keep their complex spectra: value (row g, column c),
+// c = kx NCC + j, sits at (g / rps) bstride + (g % rps) rstride + c cstride.
+// Row-major ([row][c]): rstride = W, cstride = 1, one block of all rows.
+// Column planes ([setting][c][row], the fused y-z pass's layout): rps rows
+// per setting, rstride = 1, cstride = the plane's padded length.
+struct RowLayout {
+    uint32_t rps;
+    int64_t bstride, rstride, cstride;
+    __host__ __device__ int64_t at(uint32_t g) const { return (int64_t)(g / rps) * bstride + (int64_t)(g % rps) * rstride; }
+};
+
+// pass 1: rho[row][x < nx][NC] -> out (row g, column kx NCC + j), clearing rho
 template <int M, int NC>
 __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_rows_fwd(double* __restrict__ rho, double2* __restrict__ out,
-                                                                int nx, int rows, const double2* __restrict__ tw) {
+                                                                int nx, int rows, RowLayout lay,
+                                                                const double2* __restrict__ tw) {
     using C = ColCfg<M>;
     constexpr int R1 = C::R1, R2 = C::R2, NG = C::NG, BC = C::BC;
     constexpr int NCC = NC == 1 ? 1 : NC / 2;
@@ -664,18 +678,19 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_rows_fwd(double* __restri
         dft_reg<M, R2, false>(hr[g], hi[g]);
     }
     if (!valid) return;
-    double2* dst = out + row * M * NCC + j;
+    double2* dst = out + lay.at((uint32_t)row) + j * lay.cstride;
+    const int64_t kxs = NCC * lay.cstride;
 #pragma unroll
     for (int g = 0; g < NG; ++g)
 #pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) dst[(r + R2 * g + R1 * k2) * NCC] = make_double2(hr[g][k2], hi[g][k2]);
+        for (int k2 = 0; k2 < R2; ++k2) dst[(r + R2 * g + R1 * k2) * kxs] = make_double2(hr[g][k2], hi[g][k2]);
 }
 
-// pass 5: in[row][kx < M][NCC] -> phi[row][xo < nxo][NC]; output slot xo
-// holds transform position xo - shift
+// pass 5: in (row g, column kx NCC + j) -> phi[row][xo < nxo][NC]; output
+// slot xo holds transform position xo - shift
 template <int M, int NC>
 __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_rows_inv(const double2* __restrict__ in, double* __restrict__ phi,
-                                                                int nxo, int shift, int rows,
+                                                                int nxo, int shift, int rows, RowLayout lay,
                                                                 const double2* __restrict__ tw) {
     using C = ColCfg<M>;
     constexpr int R1 = C::R1, R2 = C::R2, NG = C::NG, BC = C::BC;
@@ -692,14 +707,15 @@ __global__ __launch_bounds__(ColCfg<M>::NT) void k_fft_rows_inv(const double2* _
     const int64_t row = (int64_t)blockIdx.x * (BC / NCC) + b / NCC;
     const int j = b % NCC;
     const bool valid = row < rows;
-    const double2* src = in + row * M * NCC + j;
+    const double2* src = in + lay.at((uint32_t)row) + j * lay.cstride;
+    const int64_t kxs = NCC * lay.cstride;
     double hr[NG][R2], hi[NG][R2];  // groups k1 = r + R2 g, values over k2
 #pragma unroll
     for (int g = 0; g < NG; ++g)
 #pragma unroll
         for (int k2 = 0; k2 < R2; ++k2) {
             double2 v = make_double2(0.0, 0.0);
-            if (valid) v = src[(r + R2 * g + R1 * k2) * NCC];
+            if (valid) v = src[(r + R2 * g + R1 * k2) * kxs];
             hr[g][k2] = v.x;
             hi[g][k2] = v.y;
         }
@@ -759,14 +775,15 @@ static hipError_t launch_cols(int M, int n_outer, int nb, const ColArgs& a, cons
 }
 
 template <int NC>
-static hipError_t launch_rows_fwd_nc(int M, double* rho, double2* out, int nx, int rows, const double2* tw, hipStream_t s) {
+static hipError_t launch_rows_fwd_nc(int M, double* rho, double2* out, int nx, int rows, const RowLayout& lay,
+                                     const double2* tw, hipStream_t s) {
     constexpr int NCC = NC == 1 ? 1 : NC / 2;
     switch (M) {
 #define DPIC_ROWS_FWD(MM)                                                                                        \
     case MM: {                                                                                                   \
         constexpr int RB = ColCfg<MM>::BC / NCC;                                                                 \
         hipLaunchKernelGGL((k_fft_rows_fwd<MM, NC>), dim3((rows + RB - 1) / RB), dim3(ColCfg<MM>::NT), 0, s, rho, \
-                           out, nx, rows, tw);                                                                   \
+                           out, nx, rows, lay, tw);                                                              \
         break;                                                                                                   \
     }
         DPIC_ROWS_FWD(16) DPIC_ROWS_FWD(32) DPIC_ROWS_FWD(64) DPIC_ROWS_FWD(128)
@@ -778,14 +795,14 @@ static hipError_t launch_rows_fwd_nc(int M, double* rho, double2* out, int nx, i
 
 template <int NC>
 static hipError_t launch_rows_inv_nc(int M, const double2* in, double* phi, int nxo, int shift, int rows,
-                                     const double2* tw, hipStream_t s) {
+                                     const RowLayout& lay, const double2* tw, hipStream_t s) {
     constexpr int NCC = NC == 1 ? 1 : NC / 2;
     switch (M) {
 #define DPIC_ROWS_INV(MM)                                                                                       \
     case MM: {                                                                                                  \
         constexpr int RB = ColCfg<MM>::BC / NCC;                                                                \
         hipLaunchKernelGGL((k_fft_rows_inv<MM, NC>), dim3((rows + RB - 1) / RB), dim3(ColCfg<MM>::NT), 0, s, in, \
-                           phi, nxo, shift, rows, tw);                                                          \
+                           phi, nxo, shift, rows, lay, tw);                                                     \
         break;                                                                                                  \
     }
         DPIC_ROWS_INV(16) DPIC_ROWS_INV(32) DPIC_ROWS_INV(64) DPIC_ROWS_INV(128)
@@ -811,22 +828,34 @@ hipError_t launch_conv(dpic_ctx* cx, double* in, const int nin[3], double* out, 
     const double2* twz = cx->ws.tw + Mx + My;
     hipStream_t s = cx->stream;
     hipError_t e;
-    // 1: x forward, in -> A[nin_z][nin_y][Mx]
+    const int64_t W = (int64_t)Mx * NCC;
+    // passes 2-4 fused where y and z both have 32 or 64 nodes (forward solve)
+    const bool fused = My == Mz && (My == 128 || My == 64) && nin[1] == My / 2 && nin[2] == My / 2 &&
+                       nout[1] == My / 2 + 2 && nout[2] == My / 2 + 2 && shift == 1 && W % 8 == 0;
+    const int rows_in = nin[1] * nin[2], rows_out = nout[1] * nout[2];
+    // the fused pass reads and writes column planes (one column's rows
+    // contiguous), so that its loads and stores take whole cache lines; the
+    // output plane is padded to a multiple of 8 rows (128 bytes). Both fit
+    // the work arrays, which hold nb (nz + 2) My W values.
+    const int64_t cp_in = rows_in, cp_out = (rows_out + 7) / 8 * 8;
+    const RowLayout lay_in = fused ? RowLayout{(uint32_t)rows_in, W * cp_in, 1, cp_in} : RowLayout{1u << 31, 0, W, 1};
+    const RowLayout lay_out =
+        fused ? RowLayout{(uint32_t)rows_out, W * cp_out, 1, cp_out} : RowLayout{1u << 31, 0, W, 1};
+    // 1: x forward, in -> A (rows z, y of nin; columns kx, channel)
     switch (NC) {
-        case 1: e = launch_rows_fwd_nc<1>(Mx, in, cx->ws.buf0, nin[0], nin[1] * nin[2] * nb, twx, s); break;
-        case 8: e = launch_rows_fwd_nc<8>(Mx, in, cx->ws.buf0, nin[0], nin[1] * nin[2] * nb, twx, s); break;
-        default: e = launch_rows_fwd_nc<16>(Mx, in, cx->ws.buf0, nin[0], nin[1] * nin[2] * nb, twx, s); break;
+        case 1: e = launch_rows_fwd_nc<1>(Mx, in, cx->ws.buf0, nin[0], rows_in * nb, lay_in, twx, s); break;
+        case 8: e = launch_rows_fwd_nc<8>(Mx, in, cx->ws.buf0, nin[0], rows_in * nb, lay_in, twx, s); break;
+        default: e = launch_rows_fwd_nc<16>(Mx, in, cx->ws.buf0, nin[0], rows_in * nb, lay_in, twx, s); break;
     }
     if (e != hipSuccess) return e;
-    const int64_t W = (int64_t)Mx * NCC;
-    if (My == Mz && (My == 128 || My == 64) && nin[1] == My / 2 && nin[2] == My / 2 && nout[1] == My / 2 + 2 &&
-        nout[2] == My / 2 + 2 && shift == 1 && W % 8 == 0) {
+    if (fused) {
         // 2-4 fused: A -> D without the two intermediates
-        const int64_t n = My / 2;
         YzArgs y{};
         y.W = (int)W;
-        y.in_batch = n * n * W;
-        y.out_batch = (n + 2) * (n + 2) * W;
+        y.cp_in = cp_in;
+        y.cp_out = cp_out;
+        y.in_batch = W * cp_in;
+        y.out_batch = W * cp_out;
         y.ghat = cx->ws.ghat;
         y.ncc = NCC;
         y.gnx1 = nx + 1;
@@ -838,11 +867,11 @@ hipError_t launch_conv(dpic_ctx* cx, double* in, const int nin[3], double* out, 
             hipLaunchKernelGGL(k_fft_yz<64>, dim3((unsigned)W, nb), dim3(YzCfg<64>::NT), 0, s, cx->ws.buf0,
                                cx->ws.buf1, y, twy);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        const int rows = nout[1] * nout[2] * nb;
+        const int rows = rows_out * nb;
         switch (NC) {
-            case 1: return launch_rows_inv_nc<1>(Mx, cx->ws.buf1, out, nout[0], shift, rows, twx, s);
-            case 8: return launch_rows_inv_nc<8>(Mx, cx->ws.buf1, out, nout[0], shift, rows, twx, s);
-            default: return launch_rows_inv_nc<16>(Mx, cx->ws.buf1, out, nout[0], shift, rows, twx, s);
+            case 1: return launch_rows_inv_nc<1>(Mx, cx->ws.buf1, out, nout[0], shift, rows, lay_out, twx, s);
+            case 8: return launch_rows_inv_nc<8>(Mx, cx->ws.buf1, out, nout[0], shift, rows, lay_out, twx, s);
+            default: return launch_rows_inv_nc<16>(Mx, cx->ws.buf1, out, nout[0], shift, rows, lay_out, twx, s);
         }
     }
     ColArgs a{};
@@ -888,11 +917,11 @@ hipError_t launch_conv(dpic_ctx* cx, double* in, const int nin[3], double* out, 
     a.out_batch = (int64_t)nout[2] * a.out_outer;
     if ((e = launch_cols<2>(My, nout[2], nb, a, cx->ws.buf0, cx->ws.buf1, twy, s)) != hipSuccess) return e;
     // 5: x inverse, D -> out
-    const int rows = nout[1] * nout[2] * nb;
+    const int rows = rows_out * nb;
     switch (NC) {
-        case 1: return launch_rows_inv_nc<1>(Mx, cx->ws.buf1, out, nout[0], shift, rows, twx, s);
-        case 8: return launch_rows_inv_nc<8>(Mx, cx->ws.buf1, out, nout[0], shift, rows, twx, s);
-        default: return launch_rows_inv_nc<16>(Mx, cx->ws.buf1, out, nout[0], shift, rows, twx, s);
+        case 1: return launch_rows_inv_nc<1>(Mx, cx->ws.buf1, out, nout[0], shift, rows, lay_out, twx, s);
+        case 8: return launch_rows_inv_nc<8>(Mx, cx->ws.buf1, out, nout[0], shift, rows, lay_out, twx, s);
+        default: return launch_rows_inv_nc<16>(Mx, cx->ws.buf1, out, nout[0], shift, rows, lay_out, twx, s);
     }
 }
 
