@@ -360,6 +360,18 @@ __device__ __forceinline__ void mul_w16_at(double& re, double& im, int j, bool i
 #undef DPIC_W16
 }
 
+// Inside the y row transforms and the z column transforms, the lanes that
+// exchange values through the plane are the 8 lanes of one row or column,
+// which are always in one wavefront. A wavefront performs its LDS operations
+// in issue order, so there a fence that keeps the compiler from moving LDS
+// accesses across it replaces the workgroup barrier; barriers remain only
+// where the data crosses wavefronts (the twiddle table, rows to columns and
+// back).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <int M>
 __global__ __launch_bounds__(YzCfg<M>::NT) void k_fft_yz(const double2* __restrict__ in, double2* __restrict__ out,
                                                          YzArgs a, const double2* __restrict__ tw) {
@@ -421,7 +433,7 @@ __global__ __launch_bounds__(YzCfg<M>::NT) void k_fft_yz(const double2* __restri
             P[zr * PS + 8 * k1 + lo] = make_double2(xr[k1], xi[k1]);
         }
     }
-    __syncthreads();
+    wave_sync();  // the row's 8 lanes
     if (rowt) {
 #pragma unroll
         for (int g = 0; g < RA / 8; ++g) {
@@ -459,7 +471,7 @@ __global__ __launch_bounds__(YzCfg<M>::NT) void k_fft_yz(const double2* __restri
             const int kz = 2 * (lo + HA * k2) + h;
             gv[k2] = bt ? grow[kz <= M - kz ? kz : M - kz] : 0.0;
         }
-        __syncthreads();  // every read of the column's slots before is done
+        wave_sync();  // every read of the column's slots before is done
         // stage A: HA-point DFT over n1 of x (x W_M^z for the odd kz), twiddle W_n^(n2 k1)
         double ar[HA], ai[HA];
         {
@@ -487,7 +499,7 @@ __global__ __launch_bounds__(YzCfg<M>::NT) void k_fft_yz(const double2* __restri
                 P[(8 * k1 + lo) * PS + p] = make_double2(ar[k1], ai[k1]);
             }
         }
-        __syncthreads();
+        wave_sync();
         // stage B (r = lo < HA): 8-point DFT over n2 gives kk = r + HA k2; times Ghat;
         // inverse 8-point DFT over k2, twiddle W_n^(-r n2)
         double br[8], bi[8];
@@ -513,11 +525,11 @@ __global__ __launch_bounds__(YzCfg<M>::NT) void k_fft_yz(const double2* __restri
                 cmul_by(wr, wi, w2r, -w2i);
             }
         }
-        __syncthreads();  // every stage-B read is done
+        wave_sync();  // every stage-B read is done
         if (bt)
 #pragma unroll
             for (int n2 = 0; n2 < 8; ++n2) P[(HA * n2 + lo) * PS + p] = make_double2(br[n2], bi[n2]);
-        __syncthreads();
+        wave_sync();
         // stage A' (n2 = lo): inverse HA-point DFT over r gives z = n2 + 8 n1
 #pragma unroll
         for (int r = 0; r < HA; ++r) {
@@ -534,7 +546,7 @@ __global__ __launch_bounds__(YzCfg<M>::NT) void k_fft_yz(const double2* __restri
             }
         } else {
             // combine at z = n2 + 8 n1 (slot z + 1); z = -1 and z = n reuse z mod n
-            __syncthreads();  // every stage-A' read is done
+            wave_sync();  // every stage-A' read is done
             const double w1r = twr[lo], w1i = twi[lo];
 #pragma unroll
             for (int n1 = 0; n1 < HA; ++n1) {
@@ -579,14 +591,14 @@ __global__ __launch_bounds__(YzCfg<M>::NT) void k_fft_yz(const double2* __restri
             }
         }
     }
-    __syncthreads();
+    wave_sync();
     if (outt) {
 #pragma unroll
         for (int g = 0; g < RA / 8; ++g)
 #pragma unroll
             for (int n2 = 0; n2 < 8; ++n2) P[zr * PS + RA * n2 + lo + 8 * g] = make_double2(cr[g][n2], ci[g][n2]);
     }
-    __syncthreads();
+    wave_sync();
     if (outt) {
 #pragma unroll
         for (int k1 = 0; k1 < RA; ++k1) {
