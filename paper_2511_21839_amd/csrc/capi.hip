@@ -338,8 +338,7 @@ int upload_settings(dpic_ctx* c) {
 
 void set_swapped(dpic_ctx* c, bool swapped) {
     if (c->swapped != swapped) {
-        std::swap(c->ws.st, c->ws.st2);
-        std::swap(c->ws.pid, c->ws.pid2);
+        swap_sorted_buffers(c->ws);
         c->swapped = swapped;
     }
 }
@@ -444,7 +443,7 @@ int step_graph(dpic_ctx* c, int n) {
     ge.adj = c->adj.bound;
     ge.layout = c->layout_gen;
     const Workspace ws0 = c->ws;
-    const bool sw0 = c->swapped, ck0 = c->chunks_valid;
+    const bool sw0 = c->swapped, ck0 = c->chunks_valid, hc0 = c->hist_clean;
     const int64_t sd0 = c->steps_done;
     hipStream_t orig = c->stream;
     HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -460,6 +459,7 @@ int step_graph(dpic_ctx* c, int n) {
         c->ws = ws0;
         c->swapped = sw0;
         c->chunks_valid = ck0;
+        c->hist_clean = hc0;
         c->steps_done = sd0;
         if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
         if (r != DPIC_OK) return r;
@@ -473,6 +473,7 @@ int step_graph(dpic_ctx* c, int n) {
         c->ws = ws0;
         c->swapped = sw0;
         c->chunks_valid = ck0;
+        c->hist_clean = hc0;
         c->steps_done = sd0;
         return fail(c, DPIC_EHIP, "step: graph launch failed: %s", hipGetErrorString(e));
     }
@@ -558,9 +559,13 @@ size_t workspace_layout(const dpic_dims& d, char* base, Workspace* ws) {
     for (size_t nd : {nx, ny, nz}) nbins *= (nd - 1 + TILE_EDGE - 1) / TILE_EDGE;
     nbins += 1;
     const size_t segs = (cap + SEG - 1) / SEG;
+    w.hist = (uint32_t*)take((B * nbins + 1) * sizeof(uint32_t));
     w.bins = (uint32_t*)take((2 * B * nbins + 2) * sizeof(uint32_t));
-    w.chunks = (int4*)take((std::min(B * nbins, cap) + cap / CHUNK_MIN + 1) * sizeof(int4));
+    const size_t items = std::min(B * nbins, cap) + cap / CHUNK_MIN + 1;
+    w.chunks = (int4*)take(items * sizeof(int4));
     w.nchunks = (uint32_t*)take(sizeof(uint32_t));
+    w.chunks2 = (int4*)take(items * sizeof(int4));
+    w.nchunks2 = (uint32_t*)take(sizeof(uint32_t));
     w.set = (SettingDev*)take(B * sizeof(SettingDev));
     w.owner = (int32_t*)take(segs * sizeof(int32_t));
     w.sig = (double*)take(B * 6 * NC * sizeof(double));

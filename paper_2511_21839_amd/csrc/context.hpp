@@ -14,6 +14,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/dpic.h"
@@ -42,9 +43,12 @@ struct Workspace {
     int32_t* pid = nullptr;    // packed original row of each stored particle
     int32_t* pid2 = nullptr;
     uint32_t* key = nullptr;     // sort keys
-    uint32_t* bins = nullptr;    // sort: [B][nbins] bin totals, then first slots; [B][nbins] claim cursors
-    int4* chunks = nullptr;      // tiled work list (tile, first, count, setting)
+    uint32_t* hist = nullptr;    // sort: [B][nbins] bin totals, zero between sorts
+    uint32_t* bins = nullptr;    // sort: [B][nbins] first slots; [B][nbins] claim cursors
+    int4* chunks = nullptr;      // tiled work list (tile, first, count, setting) of the order in st
     uint32_t* nchunks = nullptr;
+    int4* chunks2 = nullptr;     // the work list of the order in st2 (written by a sort's counts)
+    uint32_t* nchunks2 = nullptr;
     SettingDev* set = nullptr;   // [B]
     int32_t* owner = nullptr;    // [cap / SEG] setting of each storage segment
     double* sig = nullptr;       // [B][6][NC] initial beam sizes as duals
@@ -173,6 +177,7 @@ struct dpic_ctx {
     int64_t part_blocks = 0;           // workgroups of the tiled particle kernel (0: resident capacity)
     bool chunks_valid = false;  // the tiled work list matches the stored order
     bool keys_ready = false;    // ws.key holds every particle's tile key (written by the last particle launch)
+    bool hist_clean = false;    // ws.hist is all zero (every sort's planning clears it)
     int stage_timing = 0;  // 0 off, 1 every stage, 2 the particle stage only
     bool use_graph = false;
     bool check_finite = false;  // dpic_step synchronises and reports non-finite state values
@@ -221,10 +226,18 @@ bool sort_geometry(const dpic_ctx* c, int* tiles, int* nbins);
 size_t max_chunks(const dpic_ctx* c);
 hipError_t launch_sort(dpic_ctx* c);  // also rebuilds the tiled work list
 // The sort in two parts around a particle launch that stores the state in
-// sorted order itself: bin totals and first slots from the stored keys, then
-// (after that launch) the work list and the buffer swap.
+// sorted order itself: bin totals, first slots and the work list of the
+// sorted order (into chunks2) from the stored keys, then (after that launch)
+// the buffer swap.
 hipError_t launch_sort_counts(dpic_ctx* c);
 hipError_t launch_sort_finish(dpic_ctx* c, bool scattered);
+// st, pid and the work list with their second buffers (a sort's swap)
+inline void swap_sorted_buffers(Workspace& w) {
+    std::swap(w.st, w.st2);
+    std::swap(w.pid, w.pid2);
+    std::swap(w.chunks, w.chunks2);
+    std::swap(w.nchunks, w.nchunks2);
+}
 
 // ---- launchers (solver.hip)
 hipError_t launch_green(dpic_ctx* c);

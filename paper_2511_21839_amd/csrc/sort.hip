@@ -97,29 +97,42 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_count(const double* __res
         if (h[b] != 0u) atomicAdd(tb + b, h[b]);
 }
 
+// Exclusive prefix sum over a 1024-thread block: a scan inside each
+// wavefront by shuffles, then every thread adds the sums of the wavefronts
+// before its own (16 values in LDS, sh[0..15]). *total gets the block's sum.
 __device__ __forceinline__ uint32_t block_excl_scan_1024(uint32_t x, uint32_t* sh, uint32_t* total) {
-    sh[threadIdx.x] = x;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t t = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0u;
-        __syncthreads();
-        sh[threadIdx.x] += t;
-        __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t v = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(v, d, 64);
+        if (lane >= d) v += y;
     }
-    const uint32_t incl = sh[threadIdx.x];
-    if (total) *total = sh[1023];
+    if (lane == 63) sh[w] = v;
     __syncthreads();
-    return incl - x;
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const uint32_t u = sh[i];
+        before += i < w ? u : 0u;
+        all += u;
+    }
+    __syncthreads();  // sh is free again for the next scan
+    if (total) *total = all;
+    return before + v - x;
 }
 
-// Starts: one block per setting; its bin totals become the first storage
-// slot of every bin (exclusive scan plus the setting's offset), in tot (for
-// the work list) and cur (the slots the scatter claims).
+// Starts: one block per setting; its bin totals (cleared here for the next
+// count) become the first storage slot of every bin (exclusive scan plus the
+// setting's offset), in tot (for the work list) and cur (the slots the
+// scatter claims).
 __global__ __launch_bounds__(1024) void k_sort_starts(const SettingDev* __restrict__ set, int nbins,
-                                                      uint32_t* __restrict__ tot, uint32_t* __restrict__ cur) {
-    __shared__ uint32_t sh[1024];
+                                                      uint32_t* __restrict__ hist, uint32_t* __restrict__ tot,
+                                                      uint32_t* __restrict__ cur) {
+    __shared__ uint32_t sh[16];
     const int b = blockIdx.x;
     const int64_t off = set[b].off;
+    uint32_t* hb = hist + (int64_t)b * nbins;
     uint32_t* tb = tot + (int64_t)b * nbins;
     uint32_t* cb = cur + (int64_t)b * nbins;
     // at most PS bins per thread; their totals are loaded together (unrolled)
@@ -131,9 +144,12 @@ __global__ __launch_bounds__(1024) void k_sort_starts(const SettingDev* __restri
     uint32_t s = 0;
 #pragma unroll
     for (int i = 0; i < PS; ++i) {
-        v[i] = (i < per && f0 + i < nbins) ? tb[f0 + i] : 0u;
+        v[i] = (i < per && f0 + i < nbins) ? hb[f0 + i] : 0u;
         s += v[i];
     }
+#pragma unroll
+    for (int i = 0; i < PS; ++i)
+        if (i < per && f0 + i < nbins) hb[f0 + i] = 0u;
     uint32_t run = (uint32_t)off + block_excl_scan_1024(s, sh, nullptr);
 #pragma unroll
     for (int i = 0; i < PS; ++i) {
@@ -210,7 +226,7 @@ __global__ __launch_bounds__(1024) void k_build_chunks(const SettingDev* __restr
                                                        const uint32_t* __restrict__ starts, int nbins, int nb,
                                                        int chunk, int4* __restrict__ chunks,
                                                        uint32_t* __restrict__ nchunks) {
-    __shared__ uint32_t sh[1024];
+    __shared__ uint32_t sh[16];
     const int nf = nbins * nb;
     const int per = (nf + 1023) / 1024;
     const int f0 = threadIdx.x * per;
@@ -268,6 +284,68 @@ __global__ __launch_bounds__(1024) void k_build_chunks(const SettingDev* __restr
     if (threadIdx.x == 0) *nchunks = total;
 }
 
+// One setting: the starts and the work list in one block. Every bin's total
+// (cleared here for the next count) gives its first slot, in tot and cur as
+// k_sort_starts writes them, and its number of items; then all threads
+// write the items, in bin order, each finding its item's bin by bisection
+// over the bins' first item indices.
+__global__ __launch_bounds__(1024) void k_sort_plan(const SettingDev* __restrict__ set, int nbins, int chunk,
+                                                    uint32_t* __restrict__ hist, uint32_t* __restrict__ tot,
+                                                    uint32_t* __restrict__ cur, int4* __restrict__ chunks,
+                                                    uint32_t* __restrict__ nchunks) {
+    constexpr int PP = (NUM_TILE_BINS_MAX + 1 + 1023) / 1024;
+    __shared__ uint32_t sh[16];
+    __shared__ uint32_t s_start[NUM_TILE_BINS_MAX + 2], s_item[NUM_TILE_BINS_MAX + 2];
+    const SettingDev sd = set[0];
+    const int per = (nbins + 1023) / 1024;
+    const int f0 = threadIdx.x * per;
+    const uint32_t ch = (uint32_t)chunk;
+    uint32_t c[PP];
+    uint32_t s = 0, si = 0;
+#pragma unroll
+    for (int i = 0; i < PP; ++i) {
+        const int f = f0 + i;
+        c[i] = (i < per && f < nbins) ? hist[f] : 0u;
+        s += c[i];
+        si += (c[i] + ch - 1u) / ch;
+    }
+#pragma unroll
+    for (int i = 0; i < PP; ++i)
+        if (i < per && f0 + i < nbins) hist[f0 + i] = 0u;
+    uint32_t items = 0;
+    uint32_t run = (uint32_t)sd.off + block_excl_scan_1024(s, sh, nullptr);
+    uint32_t irun = block_excl_scan_1024(si, sh, &items);
+#pragma unroll
+    for (int i = 0; i < PP; ++i) {
+        const int f = f0 + i;
+        if (i < per && f < nbins) {
+            tot[f] = run;
+            cur[f] = run;
+            s_start[f] = run;
+            s_item[f] = irun;
+            run += c[i];
+            irun += (c[i] + ch - 1u) / ch;
+        }
+    }
+    if (threadIdx.x == 0) {
+        s_start[nbins] = (uint32_t)(sd.off + sd.n);
+        s_item[nbins] = items;
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < items; k += 1024) {
+        int lo = 0, hi = nbins - 1;  // s_item[lo] <= k; the bin is the last such
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_item[mid] <= k) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint32_t q = s_start[lo] + (k - s_item[lo]) * ch;
+        const uint32_t left = s_start[lo + 1] - q;
+        chunks[k] = make_int4(lo, (int)q, (int)(left < ch ? left : ch), 0);
+    }
+    if (threadIdx.x == 0) *nchunks = items;
+}
+
 bool sort_geometry(const dpic_ctx* cx, int* tiles, int* nbins) {
     int t[3];
     const int n[3] = {cx->dims.nx, cx->dims.ny, cx->dims.nz};
@@ -306,8 +384,10 @@ static bool sort_geom(const dpic_ctx* cx, SortGeom* g) {
     return true;
 }
 
-// bin totals of every setting (from the stored keys when the last particle
-// launch wrote them, else from the positions), then first slots into tot and cur
+// Bin totals of every setting (from the stored keys when the last particle
+// launch wrote them, else from the positions), then first slots into tot and
+// cur and the work list of the sorted order into chunks2. The totals stay
+// zero between sorts: the planning kernels clear them.
 hipError_t launch_sort_counts(dpic_ctx* cx) {
     SortGeom g;
     if (!sort_geom(cx, &g)) return hipErrorInvalidValue;
@@ -318,25 +398,40 @@ hipError_t launch_sort_counts(dpic_ctx* cx) {
     const int64_t nbt = (int64_t)cx->B * g.nbins;
     uint32_t* tot = w.bins;
     uint32_t* cur = w.bins + nbt;
-    if (nsegs == 0) return hipSuccess;
-    hipError_t ez = launch_zero(cx, (double*)tot, (size_t)(nbt + 1) / 2);
-    if (ez != hipSuccess) return ez;
-    if (cx->keys_ready) {
-        hipLaunchKernelGGL((k_sort_count<1, true>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key,
-                           tot);
-    } else {
-        switch (cx->NC) {
-            case 1: hipLaunchKernelGGL((k_sort_count<1, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, tot); break;
-            case 8: hipLaunchKernelGGL((k_sort_count<8, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, tot); break;
-            default: hipLaunchKernelGGL((k_sort_count<16, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, tot); break;
+    if (!cx->hist_clean) {
+        hipError_t ez = launch_zero(cx, (double*)w.hist, (size_t)(nbt + 1) / 2);
+        if (ez != hipSuccess) return ez;
+    }
+    cx->hist_clean = false;
+    if (nsegs > 0) {
+        if (cx->keys_ready) {
+            hipLaunchKernelGGL((k_sort_count<1, true>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g,
+                               w.key, w.hist);
+        } else {
+            switch (cx->NC) {
+                case 1: hipLaunchKernelGGL((k_sort_count<1, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, w.hist); break;
+                case 8: hipLaunchKernelGGL((k_sort_count<8, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, w.hist); break;
+                default: hipLaunchKernelGGL((k_sort_count<16, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, w.hist); break;
+            }
         }
     }
-    hipLaunchKernelGGL(k_sort_starts, dim3(cx->B), dim3(1024), 0, s, w.set, g.nbins, tot, cur);
-    return hipGetLastError();
+    if (cx->B == 1) {
+        hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(1024), 0, s, w.set, g.nbins, (int)cx->chunk, w.hist, tot, cur,
+                           w.chunks2, w.nchunks2);
+    } else {
+        hipLaunchKernelGGL(k_sort_starts, dim3(cx->B), dim3(1024), 0, s, w.set, g.nbins, w.hist, tot, cur);
+        hipLaunchKernelGGL(k_build_chunks, dim3(1), dim3(1024), 0, s, w.set, tot, g.nbins, cx->B, (int)cx->chunk,
+                           w.chunks2, w.nchunks2);
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) cx->hist_clean = true;
+    return e;
 }
 
 // scattered: a particle launch has already stored the state in sorted order
-// in the second buffers; otherwise the scatter kernel moves it there.
+// in the second buffers; otherwise the scatter kernel moves it there. Then
+// the state, the original rows and the work list swap with their second
+// buffers.
 hipError_t launch_sort_finish(dpic_ctx* cx, bool scattered) {
     SortGeom g;
     if (!sort_geom(cx, &g)) return hipErrorInvalidValue;
@@ -344,7 +439,6 @@ hipError_t launch_sort_finish(dpic_ctx* cx, bool scattered) {
     const int64_t cap = cx->dims.n_particles;
     const Workspace& w = cx->ws;
     const int nsegs = (int)((cx->used + SEG - 1) / SEG);
-    uint32_t* tot = w.bins;
     uint32_t* cur = w.bins + (int64_t)cx->B * g.nbins;
     if (nsegs > 0 && !scattered) {
         switch (cx->NC) {
@@ -352,16 +446,11 @@ hipError_t launch_sort_finish(dpic_ctx* cx, bool scattered) {
             case 8: hipLaunchKernelGGL(k_sort_scatter<8>, dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, w.pid, cap, w.set, w.owner, w.key, cur, g.nbins, w.st2, w.pid2); break;
             default: hipLaunchKernelGGL(k_sort_scatter<16>, dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, w.pid, cap, w.set, w.owner, w.key, cur, g.nbins, w.st2, w.pid2); break;
         }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_build_chunks, dim3(1), dim3(1024), 0, s, w.set, tot, g.nbins, cx->B, (int)cx->chunk,
-                       w.chunks, w.nchunks);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (nsegs > 0) {
-        std::swap(cx->ws.st, cx->ws.st2);
-        std::swap(cx->ws.pid, cx->ws.pid2);
-        cx->swapped = !cx->swapped;
-    }
+    swap_sorted_buffers(cx->ws);
+    cx->swapped = !cx->swapped;
     cx->chunks_valid = true;
     cx->keys_ready = false;
     return hipSuccess;
