@@ -566,6 +566,7 @@ size_t workspace_layout(const dpic_dims& d, char* base, Workspace* ws) {
     w.nchunks = (uint32_t*)take(sizeof(uint32_t));
     w.chunks2 = (int4*)take(items * sizeof(int4));
     w.nchunks2 = (uint32_t*)take(sizeof(uint32_t));
+    w.nitems = (uint32_t*)take(B * sizeof(uint32_t));
     w.set = (SettingDev*)take(B * sizeof(SettingDev));
     w.owner = (int32_t*)take(segs * sizeof(int32_t));
     w.sig = (double*)take(B * 6 * NC * sizeof(double));

@@ -49,6 +49,7 @@ struct Workspace {
     uint32_t* nchunks = nullptr;
     int4* chunks2 = nullptr;     // the work list of the order in st2 (written by a sort's counts)
     uint32_t* nchunks2 = nullptr;
+    uint32_t* nitems = nullptr;  // [B] work items of each setting (batched sorts)
     SettingDev* set = nullptr;   // [B]
     int32_t* owner = nullptr;    // [cap / SEG] setting of each storage segment
     double* sig = nullptr;       // [B][6][NC] initial beam sizes as duals

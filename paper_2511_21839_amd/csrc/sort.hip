@@ -125,10 +125,10 @@ __device__ __forceinline__ uint32_t block_excl_scan_1024(uint32_t x, uint32_t* s
 // Starts: one block per setting; its bin totals (cleared here for the next
 // count) become the first storage slot of every bin (exclusive scan plus the
 // setting's offset), in tot (for the work list) and cur (the slots the
-// scatter claims).
-__global__ __launch_bounds__(1024) void k_sort_starts(const SettingDev* __restrict__ set, int nbins,
+// scatter claims), and its number of work items goes to nitems[b].
+__global__ __launch_bounds__(1024) void k_sort_starts(const SettingDev* __restrict__ set, int nbins, int chunk,
                                                       uint32_t* __restrict__ hist, uint32_t* __restrict__ tot,
-                                                      uint32_t* __restrict__ cur) {
+                                                      uint32_t* __restrict__ cur, uint32_t* __restrict__ nitems) {
     __shared__ uint32_t sh[16];
     const int b = blockIdx.x;
     const int64_t off = set[b].off;
@@ -140,17 +140,21 @@ __global__ __launch_bounds__(1024) void k_sort_starts(const SettingDev* __restri
     constexpr int PS = (NUM_TILE_BINS_MAX + 1 + 1023) / 1024;
     const int per = (nbins + 1023) / 1024;
     const int f0 = threadIdx.x * per;
+    const uint32_t ch = (uint32_t)chunk;
     uint32_t v[PS];
-    uint32_t s = 0;
+    uint32_t s = 0, si = 0;
 #pragma unroll
     for (int i = 0; i < PS; ++i) {
         v[i] = (i < per && f0 + i < nbins) ? hb[f0 + i] : 0u;
         s += v[i];
+        si += (v[i] + ch - 1u) / ch;
     }
 #pragma unroll
     for (int i = 0; i < PS; ++i)
         if (i < per && f0 + i < nbins) hb[f0 + i] = 0u;
     uint32_t run = (uint32_t)off + block_excl_scan_1024(s, sh, nullptr);
+    uint32_t items = 0;
+    (void)block_excl_scan_1024(si, sh, &items);
 #pragma unroll
     for (int i = 0; i < PS; ++i) {
         const int f = f0 + i;
@@ -160,6 +164,7 @@ __global__ __launch_bounds__(1024) void k_sort_starts(const SettingDev* __restri
             run += v[i];
         }
     }
+    if (threadIdx.x == 0) nitems[b] = items;
 }
 
 // Scatter: the block recounts its bins, claims a run of slots per non-empty
@@ -206,82 +211,81 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(const double* __r
     }
 }
 
-// One block: work list from the bin ranges of every setting. Flattened bin
-// f = b * nbins + bin holds slots [start(b, bin), start(b, bin + 1)), the
-// last bin ending at off_b + n_b; each range is cut into items of at most
-// `chunk` particles: (tile, first slot, count, setting).
-__device__ __forceinline__ void bin_range(const SettingDev* set, const uint32_t* starts, int nbins, int f, int64_t* a,
-                                          int64_t* e) {
-    const int b = f / nbins, bin = f - b * nbins;
-    const SettingDev sd = set[b];
-    if (sd.n == 0) {
-        *a = *e = 0;
-        return;
+// Cuts bins into work items and writes them in bin order from item index
+// base on: s_start[f] is bin f's first slot (s_start[nbins] the end of the
+// last), s_item[f] its first item index (s_item[nbins] the item count).
+// Each thread finds its item's bin by bisection.
+__device__ __forceinline__ void write_items(const uint32_t* s_start, const uint32_t* s_item, int nbins, uint32_t ch,
+                                            int setting, uint32_t base, int4* __restrict__ chunks) {
+    const uint32_t items = s_item[nbins];
+    for (uint32_t k = threadIdx.x; k < items; k += 1024) {
+        int lo = 0, hi = nbins - 1;  // s_item[lo] <= k; the bin is the last such
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_item[mid] <= k) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint32_t q = s_start[lo] + (k - s_item[lo]) * ch;
+        const uint32_t left = s_start[lo + 1] - q;
+        chunks[base + k] = make_int4(lo, (int)q, (int)(left < ch ? left : ch), setting);
     }
-    *a = (int64_t)starts[f];
-    *e = bin + 1 < nbins ? (int64_t)starts[f + 1] : sd.off + sd.n;
 }
 
-__global__ __launch_bounds__(1024) void k_build_chunks(const SettingDev* __restrict__ set,
-                                                       const uint32_t* __restrict__ starts, int nbins, int nb,
-                                                       int chunk, int4* __restrict__ chunks,
-                                                       uint32_t* __restrict__ nchunks) {
+// Batches: one block per setting writes its work items after those of the
+// settings before it (their counts from k_sort_starts), from its bins' first
+// slots in tot. Item (tile, first slot, count, setting), at most `chunk`
+// particles each.
+__global__ __launch_bounds__(1024) void k_build_items(const SettingDev* __restrict__ set, int nbins, int chunk,
+                                                      const uint32_t* __restrict__ tot,
+                                                      const uint32_t* __restrict__ nitems, int nb,
+                                                      int4* __restrict__ chunks, uint32_t* __restrict__ nchunks) {
+    constexpr int PP = (NUM_TILE_BINS_MAX + 1 + 1023) / 1024;
     __shared__ uint32_t sh[16];
-    const int nf = nbins * nb;
-    const int per = (nf + 1023) / 1024;
+    __shared__ uint32_t s_start[NUM_TILE_BINS_MAX + 2], s_item[NUM_TILE_BINS_MAX + 2];
+    const int b = blockIdx.x;
+    const SettingDev sd = set[b];
+    const uint32_t* tb = tot + (int64_t)b * nbins;
+    const uint32_t end = (uint32_t)(sd.off + sd.n);
+    const uint32_t ch = (uint32_t)chunk;
+    uint32_t pre = 0, all = 0;
+    for (int j = threadIdx.x; j < nb; j += 1024) {
+        const uint32_t u = nitems[j];
+        pre += j < b ? u : 0u;
+        all += u;
+    }
+    uint32_t base = 0, total = 0;
+    (void)block_excl_scan_1024(pre, sh, &base);
+    (void)block_excl_scan_1024(all, sh, &total);
+    const int per = (nbins + 1023) / 1024;
     const int f0 = threadIdx.x * per;
-    constexpr int PMAX = 8;
-    if (per <= PMAX) {
-        // up to PMAX bins per thread (every single-setting grid): their
-        // ranges are loaded once, all in flight together, and kept in
-        // registers for the writes
-        int64_t ba[PMAX], be[PMAX];
-        uint32_t s = 0;
+    uint32_t st[PP], c[PP];
+    uint32_t si = 0;
 #pragma unroll
-        for (int i = 0; i < PMAX; ++i) {
-            ba[i] = be[i] = 0;
-            if (i < per && f0 + i < nf) bin_range(set, starts, nbins, f0 + i, &ba[i], &be[i]);
-        }
-#pragma unroll
-        for (int i = 0; i < PMAX; ++i) s += (uint32_t)((be[i] - ba[i] + chunk - 1) / chunk);
-        uint32_t total = 0;
-        uint32_t run = block_excl_scan_1024(s, sh, &total);
-#pragma unroll
-        for (int i = 0; i < PMAX; ++i) {
-            const int f = f0 + i;
-            const int b = f / nbins;
-            for (int64_t q = ba[i]; q < be[i]; q += chunk) {
-                const int64_t cnt = (be[i] - q) < chunk ? (be[i] - q) : chunk;
-                chunks[run++] = make_int4(f - b * nbins, (int)q, (int)cnt, b);
-            }
-        }
-        if (threadIdx.x == 0) *nchunks = total;
-        return;
-    }
-    uint32_t s = 0;
-    for (int i = 0; i < per; ++i) {
+    for (int i = 0; i < PP; ++i) {
         const int f = f0 + i;
-        if (f < nf) {
-            int64_t a, e;
-            bin_range(set, starts, nbins, f, &a, &e);
-            s += (uint32_t)((e - a + chunk - 1) / chunk);
-        }
+        const bool in = i < per && f < nbins;
+        st[i] = in ? tb[f] : 0u;
+        c[i] = in ? (f + 1 < nbins ? tb[f + 1] : end) - st[i] : 0u;
+        si += (c[i] + ch - 1u) / ch;
     }
-    uint32_t total = 0;
-    uint32_t run = block_excl_scan_1024(s, sh, &total);
-    for (int i = 0; i < per; ++i) {
+    uint32_t items = 0;
+    uint32_t irun = block_excl_scan_1024(si, sh, &items);
+#pragma unroll
+    for (int i = 0; i < PP; ++i) {
         const int f = f0 + i;
-        if (f < nf) {
-            int64_t a, e;
-            bin_range(set, starts, nbins, f, &a, &e);
-            const int b = f / nbins;
-            for (int64_t q = a; q < e; q += chunk) {
-                const int64_t cnt = (e - q) < chunk ? (e - q) : chunk;
-                chunks[run++] = make_int4(f - b * nbins, (int)q, (int)cnt, b);
-            }
+        if (i < per && f < nbins) {
+            s_start[f] = st[i];
+            s_item[f] = irun;
+            irun += (c[i] + ch - 1u) / ch;
         }
     }
-    if (threadIdx.x == 0) *nchunks = total;
+    if (threadIdx.x == 0) {
+        s_start[nbins] = end;
+        s_item[nbins] = items;
+        if (b == 0) *nchunks = total;
+    }
+    __syncthreads();
+    write_items(s_start, s_item, nbins, ch, b, base, chunks);
 }
 
 // One setting: the starts and the work list in one block. Every bin's total
@@ -330,20 +334,10 @@ __global__ __launch_bounds__(1024) void k_sort_plan(const SettingDev* __restrict
     if (threadIdx.x == 0) {
         s_start[nbins] = (uint32_t)(sd.off + sd.n);
         s_item[nbins] = items;
+        *nchunks = items;
     }
     __syncthreads();
-    for (uint32_t k = threadIdx.x; k < items; k += 1024) {
-        int lo = 0, hi = nbins - 1;  // s_item[lo] <= k; the bin is the last such
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_item[mid] <= k) lo = mid;
-            else hi = mid - 1;
-        }
-        const uint32_t q = s_start[lo] + (k - s_item[lo]) * ch;
-        const uint32_t left = s_start[lo + 1] - q;
-        chunks[k] = make_int4(lo, (int)q, (int)(left < ch ? left : ch), 0);
-    }
-    if (threadIdx.x == 0) *nchunks = items;
+    write_items(s_start, s_item, nbins, ch, 0, 0u, chunks);
 }
 
 bool sort_geometry(const dpic_ctx* cx, int* tiles, int* nbins) {
@@ -419,9 +413,10 @@ hipError_t launch_sort_counts(dpic_ctx* cx) {
         hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(1024), 0, s, w.set, g.nbins, (int)cx->chunk, w.hist, tot, cur,
                            w.chunks2, w.nchunks2);
     } else {
-        hipLaunchKernelGGL(k_sort_starts, dim3(cx->B), dim3(1024), 0, s, w.set, g.nbins, w.hist, tot, cur);
-        hipLaunchKernelGGL(k_build_chunks, dim3(1), dim3(1024), 0, s, w.set, tot, g.nbins, cx->B, (int)cx->chunk,
-                           w.chunks2, w.nchunks2);
+        hipLaunchKernelGGL(k_sort_starts, dim3(cx->B), dim3(1024), 0, s, w.set, g.nbins, (int)cx->chunk, w.hist, tot,
+                           cur, w.nitems);
+        hipLaunchKernelGGL(k_build_items, dim3(cx->B), dim3(1024), 0, s, w.set, g.nbins, (int)cx->chunk, tot, w.nitems,
+                           cx->B, w.chunks2, w.nchunks2);
     }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) cx->hist_clean = true;
