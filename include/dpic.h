@@ -253,7 +253,10 @@ int dpic_load_state(dpic_ctx* ctx, const void* dev_buf);
  *    keys nor the one that stores the particles in sorted order); read with
  *    dpic_stage_times; other values are EINVAL;
  *  DPIC_OPT_CHUNK = particles per work item of the tiled particle kernel
- *    (a multiple of 64 in 128..8192, default 768);
+ *    (a multiple of 64 in 128..8192, default 1024). With one setting the
+ *    items that start once fewer than chunk x (the kernel's resident
+ *    workgroups) particles remain hold chunk / 2, so that the last items of
+ *    a launch are short; batches use chunk throughout;
  *  DPIC_OPT_PART_BLOCKS = workgroups of the persistent tiled particle kernel
  *    (0 = four times the device's resident capacity for it, the default;
  *    never more than the work list can hold);

@@ -561,7 +561,7 @@ size_t workspace_layout(const dpic_dims& d, char* base, Workspace* ws) {
     const size_t segs = (cap + SEG - 1) / SEG;
     w.hist = (uint32_t*)take((B * nbins + 1) * sizeof(uint32_t));
     w.bins = (uint32_t*)take((2 * B * nbins + 2) * sizeof(uint32_t));
-    const size_t items = std::min(B * nbins, cap) + cap / CHUNK_MIN + 1;
+    const size_t items = GUIDE_LEVELS * std::min(B * nbins, cap) + cap / CHUNK_MIN + 1;
     w.chunks = (int4*)take(items * sizeof(int4));
     w.nchunks = (uint32_t*)take(sizeof(uint32_t));
     w.chunks2 = (int4*)take(items * sizeof(int4));
@@ -650,7 +650,8 @@ int dpic_create(const dpic_dims* dims, void* workspace_dev, size_t workspace_byt
         hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         c->cu_count = 0;
     c->device = dev;
-    (void)particle_resident_blocks(c);  // occupancy queries happen here, never under capture
+    const int slots = particle_resident_blocks(c);  // occupancy queries happen here, never under capture
+    if (slots > 0) c->part_slots = slots;
     *out = c;
     return DPIC_OK;
 }

@@ -79,10 +79,18 @@ constexpr int TILE_EDGE = 4;                             // cells per tile edge
 constexpr int TILE_HALO = 1;                             // drift allowance (cells)
 constexpr int TILE_R = TILE_EDGE + 2 * TILE_HALO + 1;    // deposit tile nodes per dimension
 constexpr int TILE_RZ_E = TILE_EDGE + 1;                 // E tile nodes in z
-constexpr int TILE_CHUNK = 768;                          // default particles per tiled work item
+constexpr int TILE_CHUNK = 1024;                         // default particles per tiled work item
 constexpr int64_t SORT_AUTO_CADENCE = 5;                 // automatic cadence: re-sort every 5 steps
 constexpr int64_t SORT_AUTO_MIN_PARTICLES = 32768;       // ... from this many particles (all settings) up
 constexpr int CHUNK_MIN = 128;                           // smallest work item (sizes the work list)
+// One setting's work list: items of `chunk` particles while at least chunk x
+// (resident workgroups) particles remain after an item's start, then halving
+// sizes over GUIDE_LEVELS zones (never below CHUNK_MIN), so that the items
+// that start last are short.
+#ifndef DPIC_GUIDE_LEVELS
+#define DPIC_GUIDE_LEVELS 2
+#endif
+constexpr int GUIDE_LEVELS = DPIC_GUIDE_LEVELS;
 constexpr int CHUNK_MAX = 8192;
 constexpr int SORT_PB = SEG;                             // particles per sort block
 constexpr int MAX_BATCH = 4096;
@@ -175,6 +183,7 @@ struct dpic_ctx {
     // options
     int64_t sort_every = -1;  // re-sort cadence; -1 automatic (sort_cadence in capi.hip)
     int64_t chunk = dpic::TILE_CHUNK;  // particles per tiled work item
+    int part_slots = 512;              // resident workgroups of the tiled particle kernel
     int64_t part_blocks = 0;           // workgroups of the tiled particle kernel (0: resident capacity)
     bool chunks_valid = false;  // the tiled work list matches the stored order
     bool keys_ready = false;    // ws.key holds every particle's tile key (written by the last particle launch)

@@ -290,10 +290,59 @@ __global__ __launch_bounds__(1024) void k_build_items(const SettingDev* __restri
 
 // One setting: the starts and the work list in one block. Every bin's total
 // (cleared here for the next count) gives its first slot, in tot and cur as
-// k_sort_starts writes them, and its number of items; then all threads
-// write the items, in bin order, each finding its item's bin by bisection
-// over the bins' first item indices.
-__global__ __launch_bounds__(1024) void k_sort_plan(const SettingDev* __restrict__ set, int nbins, int chunk,
+// k_sort_starts writes them. The work list keeps bin order; item sizes follow
+// guide zones over the setting's sorted slots: with n particles and D
+// resident workgroups, zone z (size chunk / 2^z, at least CHUNK_MIN) holds
+// the slots whose remaining count n - P lies in [size_z D, size_(z-1) D),
+// the last zone everything after. Each bin's range is cut at the zone
+// boundaries and each piece into items of its zone's size. All threads then
+// write the items, each finding its item's bin by bisection over the bins'
+// first item indices and its piece by walking the zones.
+struct GuideZones {
+    uint32_t size[GUIDE_LEVELS];
+    uint32_t start[GUIDE_LEVELS + 1];  // first slot of each zone (relative to the setting), then n
+    __device__ GuideZones(uint32_t n, uint32_t chunk, uint32_t slots) {
+        for (int z = 0; z < GUIDE_LEVELS; ++z) {
+            const uint32_t c = chunk >> z;
+            size[z] = c > (uint32_t)CHUNK_MIN ? c : (uint32_t)CHUNK_MIN;
+        }
+        start[0] = 0u;
+        for (int z = 1; z < GUIDE_LEVELS; ++z) {
+            const uint64_t keep = (uint64_t)size[z - 1] * slots;  // remaining count that ends zone z - 1
+            const uint32_t p = keep >= n ? 0u : (uint32_t)(n - keep);
+            start[z] = p > start[z - 1] ? p : start[z - 1];
+        }
+        start[GUIDE_LEVELS] = n;
+    }
+    // items of the slot range [a, e)
+    __device__ uint32_t items(uint32_t a, uint32_t e) const {
+        uint32_t k = 0;
+        for (int z = 0; z < GUIDE_LEVELS; ++z) {
+            const uint32_t lo = a > start[z] ? a : start[z], hi = e < start[z + 1] ? e : start[z + 1];
+            if (hi > lo) k += (hi - lo + size[z] - 1u) / size[z];
+        }
+        return k;
+    }
+    // item j of the range [a, e): first slot and count
+    __device__ void item(uint32_t a, uint32_t e, uint32_t j, uint32_t* q, uint32_t* cnt) const {
+        for (int z = 0; z < GUIDE_LEVELS; ++z) {
+            const uint32_t lo = a > start[z] ? a : start[z], hi = e < start[z + 1] ? e : start[z + 1];
+            if (hi <= lo) continue;
+            const uint32_t nz = (hi - lo + size[z] - 1u) / size[z];
+            if (j < nz) {
+                *q = lo + j * size[z];
+                const uint32_t left = hi - *q;
+                *cnt = left < size[z] ? left : size[z];
+                return;
+            }
+            j -= nz;
+        }
+        *q = e;
+        *cnt = 0u;
+    }
+};
+
+__global__ __launch_bounds__(1024) void k_sort_plan(const SettingDev* __restrict__ set, int nbins, int chunk, int slots,
                                                     uint32_t* __restrict__ hist, uint32_t* __restrict__ tot,
                                                     uint32_t* __restrict__ cur, int4* __restrict__ chunks,
                                                     uint32_t* __restrict__ nchunks) {
@@ -301,43 +350,60 @@ __global__ __launch_bounds__(1024) void k_sort_plan(const SettingDev* __restrict
     __shared__ uint32_t sh[16];
     __shared__ uint32_t s_start[NUM_TILE_BINS_MAX + 2], s_item[NUM_TILE_BINS_MAX + 2];
     const SettingDev sd = set[0];
+    const uint32_t off = (uint32_t)sd.off, n = (uint32_t)sd.n;
+    const GuideZones gz(n, (uint32_t)chunk, (uint32_t)slots);
     const int per = (nbins + 1023) / 1024;
     const int f0 = threadIdx.x * per;
-    const uint32_t ch = (uint32_t)chunk;
     uint32_t c[PP];
-    uint32_t s = 0, si = 0;
+    uint32_t s = 0;
 #pragma unroll
     for (int i = 0; i < PP; ++i) {
         const int f = f0 + i;
         c[i] = (i < per && f < nbins) ? hist[f] : 0u;
         s += c[i];
-        si += (c[i] + ch - 1u) / ch;
     }
 #pragma unroll
     for (int i = 0; i < PP; ++i)
         if (i < per && f0 + i < nbins) hist[f0 + i] = 0u;
+    const uint32_t first = block_excl_scan_1024(s, sh, nullptr);  // relative to the setting
+    uint32_t si = 0, rel = first;
+#pragma unroll
+    for (int i = 0; i < PP; ++i) {
+        si += gz.items(rel, rel + c[i]);
+        rel += c[i];
+    }
     uint32_t items = 0;
-    uint32_t run = (uint32_t)sd.off + block_excl_scan_1024(s, sh, nullptr);
     uint32_t irun = block_excl_scan_1024(si, sh, &items);
+    uint32_t run = first;
 #pragma unroll
     for (int i = 0; i < PP; ++i) {
         const int f = f0 + i;
         if (i < per && f < nbins) {
-            tot[f] = run;
-            cur[f] = run;
+            tot[f] = off + run;
+            cur[f] = off + run;
             s_start[f] = run;
             s_item[f] = irun;
+            irun += gz.items(run, run + c[i]);
             run += c[i];
-            irun += (c[i] + ch - 1u) / ch;
         }
     }
     if (threadIdx.x == 0) {
-        s_start[nbins] = (uint32_t)(sd.off + sd.n);
+        s_start[nbins] = n;
         s_item[nbins] = items;
         *nchunks = items;
     }
     __syncthreads();
-    write_items(s_start, s_item, nbins, ch, 0, 0u, chunks);
+    for (uint32_t k = threadIdx.x; k < items; k += 1024) {
+        int lo = 0, hi = nbins - 1;  // s_item[lo] <= k; the bin is the last such
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_item[mid] <= k) lo = mid;
+            else hi = mid - 1;
+        }
+        uint32_t q, cnt;
+        gz.item(s_start[lo], s_start[lo + 1], k - s_item[lo], &q, &cnt);
+        chunks[k] = make_int4(lo, (int)(off + q), (int)cnt, 0);
+    }
 }
 
 bool sort_geometry(const dpic_ctx* cx, int* tiles, int* nbins) {
@@ -350,14 +416,15 @@ bool sort_geometry(const dpic_ctx* cx, int* tiles, int* nbins) {
     return *nbins <= NUM_TILE_BINS_MAX + 1;
 }
 
-// Upper bound of the work items: every non-empty (setting, bin) range gives
-// at most one item more than its particles / chunk.
+// Upper bound of the work items: a non-empty (setting, bin) range gives at
+// most one short item per guide zone, and every other item holds at least
+// CHUNK_MIN particles.
 size_t max_chunks(const dpic_ctx* cx) {
     int nbins = 0;
     sort_geometry(cx, nullptr, &nbins);
     size_t bins = 0;
     for (int b = 0; b < cx->B; ++b) bins += (size_t)std::min<int64_t>(cx->nb[b], nbins);
-    return bins + (size_t)(cx->n / cx->chunk) + 1;
+    return GUIDE_LEVELS * bins + (size_t)(cx->n / CHUNK_MIN) + 1;
 }
 
 static bool sort_geom(const dpic_ctx* cx, SortGeom* g) {
@@ -410,8 +477,8 @@ hipError_t launch_sort_counts(dpic_ctx* cx) {
         }
     }
     if (cx->B == 1) {
-        hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(1024), 0, s, w.set, g.nbins, (int)cx->chunk, w.hist, tot, cur,
-                           w.chunks2, w.nchunks2);
+        hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(1024), 0, s, w.set, g.nbins, (int)cx->chunk, cx->part_slots,
+                           w.hist, tot, cur, w.chunks2, w.nchunks2);
     } else {
         hipLaunchKernelGGL(k_sort_starts, dim3(cx->B), dim3(1024), 0, s, w.set, g.nbins, (int)cx->chunk, w.hist, tot,
                            cur, w.nitems);
