@@ -449,6 +449,10 @@ constexpr bool use_etile() {
 }
 constexpr int PART_THREADS = 256;
 constexpr int STAGE_BATCH = 8;  // E-tile staging loads in flight per thread
+#ifndef DPIC_FB_CORNERS
+#define DPIC_FB_CORNERS 4
+#endif
+constexpr int FB_CORNERS = DPIC_FB_CORNERS;  // corners per round trip of the global-memory gather
 constexpr double EHALO_MAX_BYTES = 128.0 * (1 << 20);  // fields of all settings, for PF_EHALO
 
 // Wavefront max of the extents (all 64 lanes take part), one atomic per
@@ -624,21 +628,48 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& 
                     }
                 }
             } else {
+                // E from global memory (a wavefront with one particle outside
+                // the E tile takes this path). The 8 corners' values of one
+                // component are loaded together before any is used: one round
+                // trip per component, where loads consumed one by one waited
+                // for each other. Same corner order and weights as above.
                 const int64_t n0 = ((int64_t)g.iz * a.ny + g.iy) * a.nx + g.ix;
 #pragma unroll
-                for (int kz = 0; kz < 2; ++kz) {
+                for (int c = 0; c < 3; ++c) {
 #pragma unroll
-                    for (int ky = 0; ky < 2; ++ky) {
-                        const QD<K> wyz = qd_mul(ky ? fy : qd_one_minus(fy), kz ? fz : qd_one_minus(fz));
+                  for (int h = 0; h < 8; h += FB_CORNERS) {
+                    double raw[8][K];
 #pragma unroll
-                        for (int kx = 0; kx < 2; ++kx) {
-                            const QD<K> w = qd_mul(kx ? fx : qd_one_minus(fx), wyz);
-                            const double* ep = sv.E + (n0 + kx + ky * a.nx + kz * sxy) * 3 * NC;
-                            qd_fmad(w, qd_load<K, G>(ep, q), ex);
-                            qd_fmad(w, qd_load<K, G>(ep + NC, q), ey);
-                            qd_fmad(w, qd_load<K, G>(ep + 2 * NC, q), ez);
+                    for (int k = h; k < h + FB_CORNERS; ++k) {
+                        const double* ep =
+                            sv.E + (n0 + (k & 1) + ((k >> 1) & 1) * a.nx + (k >> 2) * sxy) * 3 * NC + c * NC + q * K;
+                        if constexpr (K == 1) {
+                            raw[k][0] = ep[0];
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < K / 2; ++i) {
+                                const double2 v = reinterpret_cast<const double2*>(ep)[i];
+                                raw[k][2 * i] = v.x;
+                                raw[k][2 * i + 1] = v.y;
+                            }
                         }
                     }
+                    QD<K>& acc = c == 0 ? ex : (c == 1 ? ey : ez);
+#pragma unroll
+                    for (int k = h; k < h + FB_CORNERS; ++k) {
+                        QD<K> e;
+#pragma unroll
+                        for (int i = 0; i < K; ++i) e.t[i] = raw[k][i];
+                        if constexpr (G == 1)
+                            e.v = e.t[0];
+                        else
+                            e.v = group_bcast<G>(e.t[0]);
+                        if (q == 0) e.t[0] = 0.0;
+                        const QD<K> wyz = qd_mul(((k >> 1) & 1) ? fy : qd_one_minus(fy), (k >> 2) ? fz : qd_one_minus(fz));
+                        const QD<K> w = qd_mul((k & 1) ? fx : qd_one_minus(fx), wyz);
+                        qd_fmad(w, e, acc);
+                    }
+                  }
                 }
             }
             const QD<K> tau = qd_load_split<NC>(stau, q);
