@@ -627,7 +627,7 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& 
                         }
                     }
                 }
-            } else {
+            } else if constexpr ((F & PF_EHALO) != 0) {
                 // E from global memory (a wavefront with one particle outside
                 // the E tile takes this path). The 8 corners' values of one
                 // component are loaded together before any is used: one round
@@ -670,6 +670,27 @@ __device__ __forceinline__ void particle_body(const PartArgs& a, const SetView& 
                         qd_fmad(w, e, acc);
                     }
                   }
+                }
+            } else {
+                // the same sum with each load consumed as it arrives: the
+                // variants without the drift allowance keep this form, since
+                // the batched loads above raise their register allocation and
+                // slow their particle loop
+                const int64_t n0 = ((int64_t)g.iz * a.ny + g.iy) * a.nx + g.ix;
+#pragma unroll
+                for (int kz = 0; kz < 2; ++kz) {
+#pragma unroll
+                    for (int ky = 0; ky < 2; ++ky) {
+                        const QD<K> wyz = qd_mul(ky ? fy : qd_one_minus(fy), kz ? fz : qd_one_minus(fz));
+#pragma unroll
+                        for (int kx = 0; kx < 2; ++kx) {
+                            const QD<K> w = qd_mul(kx ? fx : qd_one_minus(fx), wyz);
+                            const double* ep = sv.E + (n0 + kx + ky * a.nx + kz * sxy) * 3 * NC;
+                            qd_fmad(w, qd_load<K, G>(ep, q), ex);
+                            qd_fmad(w, qd_load<K, G>(ep + NC, q), ey);
+                            qd_fmad(w, qd_load<K, G>(ep + 2 * NC, q), ez);
+                        }
+                    }
                 }
             }
             const QD<K> tau = qd_load_split<NC>(stau, q);
