@@ -304,9 +304,11 @@ int dpic_get_option(const dpic_ctx* ctx, int option, int64_t* value);
 
 /*
  * Autotuner: times trial_steps steps from the current state for candidate
- * work-item sizes, persistent grid sizes and sort cadences (0, 5, 10, 12,
- * 20, 40 steps; coordinate search), restores the state and the counters after every trial, and keeps
- * the fastest setting. scratch_dev: caller device memory of at least
+ * sort cadences (0, 5, 10, 12, 20, 40 steps), then work-item sizes, then
+ * persistent grid sizes (coordinate search in that order), restores the
+ * state and the counters after every trial, and keeps the fastest setting;
+ * a candidate replaces the current one only when its trial is at least 2%
+ * faster. scratch_dev: caller device memory of at least
  * dpic_state_bytes(). best[3] (host, may be NULL) receives
  * {sort_every, chunk, part_blocks}; ms_best the time of the winning trial.
  * Needs space charge on and no adjoint bound; synchronises.

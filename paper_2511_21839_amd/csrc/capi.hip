@@ -1109,6 +1109,8 @@ int dpic_stage_times(dpic_ctx* c, double* ms, int64_t* launches) {
     return DPIC_OK;
 }
 
+constexpr double TUNE_MARGIN = 0.02;  // a tuning candidate must be this much faster to be kept
+
 int dpic_autotune(dpic_ctx* c, void* scratch, size_t scratch_bytes, int trial_steps, int64_t* best, double* ms_best) {
     if (!c || !scratch) return DPIC_EINVAL;
     size_t need = 0;
@@ -1152,9 +1154,20 @@ int dpic_autotune(dpic_ctx* c, void* scratch, size_t scratch_bytes, int trial_st
     const int64_t resident = particle_resident_blocks(c);
     r = trial(se, ch, pb, &t);  // warm-up, then the incumbent
     if (r == DPIC_OK) r = trial(se, ch, pb, &bms);
+    // a candidate replaces the incumbent only when it is TUNE_MARGIN faster:
+    // trial-to-trial spread must not decide the pick. The sort cadence, which
+    // matters most, is searched first.
+    auto better = [&](double cand) { return cand < bms * (1.0 - TUNE_MARGIN); };
+    for (int64_t v : {0, 5, 10, 12, 20, 40}) {  // 0: storage order, no sort
+        if (r != DPIC_OK || v == se) continue;
+        if ((r = trial(v, ch, pb, &t)) == DPIC_OK && better(t)) {
+            bms = t;
+            se = v;
+        }
+    }
     for (int64_t v : {256, 512, 768, 1024, 2048}) {
         if (r != DPIC_OK || v == ch) continue;
-        if ((r = trial(se, v, pb, &t)) == DPIC_OK && t < bms) {
+        if ((r = trial(se, v, pb, &t)) == DPIC_OK && better(t)) {
             bms = t;
             ch = v;
         }
@@ -1162,16 +1175,9 @@ int dpic_autotune(dpic_ctx* c, void* scratch, size_t scratch_bytes, int trial_st
     for (int64_t v : {resident / 2, resident, 2 * resident, 4 * resident}) {
         const int64_t cur = pb == 0 ? resident : pb;
         if (r != DPIC_OK || v < 1 || v == cur) continue;
-        if ((r = trial(se, ch, v, &t)) == DPIC_OK && t < bms) {
+        if ((r = trial(se, ch, v, &t)) == DPIC_OK && better(t)) {
             bms = t;
             pb = v;
-        }
-    }
-    for (int64_t v : {0, 5, 10, 12, 20, 40}) {  // 0: storage order, no sort
-        if (r != DPIC_OK || v == se) continue;
-        if ((r = trial(v, ch, pb, &t)) == DPIC_OK && t < bms) {
-            bms = t;
-            se = v;
         }
     }
     (void)hipEventDestroy(e0);
