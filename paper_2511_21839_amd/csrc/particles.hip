@@ -1194,10 +1194,11 @@ hipError_t launch_particles(dpic_ctx* cx, int flags, int e_tau, int map_off, boo
         t.cur = cx->ws.bins + (size_t)cx->B * t.nbins;
         flags |= PF_SCATTER;
     }
-    // the E tile with the drift allowance while the fields of all settings
-    // fit in the caches
+    // the tiles with the drift allowance wherever an E tile is staged (up
+    // to 8 channels), and otherwise while the fields of all settings fit in
+    // the caches (at 16 channels the flag only shapes the deposit tile)
     const double ebytes = (double)cx->B * cx->dims.nx * cx->dims.ny * cx->dims.nz * 3.0 * cx->NC * sizeof(double);
-    if (tiled && (flags & PF_KICK) && ebytes <= EHALO_MAX_BYTES) flags |= PF_EHALO;
+    if (tiled && (flags & PF_KICK) && (cx->NC <= 8 || ebytes <= EHALO_MAX_BYTES)) flags |= PF_EHALO;
     switch (cx->NC) {
         case 1: return tiled ? launch_particles_nc<1, true>(cx, flags, a, t, items) : launch_particles_nc<1, false>(cx, flags, a, t, items);
         case 8: return tiled ? launch_particles_nc<8, true>(cx, flags, a, t, items) : launch_particles_nc<8, false>(cx, flags, a, t, items);
