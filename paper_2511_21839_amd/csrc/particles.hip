@@ -928,6 +928,42 @@ __device__ __forceinline__ void tiled_body(const PartArgs& a, const TiledArgs& t
             // along x in global memory) into the split layout, SB loads in
             // flight per thread before their LDS writes
             constexpr int ER = etile_r<F>(), EN = etile_nodes<F>();
+            if constexpr (NC >= 2 && NC % 2 == 0 && (F & PF_EHALO) != 0) {
+                // (the variants with the drift allowance, which every kick at
+                // up to 8 channels takes) straight from global memory into
+                // LDS, 16 bytes per lane,
+                // every load of the tile in flight at once and none through
+                // registers. A wavefront's load fills 64 consecutive 16-byte
+                // chunks of the tile; a dual's chunks are its channel pairs
+                // (0, 1), (2, 3), .. and (value, pad), each one aligned chunk
+                // of the node's E, so the first holds the value where the
+                // split layout wants a zero, written after the loads land
+                // (by every thread over the duals after a barrier: measured
+                // faster than each lane zeroing the chunks it loaded). Nodes
+                // outside the grid get zeros by plain LDS stores.
+                constexpr int CD = lds_dual<NC>() / 2, CN = 3 * CD, SC = EN * CN;
+                const int c0w = (int)(threadIdx.x & ~63u), lane = (int)(threadIdx.x & 63u);
+#pragma unroll 1
+                for (int c0 = c0w; c0 < SC; c0 += PART_THREADS) {
+                    const int c = c0 + lane;
+                    const int node = c / CN, rc = c - node * CN, comp = rc / CD, k = rc - comp * CD;
+                    const int lx = node % ER, ly = (node / ER) % ER, lz = node / (ER * ER);
+                    const int gx = ox + etile_off<F>() + lx, gy = oy + etile_off<F>() + ly, gz = oze + lz;
+                    if (c < SC) {
+                        if (gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz) {
+                            const double* src = Eb + (((int64_t)gz * a.ny + gy) * a.nx + gx) * 3 * NC + comp * NC +
+                                                2 * (k == CD - 1 ? 0 : k);
+                            __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(le + 2 * c0),
+                                                             16, 0, 0);
+                        } else {
+                            reinterpret_cast<double2*>(le)[c] = make_double2(0.0, 0.0);
+                        }
+                    }
+                }
+                __builtin_amdgcn_s_waitcnt(0);  // the direct loads have written LDS
+                __syncthreads();
+                for (int j = threadIdx.x; j < EN * 3; j += PART_THREADS) le[j * lds_dual<NC>()] = 0.0;
+            } else {
             constexpr int SN = EN * 3 * NC, SB = STAGE_BATCH;
 #pragma unroll 1
             for (int j0 = 0; j0 < SN; j0 += SB * PART_THREADS) {
@@ -948,6 +984,7 @@ __device__ __forceinline__ void tiled_body(const PartArgs& a, const TiledArgs& t
                     const int node = j / (3 * NC), r = j - node * (3 * NC);
                     if (j < SN) put_split<NC>(le + (node * 3 + r / NC) * lds_dual<NC>(), r % NC, v[k]);
                 }
+            }
             }
         }
         __syncthreads();
