@@ -67,30 +67,48 @@ __device__ __forceinline__ SegInfo seg_info(const SettingDev* set, const int32_t
 
 // Count: the block's histogram over the bins, added into the setting's
 // totals tot[b][bin] (non-empty bins only). FROM_KEYS: the keys were
-// written by the particle launch that produced these positions.
-template <int NC, bool FROM_KEYS>
+// written by the particle launch that produced these positions. A block
+// counts SPB consecutive segments (one particle of each per thread, loaded
+// together), which must belong to one setting: SPB > 1 only with one
+// setting. Clearing and flushing the histogram's bins costs more than
+// counting one segment, so one setting takes 4 segments per block.
+template <int NC, bool FROM_KEYS, int SPB>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_count(const double* __restrict__ st, int64_t cap,
                                                              const SettingDev* __restrict__ set,
                                                              const int32_t* __restrict__ owner, SortGeom g,
-                                                             uint32_t* __restrict__ key, uint32_t* __restrict__ tot) {
+                                                             int nsegs, uint32_t* __restrict__ key,
+                                                             uint32_t* __restrict__ tot) {
+    static_assert(SORT_PB == SORT_THREADS, "one particle of a segment per thread");
     __shared__ uint32_t h[NUM_TILE_BINS_MAX + 1];
     for (int b = threadIdx.x; b < g.nbins; b += SORT_THREADS) h[b] = 0u;
     __syncthreads();
-    const SegInfo si = seg_info(set, owner, blockIdx.x);
+    const int64_t k0 = (int64_t)blockIdx.x * SPB;
+    const SegInfo si = seg_info(set, owner, k0);
+    const SettingDev sd = set[si.b];
+    const int64_t end = sd.off + sd.n;  // the setting's last slot + 1
     const int64_t cs = cap * NC;
-    for (int i = threadIdx.x; i < SORT_PB; i += SORT_THREADS) {
-        const int64_t p = si.lo + i;
-        if (p < si.hi) {
-            uint32_t k;
-            if (FROM_KEYS) {
-                k = key[p];
-            } else {
-                k = tile_key(st[p * NC], st[2 * cs + p * NC], st[4 * cs + p * NC], g);
-                key[p] = k;
+    uint32_t kv[SPB];
+    bool in[SPB];
+#pragma unroll
+    for (int j = 0; j < SPB; ++j) {
+        in[j] = false;
+        kv[j] = 0u;
+        if (k0 + j < nsegs) {
+            const int64_t p = (k0 + j) * SEG + threadIdx.x;
+            if (p < end) {
+                in[j] = true;
+                if (FROM_KEYS) {
+                    kv[j] = key[p];
+                } else {
+                    kv[j] = tile_key(st[p * NC], st[2 * cs + p * NC], st[4 * cs + p * NC], g);
+                    key[p] = kv[j];
+                }
             }
-            atomicAdd(&h[k], 1u);
         }
     }
+#pragma unroll
+    for (int j = 0; j < SPB; ++j)
+        if (in[j]) atomicAdd(&h[kv[j]], 1u);
     __syncthreads();
     uint32_t* tb = tot + (int64_t)si.b * g.nbins;
     for (int b = threadIdx.x; b < g.nbins; b += SORT_THREADS)
@@ -466,13 +484,17 @@ hipError_t launch_sort_counts(dpic_ctx* cx) {
     cx->hist_clean = false;
     if (nsegs > 0) {
         if (cx->keys_ready) {
-            hipLaunchKernelGGL((k_sort_count<1, true>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g,
-                               w.key, w.hist);
+            if (cx->B == 1)
+                hipLaunchKernelGGL((k_sort_count<1, true, 4>), dim3((nsegs + 3) / 4), dim3(SORT_THREADS), 0, s, w.st, cap,
+                                   w.set, w.owner, g, nsegs, w.key, w.hist);
+            else
+                hipLaunchKernelGGL((k_sort_count<1, true, 1>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set,
+                                   w.owner, g, nsegs, w.key, w.hist);
         } else {
             switch (cx->NC) {
-                case 1: hipLaunchKernelGGL((k_sort_count<1, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, w.hist); break;
-                case 8: hipLaunchKernelGGL((k_sort_count<8, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, w.hist); break;
-                default: hipLaunchKernelGGL((k_sort_count<16, false>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, w.key, w.hist); break;
+                case 1: hipLaunchKernelGGL((k_sort_count<1, false, 1>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, nsegs, w.key, w.hist); break;
+                case 8: hipLaunchKernelGGL((k_sort_count<8, false, 1>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, nsegs, w.key, w.hist); break;
+                default: hipLaunchKernelGGL((k_sort_count<16, false, 1>), dim3(nsegs), dim3(SORT_THREADS), 0, s, w.st, cap, w.set, w.owner, g, nsegs, w.key, w.hist); break;
             }
         }
     }
