@@ -515,7 +515,7 @@ __device__ __forceinline__ void nonfinite_flush_wave(unsigned long long* cnt, bo
 }
 
 template <int K>
-__device__ __forceinline__ bool qd_nonfinite(const QD<K>& x) {
+__device__ __forceinline__ int qd_nonfinite(const QD<K>& x) {  // 0 or 1, so that checks combine without branches
     bool bad = !__builtin_isfinite(x.v);
 #pragma unroll
     for (int k = 0; k < K; ++k) bad |= !__builtin_isfinite(x.t[k]);
@@ -925,15 +925,13 @@ __device__ __forceinline__ void tiled_body(const PartArgs& a, const TiledArgs& t
             // for the setting record
             const double* __restrict__ Eb = t.E0 + (int64_t)ck.w * t.estride;
             // E of the tile's nodes (runs of TILE_R nodes x 3 x NC doubles
-            // along x in global memory) into the split layout, SB loads in
-            // flight per thread before their LDS writes
+            // along x in global memory) into the split layout
             constexpr int ER = etile_r<F>(), EN = etile_nodes<F>();
             if constexpr (NC >= 2 && NC % 2 == 0 && (F & PF_EHALO) != 0) {
-                // (the variants with the drift allowance, which every kick at
-                // up to 8 channels takes) straight from global memory into
-                // LDS, 16 bytes per lane,
-                // every load of the tile in flight at once and none through
-                // registers. A wavefront's load fills 64 consecutive 16-byte
+                // In the variants with the drift allowance (which every kick
+                // at up to 8 channels takes): straight from global memory into
+                // LDS, 16 bytes per lane, every load of the tile in flight at
+                // once and none through registers. A wavefront's load fills 64 consecutive 16-byte
                 // chunks of the tile; a dual's chunks are its channel pairs
                 // (0, 1), (2, 3), .. and (value, pad), each one aligned chunk
                 // of the node's E, so the first holds the value where the
@@ -964,6 +962,7 @@ __device__ __forceinline__ void tiled_body(const PartArgs& a, const TiledArgs& t
                 __syncthreads();
                 for (int j = threadIdx.x; j < EN * 3; j += PART_THREADS) le[j * lds_dual<NC>()] = 0.0;
             } else {
+            // SB loads in flight per thread before their LDS writes
             constexpr int SN = EN * 3 * NC, SB = STAGE_BATCH;
 #pragma unroll 1
             for (int j0 = 0; j0 < SN; j0 += SB * PART_THREADS) {
